@@ -1,0 +1,45 @@
+"""Seeded input generators: determinism and the structure the recipe promises."""
+
+import numpy as np
+
+from paper_2512_11606_amd import synth
+
+
+def test_tiny_is_deterministic_and_well_formed():
+    a = synth.make_graph("tiny")
+    b = synth.make_graph("tiny")
+    for f in ("edge_u", "edge_v", "edge_w", "assoc_u", "assoc_a", "assoc_w"):
+        assert np.array_equal(getattr(a, f), getattr(b, f))
+    keys = a.edge_u.astype(np.int64) * a.n_v + a.edge_v
+    assert np.unique(keys).size == keys.size                     # distinct pairs
+    assert a.m_e >= 20_000
+    assert np.bincount(a.edge_u, minlength=a.n_u).min() >= 1     # no edgeless U node
+    cnt = np.bincount(a.assoc_u, minlength=a.n_u)
+    assert (cnt == 5).all()                                      # c distinct attributes each
+    ak = a.assoc_u.astype(np.int64) * a.n_attr + a.assoc_a
+    assert np.unique(ak).size == ak.size
+    assert (a.edge_w == 1).all() and (a.assoc_w == 1).all()
+
+
+def test_weighted_ranges_and_power_law():
+    g = synth.make_custom(3000, 1500, 30000, 200, 6, seed=77)
+    assert g.edge_w.min() >= 0.5 and g.edge_w.max() <= 1.0
+    assert g.assoc_w.min() > 0 and g.assoc_w.max() <= 1.0
+    deg = np.bincount(g.edge_u, minlength=g.n_u)
+    # heavy tail: the largest degree is far above the mean
+    assert deg.max() > 10 * deg.mean()
+    pop = np.bincount(g.assoc_a, minlength=g.n_attr)
+    assert pop.max() > 0.5 * g.n_u                               # Zipf(1.5) head attribute
+
+
+def test_query_sets():
+    g = synth.make_graph("tiny")
+    q = synth.mixed_batch_queries(g, 64, 2002)
+    assert np.unique(q).size == 64 and q.min() >= 0 and q.max() < g.n_u
+    deg = g.u_degree_counts()
+    top = set(np.argsort(-deg, kind="stable")[: g.n_u // 100].tolist())
+    assert sum(int(x) in top for x in q[:20]) == 20
+    d = synth.degree_queries(g, 1000, 5)
+    assert deg[d].mean() > deg.mean()                            # degree-biased
+    u = synth.uniform_queries(g, 10, 1)
+    assert np.array_equal(u, synth.uniform_queries(g, 10, 1))
