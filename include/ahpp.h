@@ -1,0 +1,170 @@
+/*
+ * ahpp.h -- C ABI of the MI355X (gfx950) AHPP library.
+ *
+ * AHPP is the Attribute-augmented Hidden Personalized PageRank of
+ * arXiv 2512.11606 (Def. 2, Eq. 3): for a source u in U,
+ *     pi(u, .) = sum_{l>=0} alpha (1-alpha)^l e_u P^l,
+ *     P = (1-beta) P_S + beta P_A,
+ * with P_S the structure transition matrix of Eq. 1 (two hops U->V->U) and
+ * P_A the attribute transition matrix of Eq. 2 (two hops U->attribute->U).
+ *
+ * The library answers the eps-approximate single-source AHPP query of
+ * Section 2.3 (Eq. 4): it returns pi_hat(u, .) over U with
+ * 0 <= pi(u,i) - pi_hat(u,i) <= eps (Theorem 2), computed by the residue
+ * push of Algorithm 4 (ASRP) with lambda from Theorem 3 (Eq. 6), and the
+ * k most similar nodes of u (the top-k use of the scores in Section 5).
+ *
+ * Conventions shared by every call
+ *   - ids are 0-based int32; node sets U = [0, n_u), V = [0, n_v),
+ *     attributes = [0, n_attr).
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory of the graph's device (e.g. torch tensors on cuda:N).
+ *   - The caller owns every buffer it passes.  The library copies what it
+ *     needs and never keeps a caller pointer after a call returns.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  Device
+ *     outputs are written in stream order; a call returns once its results
+ *     are complete on that stream unless stated otherwise.
+ *   - No C++ exception crosses this boundary.  Every call returns a status;
+ *     on failure ahpp_last_error() describes it (per calling thread).
+ *   - A graph handle may be used by one thread at a time.
+ */
+#ifndef AHPP_H
+#define AHPP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ahpp_graph ahpp_graph_t;
+
+typedef enum {
+    AHPP_OK = 0,
+    AHPP_ERR_INVALID_ARG = -1,   /* bad id, weight, parameter or size          */
+    AHPP_ERR_OUT_OF_MEMORY = -2, /* device allocation failed                    */
+    AHPP_ERR_DEVICE = -3,        /* a HIP runtime call failed                   */
+    AHPP_ERR_NOT_CONVERGED = -4  /* max_iters rounds ran before the stop rule   */
+} ahpp_status_t;
+
+/* Graph description for ahpp_graph_load (all pointers host memory).
+ *   Edges E (Section 2.1): n_edges triples (edge_u[e], edge_v[e], edge_w[e])
+ *     with edge_u in U, edge_v in V, weight > 0 and finite; edge_w == NULL
+ *     means every weight is 1.  Edges are undirected (w(v,u) = w(u,v)).
+ *   Node-attribute associations E_A (Section 2.1): n_assoc triples
+ *     (assoc_u[e], assoc_a[e], assoc_w[e]), weight > 0 and finite;
+ *     assoc_w == NULL means every value is 1.
+ *   Repeated pairs are allowed and behave as one pair with the summed weight
+ *   (Eq. 1 and Eq. 2 are linear in each weight).
+ *   alpha in (0,1): restart probability; beta in [0,1]: attribute-jumping
+ *   probability (Def. 2).
+ *   lambda > 0 overrides the Theorem 3 estimate; lambda <= 0 asks the library
+ *   to compute Eq. 6 with lambda_iters rounds (<= 0: the smallest T with
+ *   n_u (1-alpha)^T <= 0.01) and round it up by a factor 1 + 1e-4.
+ *   device: HIP device ordinal that will hold the graph. */
+typedef struct {
+    int64_t n_u, n_v, n_attr;
+    int64_t n_edges;
+    const int32_t *edge_u, *edge_v;
+    const float *edge_w;
+    int64_t n_assoc;
+    const int32_t *assoc_u, *assoc_a;
+    const float *assoc_w;
+    double alpha, beta;
+    double lambda;
+    int32_t lambda_iters;
+    int32_t device;
+} ahpp_graph_desc_t;
+
+typedef struct {
+    int64_t n_u, n_v, n_attr, n_edges, n_assoc;
+    double alpha, beta;
+    double lambda;              /* the value eps is divided by (Algorithm 4)   */
+    int32_t lambda_iters;       /* rounds used by Theorem 3 (0 if overridden)  */
+    int32_t device;
+    int64_t dangling_u;         /* U nodes with no edge or no attribute        */
+    int64_t device_bytes;       /* device memory held by the graph            */
+    double load_ms, lambda_ms;  /* wall time of the CSR build and of Eq. 6     */
+} ahpp_graph_info_t;
+
+/* Per-query statistics.  n_push counts edge visits as Algorithm 4 counts n_p
+ * (every phase); sync_switch_iter is the round after which the synchronous
+ * phase (threshold 0) began, or -1. */
+typedef struct {
+    int32_t iters;
+    int32_t sync_switch_iter;
+    int32_t converged;
+    int32_t reserved;
+    int64_t n_push;
+    double max_residual;        /* max_i r(u, u_i) at return                   */
+    double sum_residual;        /* sum_i r(u, u_i) at return                   */
+    float ms;                   /* device time of the query (or of its batch)  */
+    float pad;
+} ahpp_stats_t;
+
+/* Builds the graph on the device: the CSR of U -> (V and attributes) and of
+ * (V and attributes) -> U, the normalisers d(u), d(v), s(u), t(a) of Eq. 1 and
+ * Eq. 2, the push schedules, and lambda (Theorem 3, Eq. 6).
+ * Synchronous.  On success *out owns all device memory of the graph.
+ * Errors: INVALID_ARG (sizes < 0, ids out of range, weights <= 0 or not
+ * finite, alpha or beta out of range, out == NULL), OUT_OF_MEMORY, DEVICE. */
+ahpp_status_t ahpp_graph_load(const ahpp_graph_desc_t *desc, ahpp_graph_t **out);
+
+/* Fills *info (host). */
+ahpp_status_t ahpp_graph_info(const ahpp_graph_t *g, ahpp_graph_info_t *info);
+
+/* Releases the graph and every device buffer it owns.  NULL is ignored. */
+void ahpp_graph_free(ahpp_graph_t *g);
+
+/* eps-approximate single-source query (Eq. 4) by Algorithm 4 (ASRP):
+ *   eps_f = eps / lambda; rounds with push threshold eps_f until the budget
+ *   n_p >= 2(|E| + |E_A|) log_{1/(1-alpha)}(max_i r(u,u_i) / eps_f) is spent,
+ *   then rounds with threshold 0, until max_i r(u,u_i) <= eps_f.
+ *   source:    node of U.
+ *   eps:       > 0.
+ *   max_iters: cap on rounds (<= 0: 100000); reaching it returns
+ *              AHPP_ERR_NOT_CONVERGED with the outputs of the last round.
+ *   pi_out:    device float[n_u] or NULL: pi_hat(source, .).
+ *   resid_out: device float[n_u] or NULL: final residues r(source, .).
+ *   k:         0 = no top-k, else k >= 1.
+ *   topk_idx / topk_val / topk_n: device int32[k] / float[k] / int32[1]:
+ *              the k nodes with the largest pi_hat > 0, source excluded,
+ *              sorted by score descending then id ascending; *topk_n <= k is
+ *              how many were written.  Required when k > 0.
+ *   stats:     host or NULL.
+ * Blocks the calling thread until the query has finished on hip_stream. */
+ahpp_status_t ahpp_query(ahpp_graph_t *g, int32_t source, double eps, int32_t max_iters,
+                         float *pi_out, float *resid_out,
+                         int32_t k, int32_t *topk_idx, float *topk_val, int32_t *topk_n,
+                         ahpp_stats_t *stats, void *hip_stream);
+
+/* n_q independent queries answered together (Section 5.1 runs queries
+ * independently): the rounds of Algorithm 4 for all of them share each pass
+ * over the edge lists.  Each query keeps its own eps_f, threshold, phase and
+ * stop rule, so every result satisfies the same guarantee as ahpp_query.
+ *   sources: host int32[n_q]; eps: host double[n_q] (each > 0).
+ *   pi_out:  device float[n_q * n_u] (row q = query q) or NULL.
+ *   k, topk_idx (device int32[n_q*k]), topk_val (device float[n_q*k]),
+ *   topk_n (device int32[n_q]): as in ahpp_query, row q for query q.
+ *   stats: host ahpp_stats_t[n_q] or NULL.
+ * Returns NOT_CONVERGED if any query hit max_iters. Blocks until done. */
+ahpp_status_t ahpp_query_batch(ahpp_graph_t *g, int32_t n_q, const int32_t *sources, const double *eps,
+                               int32_t max_iters, float *pi_out,
+                               int32_t k, int32_t *topk_idx, float *topk_val, int32_t *topk_n,
+                               ahpp_stats_t *stats, void *hip_stream);
+
+/* Top-k of a device score vector pi (float[n_u]): the k largest entries
+ * with pi > 0, `exclude` left out (-1: none), sorted by score descending then
+ * id ascending.  Outputs are device pointers as in ahpp_query.
+ * Enqueued on hip_stream; returns after enqueueing. */
+ahpp_status_t ahpp_topk(const ahpp_graph_t *g, const float *pi, int32_t k, int32_t exclude,
+                        int32_t *idx_out, float *val_out, int32_t *n_out, void *hip_stream);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *ahpp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AHPP_H */

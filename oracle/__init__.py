@@ -113,7 +113,8 @@ class OracleGraph:
     def __init__(self, n_u, n_v, n_attr, edge_u, edge_v, edge_w, assoc_u, assoc_a, assoc_w):
         lib = _load()
         self.n_u, self.n_v, self.n_attr = int(n_u), int(n_v), int(n_attr)
-        self._keep = [np.ascontiguousarray(x, dtype=t) for x, t in
+        # A missing weight array means every weight is 1 (passed to C as NULL).
+        self._keep = [None if x is None else np.ascontiguousarray(x, dtype=t) for x, t in
                       ((edge_u, np.int32), (edge_v, np.int32), (edge_w, np.float32),
                        (assoc_u, np.int32), (assoc_a, np.int32), (assoc_w, np.float32))]
         eu, ev, ew, au, aa, aw = self._keep
@@ -219,7 +220,9 @@ def max_threads() -> int:
 
 def _dense_w(n_rows, n_cols, rows, cols, w):
     M = np.zeros((n_rows, n_cols))
-    np.add.at(M, (np.asarray(rows), np.asarray(cols)), np.asarray(w, dtype=np.float64))
+    rows = np.asarray(rows)
+    vals = np.ones(rows.shape) if w is None else np.asarray(w, dtype=np.float64)
+    np.add.at(M, (rows, np.asarray(cols)), vals)
     return M
 
 
@@ -246,7 +249,8 @@ def dense_PA(g) -> np.ndarray:
 def dense_PS_literal(g) -> np.ndarray:
     """Eq. 1 as written: a sum over common neighbours v, one pair at a time (small graphs only)."""
     nbr = [dict() for _ in range(g.n_u)]
-    for u, v, w in zip(g.edge_u.tolist(), g.edge_v.tolist(), g.edge_w.tolist()):
+    ew = np.ones(len(g.edge_u)) if g.edge_w is None else g.edge_w
+    for u, v, w in zip(g.edge_u.tolist(), g.edge_v.tolist(), ew.tolist()):
         nbr[u][v] = nbr[u].get(v, 0.0) + float(w)
     d_u = [sum(x.values()) for x in nbr]
     d_v = [0.0] * g.n_v
@@ -264,7 +268,8 @@ def dense_PS_literal(g) -> np.ndarray:
 def dense_PA_literal(g) -> np.ndarray:
     """Eq. 2 as written: a sum over common attributes a (small graphs only)."""
     att = [dict() for _ in range(g.n_u)]
-    for u, a, w in zip(g.assoc_u.tolist(), g.assoc_a.tolist(), g.assoc_w.tolist()):
+    aw = np.ones(len(g.assoc_u)) if g.assoc_w is None else g.assoc_w
+    for u, a, w in zip(g.assoc_u.tolist(), g.assoc_a.tolist(), aw.tolist()):
         att[u][a] = att[u].get(a, 0.0) + float(w)
     s_u = [sum(x.values()) for x in att]
     t_a = [0.0] * g.n_attr

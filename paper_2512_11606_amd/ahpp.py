@@ -1,0 +1,234 @@
+"""Python binding of the gfx950 AHPP library (include/ahpp.h).
+
+Argument marshalling only: every step of a query runs in the HIP library
+``libahpp.so``.  Torch is used for device buffers and streams.  If the
+library has not been built this module raises at import of the library; there
+is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libahpp.so")
+
+OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CONVERGED = 0, -1, -2, -3, -4
+
+EXPORTED = ("ahpp_graph_load", "ahpp_graph_info", "ahpp_graph_free", "ahpp_query", "ahpp_query_batch", "ahpp_topk",
+            "ahpp_last_error")
+
+
+class AhppError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+class GraphDesc(ctypes.Structure):
+    _fields_ = [("n_u", ctypes.c_int64), ("n_v", ctypes.c_int64), ("n_attr", ctypes.c_int64),
+                ("n_edges", ctypes.c_int64), ("edge_u", ctypes.c_void_p), ("edge_v", ctypes.c_void_p),
+                ("edge_w", ctypes.c_void_p), ("n_assoc", ctypes.c_int64), ("assoc_u", ctypes.c_void_p),
+                ("assoc_a", ctypes.c_void_p), ("assoc_w", ctypes.c_void_p), ("alpha", ctypes.c_double),
+                ("beta", ctypes.c_double), ("lam", ctypes.c_double), ("lambda_iters", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n_u", ctypes.c_int64), ("n_v", ctypes.c_int64), ("n_attr", ctypes.c_int64),
+                ("n_edges", ctypes.c_int64), ("n_assoc", ctypes.c_int64), ("alpha", ctypes.c_double),
+                ("beta", ctypes.c_double), ("lam", ctypes.c_double), ("lambda_iters", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("dangling_u", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("load_ms", ctypes.c_double), ("lambda_ms", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("sync_switch_iter", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("n_push", ctypes.c_int64), ("max_residual", ctypes.c_double),
+                ("sum_residual", ctypes.c_double), ("ms", ctypes.c_float), ("pad", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f not in ("reserved", "pad")}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libahpp.so; raises if it is missing (build it first)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() or "
+                          "python paper_2512_11606_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.ahpp_graph_load.restype = ctypes.c_int
+    lib.ahpp_graph_load.argtypes = [ctypes.POINTER(GraphDesc), ctypes.POINTER(ctypes.c_void_p)]
+    lib.ahpp_graph_info.restype = ctypes.c_int
+    lib.ahpp_graph_info.argtypes = [P, ctypes.POINTER(GraphInfo)]
+    lib.ahpp_graph_free.restype = None
+    lib.ahpp_graph_free.argtypes = [P]
+    lib.ahpp_query.restype = ctypes.c_int
+    lib.ahpp_query.argtypes = [P, i32, dbl, i32, P, P, i32, P, P, P, P, P]
+    lib.ahpp_query_batch.restype = ctypes.c_int
+    lib.ahpp_query_batch.argtypes = [P, i32, P, P, i32, P, i32, P, P, P, P, P]
+    lib.ahpp_topk.restype = ctypes.c_int
+    lib.ahpp_topk.argtypes = [P, P, i32, i32, P, P, P, P]
+    lib.ahpp_last_error.restype = ctypes.c_char_p
+    lib.ahpp_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(status: int, allow_not_converged: bool = False) -> int:
+    if status == OK or (allow_not_converged and status == ERR_NOT_CONVERGED):
+        return status
+    raise AhppError(status, load_library().ahpp_last_error().decode())
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev_ptr(t) -> Optional[int]:
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device: int, stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class QueryResult:
+    pi: object                # torch float32 [n_u] (or [n_q, n_u]) on the device, or None
+    resid: object             # torch float32 [n_u] or None
+    topk_idx: object          # torch int32 [k] (or [n_q, k]) or None
+    topk_val: object
+    topk_n: object
+    stats: list               # list of dicts (one per query)
+    status: int
+
+
+class Graph:
+    """Handle of a graph loaded on one device (owns its device memory)."""
+
+    def __init__(self, handle: ctypes.c_void_p, device: int):
+        self._h = handle
+        self.device = device
+        self.info = ahpp_graph_info(self)
+
+    @property
+    def n_u(self) -> int:
+        return int(self.info["n_u"])
+
+    @property
+    def lam(self) -> float:
+        return float(self.info["lam"])
+
+    def free(self):
+        if self._h:
+            load_library().ahpp_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def ahpp_graph_load(n_u: int, n_v: int, n_attr: int, edge_u, edge_v, edge_w, assoc_u, assoc_a, assoc_w,
+                    alpha: float = 0.15, beta: float = 0.35, lam: float = 0.0, lambda_iters: int = 0,
+                    device: int = 0) -> Graph:
+    """Loads COO lists (host arrays) onto `device`; see ahpp_graph_load in ahpp.h."""
+    lib = load_library()
+    eu = np.ascontiguousarray(edge_u, dtype=np.int32)
+    ev = np.ascontiguousarray(edge_v, dtype=np.int32)
+    ew = None if edge_w is None else np.ascontiguousarray(edge_w, dtype=np.float32)
+    au = np.ascontiguousarray(assoc_u, dtype=np.int32)
+    aa = np.ascontiguousarray(assoc_a, dtype=np.int32)
+    aw = None if assoc_w is None else np.ascontiguousarray(assoc_w, dtype=np.float32)
+    if eu.shape != ev.shape or (ew is not None and ew.shape != eu.shape):
+        raise ValueError("edge arrays differ in length")
+    if au.shape != aa.shape or (aw is not None and aw.shape != au.shape):
+        raise ValueError("association arrays differ in length")
+    d = GraphDesc(int(n_u), int(n_v), int(n_attr), int(eu.size), _np_ptr(eu), _np_ptr(ev), _np_ptr(ew),
+                  int(au.size), _np_ptr(au), _np_ptr(aa), _np_ptr(aw), float(alpha), float(beta), float(lam),
+                  int(lambda_iters), int(device))
+    h = ctypes.c_void_p()
+    _check(lib.ahpp_graph_load(ctypes.byref(d), ctypes.byref(h)))
+    return Graph(h, int(device))
+
+
+def load_graph(g, alpha: float = 0.15, beta: float = 0.35, lam: float = 0.0, lambda_iters: int = 0,
+               device: int = 0) -> Graph:
+    """ahpp_graph_load for an object with the fields of synth.AttributedBipartiteGraph."""
+    return ahpp_graph_load(g.n_u, g.n_v, g.n_attr, g.edge_u, g.edge_v, g.edge_w, g.assoc_u, g.assoc_a, g.assoc_w,
+                           alpha, beta, lam, lambda_iters, device)
+
+
+def ahpp_graph_info(g: Graph) -> dict:
+    info = GraphInfo()
+    _check(load_library().ahpp_graph_info(g._h, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in info._fields_}
+
+
+def ahpp_query(g: Graph, source: int, eps: float, k: int = 0, max_iters: int = 0, want_pi: bool = True,
+               want_resid: bool = False, want_stats: bool = True, stream=None,
+               allow_not_converged: bool = False) -> QueryResult:
+    """One eps-approximate query; outputs are torch tensors on the graph's device."""
+    import torch
+    dev = torch.device("cuda", g.device)
+    pi = torch.empty(g.n_u, dtype=torch.float32, device=dev) if want_pi else None
+    resid = torch.empty(g.n_u, dtype=torch.float32, device=dev) if want_resid else None
+    ti = torch.empty(max(k, 1), dtype=torch.int32, device=dev) if k > 0 else None
+    tv = torch.empty(max(k, 1), dtype=torch.float32, device=dev) if k > 0 else None
+    tn = torch.empty(1, dtype=torch.int32, device=dev) if k > 0 else None
+    st = Stats()
+    status = _check(load_library().ahpp_query(g._h, int(source), float(eps), int(max_iters), _dev_ptr(pi),
+                                              _dev_ptr(resid), int(k), _dev_ptr(ti), _dev_ptr(tv), _dev_ptr(tn),
+                                              ctypes.byref(st) if want_stats else None, _stream(g.device, stream)),
+                    allow_not_converged)
+    return QueryResult(pi, resid, ti, tv, tn, [st.as_dict()] if want_stats else [], status)
+
+
+def ahpp_query_batch(g: Graph, sources: Sequence[int], eps, k: int = 0, max_iters: int = 0, want_pi: bool = True,
+                     want_stats: bool = True, stream=None, allow_not_converged: bool = False) -> QueryResult:
+    """n_q queries answered together; row q of every output belongs to query q."""
+    import torch
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    n_q = int(src.size)
+    e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (n_q,)))
+    dev = torch.device("cuda", g.device)
+    pi = torch.empty((n_q, g.n_u), dtype=torch.float32, device=dev) if want_pi else None
+    ti = torch.empty((n_q, max(k, 1)), dtype=torch.int32, device=dev) if k > 0 else None
+    tv = torch.empty((n_q, max(k, 1)), dtype=torch.float32, device=dev) if k > 0 else None
+    tn = torch.empty(n_q, dtype=torch.int32, device=dev) if k > 0 else None
+    st = (Stats * max(n_q, 1))()
+    status = _check(load_library().ahpp_query_batch(g._h, n_q, _np_ptr(src), _np_ptr(e), int(max_iters),
+                                                    _dev_ptr(pi), int(k), _dev_ptr(ti), _dev_ptr(tv), _dev_ptr(tn),
+                                                    ctypes.cast(st, ctypes.c_void_p) if want_stats else None,
+                                                    _stream(g.device, stream)), allow_not_converged)
+    return QueryResult(pi, None, ti, tv, tn, [s.as_dict() for s in st[:n_q]] if want_stats else [], status)
+
+
+def ahpp_topk(g: Graph, pi, k: int, exclude: int = -1, stream=None):
+    """Top-k of a device score vector (torch float32 [n_u]): (idx, val, n) tensors."""
+    import torch
+    if pi.dtype != torch.float32 or not pi.is_cuda or pi.numel() != g.n_u or not pi.is_contiguous():
+        raise ValueError("pi must be a contiguous float32 device tensor of length n_u")
+    ti = torch.empty(max(k, 1), dtype=torch.int32, device=pi.device)
+    tv = torch.empty(max(k, 1), dtype=torch.float32, device=pi.device)
+    tn = torch.empty(1, dtype=torch.int32, device=pi.device)
+    _check(load_library().ahpp_topk(g._h, _dev_ptr(pi), int(k), int(exclude), _dev_ptr(ti), _dev_ptr(tv),
+                                    _dev_ptr(tn), _stream(g.device, stream)))
+    return ti, tv, tn

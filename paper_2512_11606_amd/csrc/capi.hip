@@ -1,0 +1,313 @@
+// C ABI of the AHPP library (declared in include/ahpp.h): argument checks,
+// device selection, the host side of the round loop, and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/ahpp.h"
+#include "ahpp_internal.h"
+
+struct ahpp_graph {
+    ahpp::Graph g;
+};
+
+namespace ahpp {
+
+namespace {
+thread_local std::string g_last_error;
+
+ahpp_status_t fail(int status, const std::string &msg) {
+    g_last_error = msg;
+    return (ahpp_status_t)status;
+}
+
+// Makes `dev` current for the lifetime of the object, restoring the
+// caller's device afterwards.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) check_hip(hipSetDevice(dev), "hipSetDevice");
+    }
+    ~DeviceScope() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+void ensure_query_scratch(Graph &g) {
+    if (g.q_r) return;
+    g.q_r = (float *)dev_alloc(g, (size_t)std::max<int64_t>(g.n_u, 1) * 4, "query residues");
+    g.q_pi = (float *)dev_alloc(g, (size_t)std::max<int64_t>(g.n_u, 1) * 4, "query reserves");
+    g.q_rho = (float *)dev_alloc(g, (size_t)std::max<int64_t>(2 * g.n_u, 1) * 4, "query push buffer");
+    g.q_z = (float *)dev_alloc(g, (size_t)std::max<int64_t>(g.n_v + g.n_a, 1) * 4, "query V/attribute residues");
+    g.q_ctl = (Control *)dev_alloc(g, sizeof(Control), "query control");
+}
+
+void ensure_topk_scratch(Graph &g, int64_t n_q) {
+    size_t need = topk_scratch_bytes(n_q);
+    if (g.tk_scratch_bytes >= need) return;
+    if (g.tk_scratch) {
+        dfree(g.tk_scratch);
+        g.device_bytes -= (int64_t)g.tk_scratch_bytes;
+    }
+    g.tk_scratch = nullptr;
+    g.tk_scratch_bytes = 0;
+    g.tk_scratch = dev_alloc(g, need, "top-k scratch");
+    g.tk_scratch_bytes = need;
+}
+
+int default_lambda_iters(int64_t n_u, double alpha) {
+    double t = std::ceil(std::log(0.01 / (double)std::max<int64_t>(n_u, 1)) / std::log(1.0 - alpha));
+    return std::max(1, (int)t);
+}
+
+// Runs rounds until the control block reports done; the host checks after
+// chunks of rounds that grow from 4 to 32.
+void run_single(Graph &g, hipStream_t s) {
+    int chunk = 4;
+    for (;;) {
+        for (int i = 0; i < chunk; ++i) single_query_round(g, s);
+        int32_t done = 0;
+        check_hip(hipMemcpyAsync(&done, &g.q_ctl->done, sizeof(int32_t), hipMemcpyDeviceToHost, s), "poll");
+        check_hip(hipStreamSynchronize(s), "poll");
+        if (done) break;
+        chunk = std::min(chunk * 2, 32);
+    }
+}
+
+}  // namespace
+
+void check_hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory) throw Failure{AHPP_ERR_OUT_OF_MEMORY, std::string(what) + ": out of device memory"};
+    throw Failure{AHPP_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+void *dev_alloc(Graph &g, size_t bytes, const char *what) {
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Failure{AHPP_ERR_OUT_OF_MEMORY, std::string(what) + ": hipMalloc of " + std::to_string(bytes) +
+                                                   " bytes failed (" + hipGetErrorString(e) + ")"};
+    }
+    g.device_bytes += (int64_t)bytes;
+    return p;
+}
+
+}  // namespace ahpp
+
+using namespace ahpp;
+
+extern "C" {
+
+const char *ahpp_last_error(void) { return g_last_error.c_str(); }
+
+ahpp_status_t ahpp_graph_load(const ahpp_graph_desc_t *d, ahpp_graph_t **out) {
+    g_last_error.clear();
+    if (!d || !out) return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: desc and out must not be NULL");
+    *out = nullptr;
+    if (d->n_u <= 0 || d->n_v < 0 || d->n_attr < 0 || d->n_edges < 0 || d->n_assoc < 0)
+        return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: sizes must be >= 0 and n_u >= 1");
+    if (d->n_u > INT32_MAX || d->n_v > INT32_MAX || d->n_attr > INT32_MAX || 2 * d->n_u > INT32_MAX ||
+        d->n_v + d->n_attr > INT32_MAX)
+        return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: node counts exceed the int32 id range");
+    if ((d->n_edges > 0 && (!d->edge_u || !d->edge_v)) || (d->n_assoc > 0 && (!d->assoc_u || !d->assoc_a)))
+        return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: id arrays must not be NULL when their count is > 0");
+    if (!(d->alpha > 0.0 && d->alpha < 1.0)) return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: alpha must be in (0,1)");
+    if (!(d->beta >= 0.0 && d->beta <= 1.0)) return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: beta must be in [0,1]");
+    if (std::isnan(d->lambda) || std::isinf(d->lambda))
+        return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: lambda must be finite");
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev <= 0)
+        return fail(AHPP_ERR_DEVICE, "ahpp_graph_load: no HIP device");
+    if (d->device < 0 || d->device >= n_dev) return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: bad device ordinal");
+    ahpp_graph *h = new (std::nothrow) ahpp_graph();
+    if (!h) return fail(AHPP_ERR_OUT_OF_MEMORY, "ahpp_graph_load: host allocation failed");
+    Graph &g = h->g;
+    g.device = d->device;
+    g.n_u = d->n_u;
+    g.n_v = d->n_v;
+    g.n_a = d->n_attr;
+    g.m_e = d->n_edges;
+    g.m_a = d->n_assoc;
+    g.alpha = d->alpha;
+    g.beta = d->beta;
+    hipStream_t s = nullptr;
+    try {
+        DeviceScope scope(g.device);
+        check_hip(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "stream");
+        build_graph(g, d->edge_u, d->edge_v, d->edge_w, d->assoc_u, d->assoc_a, d->assoc_w, s);
+        ensure_query_scratch(g);
+        ensure_topk_scratch(g, 1);
+        if (d->lambda > 0) {
+            g.lambda = d->lambda;
+            g.lambda_iters = 0;
+        } else {
+            auto t0 = std::chrono::steady_clock::now();
+            g.lambda_iters = d->lambda_iters > 0 ? d->lambda_iters : default_lambda_iters(g.n_u, g.alpha);
+            g.lambda = compute_lambda(g, g.lambda_iters, s) * (1.0 + 1e-4);
+            g.lambda_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        check_hip(hipStreamSynchronize(s), "load");
+        check_hip(hipStreamDestroy(s), "stream");
+        s = nullptr;
+    } catch (const Failure &f) {
+        if (s) (void)hipStreamDestroy(s);
+        free_graph(g);
+        delete h;
+        return fail(f.status, f.msg);
+    } catch (const std::exception &e) {
+        if (s) (void)hipStreamDestroy(s);
+        free_graph(g);
+        delete h;
+        return fail(AHPP_ERR_OUT_OF_MEMORY, std::string("ahpp_graph_load: ") + e.what());
+    }
+    *out = h;
+    return AHPP_OK;
+}
+
+ahpp_status_t ahpp_graph_info(const ahpp_graph_t *h, ahpp_graph_info_t *info) {
+    g_last_error.clear();
+    if (!h || !info) return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_info: NULL argument");
+    const Graph &g = h->g;
+    info->n_u = g.n_u;
+    info->n_v = g.n_v;
+    info->n_attr = g.n_a;
+    info->n_edges = g.m_e;
+    info->n_assoc = g.m_a;
+    info->alpha = g.alpha;
+    info->beta = g.beta;
+    info->lambda = g.lambda;
+    info->lambda_iters = g.lambda_iters;
+    info->device = g.device;
+    info->dangling_u = g.dangling_u;
+    info->device_bytes = g.device_bytes;
+    info->load_ms = g.load_ms;
+    info->lambda_ms = g.lambda_ms;
+    return AHPP_OK;
+}
+
+void ahpp_graph_free(ahpp_graph_t *h) {
+    if (!h) return;
+    try {
+        DeviceScope scope(h->g.device);
+        (void)hipDeviceSynchronize();
+        free_graph(h->g);
+    } catch (...) {
+    }
+    delete h;
+}
+
+ahpp_status_t ahpp_query(ahpp_graph_t *h, int32_t source, double eps, int32_t max_iters, float *pi_out,
+                         float *resid_out, int32_t k, int32_t *topk_idx, float *topk_val, int32_t *topk_n,
+                         ahpp_stats_t *stats, void *hip_stream) {
+    g_last_error.clear();
+    if (!h) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query: NULL graph");
+    Graph &g = h->g;
+    if (source < 0 || source >= g.n_u) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query: source out of range");
+    if (!(eps > 0.0) || std::isinf(eps)) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query: eps must be > 0 and finite");
+    if (k < 0 || k > kMaxTopK) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query: k must be in [0, 2048]");
+    if (k > 0 && (!topk_idx || !topk_val || !topk_n))
+        return fail(AHPP_ERR_INVALID_ARG, "ahpp_query: top-k outputs required when k > 0");
+    if (max_iters <= 0) max_iters = 100000;
+    hipStream_t s = (hipStream_t)hip_stream;
+    int32_t status = 0;
+    try {
+        DeviceScope scope(g.device);
+        hipEvent_t e0, e1;
+        check_hip(hipEventCreate(&e0), "event");
+        check_hip(hipEventCreate(&e1), "event");
+        check_hip(hipEventRecord(e0, s), "event");
+        const float eps_f = (float)(eps / g.lambda);
+        single_query_init(g, source, eps_f, max_iters, s);
+        run_single(g, s);
+        if (k > 0)
+            topk_launch(g.q_pi, g.n_u, 0, 1, nullptr, source, k, topk_idx, topk_val, topk_n, g.tk_scratch, s);
+        if (pi_out) check_hip(hipMemcpyAsync(pi_out, g.q_pi, (size_t)g.n_u * 4, hipMemcpyDeviceToDevice, s), "pi out");
+        if (resid_out)
+            check_hip(hipMemcpyAsync(resid_out, g.q_r, (size_t)g.n_u * 4, hipMemcpyDeviceToDevice, s), "resid out");
+        check_hip(hipEventRecord(e1, s), "event");
+        Control ctl;
+        check_hip(hipMemcpyAsync(&ctl, g.q_ctl, sizeof(Control), hipMemcpyDeviceToHost, s), "control D2H");
+        check_hip(hipStreamSynchronize(s), "query");
+        status = ctl.status;
+        float ms = 0.0f;
+        check_hip(hipEventElapsedTime(&ms, e0, e1), "event");
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (stats) {
+            double sum_r = 0.0;
+            single_query_stats(g, &sum_r, s);
+            stats->iters = ctl.iter;
+            stats->sync_switch_iter = ctl.switch_iter;
+            stats->converged = ctl.status == 1;
+            stats->reserved = 0;
+            stats->n_push = (int64_t)ctl.n_p;
+            stats->max_residual = ctl.last_max;
+            stats->sum_residual = sum_r;
+            stats->ms = ms;
+            stats->pad = 0;
+        }
+    } catch (const Failure &f) {
+        return fail(f.status, f.msg);
+    }
+    if (status != 1) return fail(AHPP_ERR_NOT_CONVERGED, "ahpp_query: max_iters reached before max r <= eps/lambda");
+    return AHPP_OK;
+}
+
+ahpp_status_t ahpp_query_batch(ahpp_graph_t *h, int32_t n_q, const int32_t *sources, const double *eps,
+                               int32_t max_iters, float *pi_out, int32_t k, int32_t *topk_idx, float *topk_val,
+                               int32_t *topk_n, ahpp_stats_t *stats, void *hip_stream) {
+    g_last_error.clear();
+    if (!h) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_batch: NULL graph");
+    Graph &g = h->g;
+    if (n_q < 0) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_batch: n_q < 0");
+    if (n_q == 0) return AHPP_OK;
+    if (!sources || !eps) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_batch: sources and eps required");
+    for (int32_t q = 0; q < n_q; ++q) {
+        if (sources[q] < 0 || sources[q] >= g.n_u) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_batch: source out of range");
+        if (!(eps[q] > 0.0) || std::isinf(eps[q])) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_batch: eps must be > 0");
+    }
+    if (k < 0 || k > kMaxTopK) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_batch: k must be in [0, 2048]");
+    if (k > 0 && (!topk_idx || !topk_val || !topk_n))
+        return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_batch: top-k outputs required when k > 0");
+    ahpp_status_t worst = AHPP_OK;
+    for (int32_t q = 0; q < n_q; ++q) {
+        ahpp_status_t st = ahpp_query(h, sources[q], eps[q], max_iters, pi_out ? pi_out + (size_t)q * g.n_u : nullptr,
+                                      nullptr, k, k ? topk_idx + (size_t)q * k : nullptr,
+                                      k ? topk_val + (size_t)q * k : nullptr, k ? topk_n + q : nullptr,
+                                      stats ? stats + q : nullptr, hip_stream);
+        if (st == AHPP_ERR_NOT_CONVERGED) worst = st;
+        else if (st != AHPP_OK) return st;
+    }
+    if (worst != AHPP_OK) return fail(worst, "ahpp_query_batch: some query reached max_iters");
+    return AHPP_OK;
+}
+
+ahpp_status_t ahpp_topk(const ahpp_graph_t *hc, const float *pi, int32_t k, int32_t exclude, int32_t *idx_out,
+                        float *val_out, int32_t *n_out, void *hip_stream) {
+    g_last_error.clear();
+    if (!hc || !pi || !idx_out || !val_out || !n_out) return fail(AHPP_ERR_INVALID_ARG, "ahpp_topk: NULL argument");
+    ahpp_graph_t *h = const_cast<ahpp_graph_t *>(hc);
+    Graph &g = h->g;
+    if (k < 1 || k > kMaxTopK) return fail(AHPP_ERR_INVALID_ARG, "ahpp_topk: k must be in [1, 2048]");
+    if (exclude < -1 || exclude >= g.n_u) return fail(AHPP_ERR_INVALID_ARG, "ahpp_topk: exclude out of range");
+    try {
+        DeviceScope scope(g.device);
+        topk_launch(pi, g.n_u, 0, 1, nullptr, exclude, k, idx_out, val_out, n_out, g.tk_scratch,
+                    (hipStream_t)hip_stream);
+    } catch (const Failure &f) {
+        return fail(f.status, f.msg);
+    }
+    return AHPP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,449 @@
+// Device-side construction of the AHPP graph store (once per graph).
+//
+// From the COO lists E and E_A (Section 2.1) this builds, in HBM:
+//   fwd : CSR over U.  Row u holds its V neighbours N(u) (column v) followed by
+//         its attributes A(u) (column n_v + a), each with its raw weight.
+//   back: CSR over V then attributes.  Row v holds N(v) (column u); row
+//         n_v + a holds A^-1(a) (column n_u + u, so that one gathered vector
+//         of length 2 n_u serves both halves).
+// and the per-node coefficients of the push (Eq. 1 and Eq. 2 denominators):
+//   c_d[u]   = (1-beta)(1-alpha) / d(u),     c_s[u] = beta (1-alpha) / s(u),
+//   inv_b[v] = 1 / d(v),                     inv_b[n_v + a] = 1 / t(a).
+// Rows keep the input order of their entries: a stable LSD radix sort
+// (4-bit digits) groups entries by row.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "ahpp_internal.h"
+#include "dev_util.h"
+
+namespace ahpp {
+
+namespace {
+
+constexpr int kSortItems = 8;                       // keys per thread
+constexpr int kSortTile = kBlock * kSortItems;      // keys per workgroup
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+// ---------------------------------------------------------------- validation
+
+// flags bit 0: edge id out of range, bit 1: edge weight <= 0 or not finite,
+//       bit 2: attribute id out of range, bit 3: attribute value <= 0 or not
+//       finite, bit 4: some weight differs from 1.
+__global__ void k_validate(const int32_t *a, const int32_t *b, const float *w, int64_t m, int64_t na, int64_t nb,
+                           int id_bit, int w_bit, unsigned *flags) {
+    unsigned f = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t x = a[i], y = b[i];
+        if (x < 0 || x >= na || y < 0 || y >= nb) f |= 1u << id_bit;
+        if (w) {
+            float v = w[i];
+            if (!(v > 0.0f) || !isfinite(v)) f |= 1u << w_bit;
+            if (v != 1.0f) f |= 1u << 4;
+        }
+    }
+    if (f) atomicOr(flags, f);
+}
+
+// Keys, columns and weights of the entries to sort.
+__global__ void k_make_entries(const int32_t *row_ids, const int32_t *col_ids, const float *w, int64_t m,
+                               int32_t col_offset, uint32_t key_offset, uint32_t *key, int32_t *col, float *wo) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        key[i] = (uint32_t)row_ids[i] + key_offset;
+        col[i] = col_ids[i] + col_offset;
+        wo[i] = w ? w[i] : 1.0f;
+    }
+}
+
+// ---------------------------------------------------------------- scan
+
+__global__ void k_scan_partials(const unsigned long long *in, int64_t n, unsigned long long *part) {
+    __shared__ unsigned long long lds[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    unsigned long long s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j)
+        if (base + j < n) s += in[base + j];
+    s = block_sum<unsigned long long>(s, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Exclusive scan of `part` (n_part entries) by one workgroup, in place.
+__global__ void k_scan_single(unsigned long long *part, int64_t n_part) {
+    __shared__ unsigned long long lds[4];
+    unsigned long long carry = 0;
+    for (int64_t base = 0; base < n_part; base += kBlock) {
+        int64_t i = base + threadIdx.x;
+        unsigned long long v = i < n_part ? part[i] : 0ull;
+        unsigned long long tot;
+        unsigned long long ex = block_exclusive_scan<unsigned long long>(v, lds, &tot);
+        if (i < n_part) part[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ void k_scan_apply(const unsigned long long *in, int64_t n, const unsigned long long *part,
+                             unsigned long long *out) {
+    __shared__ unsigned long long lds[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    unsigned long long v[kScanItems];
+    unsigned long long s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        v[j] = base + j < n ? in[base + j] : 0ull;
+        s += v[j];
+    }
+    unsigned long long tot;
+    unsigned long long ex = block_exclusive_scan<unsigned long long>(s, lds, &tot) + part[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        if (base + j < n) out[base + j] = ex;
+        ex += v[j];
+    }
+}
+
+// Exclusive scan of n unsigned 64-bit values (in may equal out).
+void exclusive_scan_u64(const unsigned long long *in, unsigned long long *out, int64_t n,
+                        unsigned long long *part, hipStream_t s) {
+    if (n <= 0) return;
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kBlock), 0, s, part, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, part, out);
+    check_hip(hipGetLastError(), "scan launch");
+}
+
+// ---------------------------------------------------------------- radix sort
+
+// Digit histogram of every tile, stored digit-major: cnt[d * n_tiles + t].
+__global__ void k_radix_count(const uint32_t *key, int64_t n, int shift, unsigned long long *cnt, int64_t n_tiles) {
+    __shared__ unsigned h[16];
+    if (threadIdx.x < 16) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j)
+        if (base + j < n) atomicAdd(&h[(key[base + j] >> shift) & 15u], 1u);
+    __syncthreads();
+    if (threadIdx.x < 16) cnt[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter of one tile: thread t owns keys [t*8, t*8+8) of the tile, so
+// (thread, item) order is input order; within a digit, keys keep that order.
+__global__ void k_radix_scatter(const uint32_t *key, const int32_t *col, const float *w, int64_t n, int shift,
+                                const unsigned long long *dig_off, int64_t n_tiles, uint32_t *key_o, int32_t *col_o,
+                                float *w_o) {
+    __shared__ unsigned cnt[16 * kBlock];  // [digit][thread]
+    __shared__ unsigned dstart[16];
+    __shared__ unsigned lds[4];
+    const int tid = threadIdx.x;
+    for (int d = 0; d < 16; ++d) cnt[d * kBlock + tid] = 0;
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)tid * kSortItems;
+    uint32_t k[kSortItems];
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        k[j] = base + j < n ? key[base + j] : 0xffffffffu;
+        if (base + j < n) cnt[((k[j] >> shift) & 15u) * kBlock + tid] += 1;
+    }
+    __syncthreads();
+    // Exclusive scan over cnt in digit-major order: thread tid scans entries
+    // [tid*16, tid*16+16).
+    unsigned v[16];
+    unsigned s = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        v[j] = cnt[tid * 16 + j];
+        s += v[j];
+    }
+    unsigned tot;
+    unsigned ex = block_exclusive_scan<unsigned>(s, lds, &tot);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        cnt[tid * 16 + j] = ex;
+        ex += v[j];
+    }
+    __syncthreads();
+    // Tile-local start of digit d, read before any thread advances its slots.
+    if (tid < 16) dstart[tid] = cnt[tid * kBlock];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        if (base + j >= n) continue;
+        unsigned d = (k[j] >> shift) & 15u;
+        unsigned local = cnt[d * kBlock + tid] - dstart[d];
+        cnt[d * kBlock + tid] += 1;
+        int64_t pos = (int64_t)dig_off[(int64_t)d * n_tiles + blockIdx.x] + local;
+        key_o[pos] = k[j];
+        col_o[pos] = col[base + j];
+        w_o[pos] = w[base + j];
+    }
+}
+
+// off[r] = first position whose key is >= r, for r in [0, n_rows]; key sorted.
+__global__ void k_offsets(const uint32_t *key, int64_t n, int64_t n_rows, int64_t *off) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t prev = i == 0 ? -1 : (int64_t)key[i - 1];
+        int64_t cur = i == n ? n_rows : (int64_t)key[i];
+        for (int64_t r = prev + 1; r <= cur; ++r) off[r] = i;
+    }
+}
+
+// Row sums of fwd: d(u) over columns < n_v, s(u) over the rest.
+__global__ void k_fwd_coeffs(const int64_t *off, const int32_t *col, const float *w, int64_t n_u, int64_t n_v,
+                             float alpha, float beta, float *c_d, float *c_s, unsigned long long *dangling) {
+    unsigned long long dang = 0;
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n_u; u += (int64_t)gridDim.x * blockDim.x) {
+        double d = 0.0, s = 0.0;
+        for (int64_t p = off[u]; p < off[u + 1]; ++p) {
+            double x = w ? (double)w[p] : 1.0;
+            if (col[p] < n_v) d += x; else s += x;
+        }
+        c_d[u] = d > 0 ? (float)((1.0 - beta) * (1.0 - alpha) / d) : 0.0f;
+        c_s[u] = s > 0 ? (float)(beta * (1.0 - alpha) / s) : 0.0f;
+        if (!(d > 0) || !(s > 0)) dang += 1;
+    }
+    if (dang) atomicAdd(dangling, dang);
+}
+
+__global__ void k_back_coeffs(const int64_t *off, const float *w, int64_t n_rows, float *inv_b) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n_rows; r += (int64_t)gridDim.x * blockDim.x) {
+        double d = 0.0;
+        for (int64_t p = off[r]; p < off[r + 1]; ++p) d += w ? (double)w[p] : 1.0;
+        inv_b[r] = d > 0 ? (float)(1.0 / d) : 0.0f;
+    }
+}
+
+unsigned grid_for(int64_t n, int per_block = kBlock, unsigned cap = 65536u) {
+    int64_t g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    return (unsigned)std::min<int64_t>(g, cap);
+}
+
+int bits_for(int64_t n) {
+    int b = 1;
+    while ((int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+// Builds the wave schedule of a CSR from its host copy of the offsets.
+void build_items(const std::vector<int64_t> &off, std::vector<WorkItem> &items, std::vector<int32_t> &split,
+                 int32_t &max_len) {
+    const int64_t n_rows = (int64_t)off.size() - 1;
+    items.clear();
+    split.clear();
+    max_len = 0;
+    int64_t r = 0;
+    while (r < n_rows) {
+        int64_t len = off[r + 1] - off[r];
+        max_len = (int32_t)std::max<int64_t>(max_len, len);
+        if (len > kShortRow) {
+            int64_t chunks = (len + kItemEdges - 1) / kItemEdges;
+            if (chunks > 1) split.push_back((int32_t)r);
+            for (int64_t c = 0; c < chunks; ++c) items.push_back(WorkItem{(int32_t)r, (int32_t)(-c)});
+            ++r;
+            continue;
+        }
+        // Pack consecutive short rows.
+        int64_t r1 = r, e = 0;
+        while (r1 < n_rows && r1 - r < kMaxRowsPerItem) {
+            int64_t l = off[r1 + 1] - off[r1];
+            if (l > kShortRow || e + l > kItemEdges) break;
+            e += l;
+            ++r1;
+        }
+        items.push_back(WorkItem{(int32_t)r, (int32_t)(r1 - r)});
+        r = r1;
+    }
+}
+
+// Sorts (key, col, w) by key (stable) and builds offsets + schedule.
+void build_csr(Graph &g, DevCsr &c, int64_t n_rows, uint32_t *key, int32_t *col, float *w, int64_t m,
+               hipStream_t s) {
+    c.n_rows = n_rows;
+    c.nnz = m;
+    c.off = (int64_t *)dev_alloc(g, (size_t)(n_rows + 1) * sizeof(int64_t), "csr offsets");
+    c.col = (int32_t *)dev_alloc(g, (size_t)std::max<int64_t>(m, 1) * sizeof(int32_t), "csr columns");
+    if (!g.unit) c.w = (float *)dev_alloc(g, (size_t)std::max<int64_t>(m, 1) * sizeof(float), "csr weights");
+    if (m > 0) {
+        uint32_t *key2 = nullptr;
+        int32_t *col2 = nullptr;
+        float *w2 = nullptr;
+        unsigned long long *cnt = nullptr, *part = nullptr;
+        const int64_t n_tiles = (m + kSortTile - 1) / kSortTile;
+        const int64_t n_cnt = 16 * n_tiles;
+        check_hip(hipMalloc(&key2, (size_t)m * 4), "sort buffer");
+        check_hip(hipMalloc(&col2, (size_t)m * 4), "sort buffer");
+        check_hip(hipMalloc(&w2, (size_t)m * 4), "sort buffer");
+        check_hip(hipMalloc(&cnt, (size_t)n_cnt * 8), "sort counts");
+        check_hip(hipMalloc(&part, (size_t)((n_cnt + kScanTile - 1) / kScanTile + 1) * 8), "scan partials");
+        const int passes = (bits_for(n_rows) + 3) / 4;
+        uint32_t *ki = key, *ko = key2;
+        int32_t *ci = col, *co = col2;
+        float *wi = w, *wo = w2;
+        for (int p = 0; p < passes; ++p) {
+            hipLaunchKernelGGL(k_radix_count, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, ki, m, 4 * p, cnt, n_tiles);
+            exclusive_scan_u64(cnt, cnt, n_cnt, part, s);
+            hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, ki, ci, wi, m, 4 * p, cnt,
+                               n_tiles, ko, co, wo);
+            check_hip(hipGetLastError(), "radix sort launch");
+            std::swap(ki, ko);
+            std::swap(ci, co);
+            std::swap(wi, wo);
+        }
+        hipLaunchKernelGGL(k_offsets, dim3(grid_for(m + 1)), dim3(kBlock), 0, s, ki, m, n_rows, c.off);
+        check_hip(hipMemcpyAsync(c.col, ci, (size_t)m * 4, hipMemcpyDeviceToDevice, s), "csr copy");
+        if (c.w) check_hip(hipMemcpyAsync(c.w, wi, (size_t)m * 4, hipMemcpyDeviceToDevice, s), "csr copy");
+        check_hip(hipStreamSynchronize(s), "csr build");
+        dfree(key2);
+        dfree(col2);
+        dfree(w2);
+        dfree(cnt);
+        dfree(part);
+    } else {
+        check_hip(hipMemsetAsync(c.off, 0, (size_t)(n_rows + 1) * sizeof(int64_t), s), "csr offsets");
+    }
+    // Wave schedule (host side: a linear greedy pass over the offsets).
+    std::vector<int64_t> off((size_t)n_rows + 1);
+    check_hip(hipMemcpyAsync(off.data(), c.off, off.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s), "offsets D2H");
+    check_hip(hipStreamSynchronize(s), "offsets D2H");
+    std::vector<WorkItem> items;
+    std::vector<int32_t> split;
+    build_items(off, items, split, c.max_row_len);
+    c.n_items = (int64_t)items.size();
+    c.n_split = (int64_t)split.size();
+    c.items = (WorkItem *)dev_alloc(g, std::max<size_t>(items.size(), 1) * sizeof(WorkItem), "schedule");
+    c.split_rows = (int32_t *)dev_alloc(g, std::max<size_t>(split.size(), 1) * sizeof(int32_t), "split rows");
+    c.split_cnt = (uint32_t *)dev_alloc(g, (size_t)std::max<int64_t>(n_rows, 1) * sizeof(uint32_t), "split counters");
+    if (!items.empty())
+        check_hip(hipMemcpyAsync(c.items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s),
+                  "schedule H2D");
+    if (!split.empty())
+        check_hip(hipMemcpyAsync(c.split_rows, split.data(), split.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+                  "split H2D");
+    check_hip(hipMemsetAsync(c.split_cnt, 0, (size_t)std::max<int64_t>(n_rows, 1) * sizeof(uint32_t), s),
+              "split counters");
+    check_hip(hipStreamSynchronize(s), "schedule upload");
+}
+
+}  // namespace
+
+void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew, const int32_t *au,
+                 const int32_t *aa, const float *aw, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int64_t m_e = g.m_e, m_a = g.m_a, m = m_e + m_a;
+    // Upload COO.
+    int32_t *d_eu = nullptr, *d_ev = nullptr, *d_au = nullptr, *d_aa = nullptr;
+    float *d_ew = nullptr, *d_aw = nullptr;
+    unsigned *d_flags = nullptr;
+    auto up = [&](void **dst, const void *src, int64_t n, const char *what) {
+        if (n <= 0 || !src) return;
+        check_hip(hipMalloc(dst, (size_t)n * 4), what);
+        check_hip(hipMemcpyAsync(*dst, src, (size_t)n * 4, hipMemcpyHostToDevice, s), what);
+    };
+    up((void **)&d_eu, eu, m_e, "edge upload");
+    up((void **)&d_ev, ev, m_e, "edge upload");
+    up((void **)&d_ew, ew, m_e, "edge upload");
+    up((void **)&d_au, au, m_a, "assoc upload");
+    up((void **)&d_aa, aa, m_a, "assoc upload");
+    up((void **)&d_aw, aw, m_a, "assoc upload");
+    check_hip(hipMalloc(&d_flags, sizeof(unsigned)), "flags");
+    check_hip(hipMemsetAsync(d_flags, 0, sizeof(unsigned), s), "flags");
+    if (m_e > 0)
+        hipLaunchKernelGGL(k_validate, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_eu, d_ev, d_ew, m_e, g.n_u, g.n_v, 0,
+                           1, d_flags);
+    if (m_a > 0)
+        hipLaunchKernelGGL(k_validate, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_au, d_aa, d_aw, m_a, g.n_u, g.n_a, 2,
+                           3, d_flags);
+    unsigned flags = 0;
+    check_hip(hipMemcpyAsync(&flags, d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, s), "flags D2H");
+    check_hip(hipStreamSynchronize(s), "validation");
+    dfree(d_flags);
+    auto release = [&]() {
+        dfree(d_eu); dfree(d_ev); dfree(d_ew); dfree(d_au); dfree(d_aa); dfree(d_aw);
+    };
+    if (flags & 15u) {
+        release();
+        std::string msg = "ahpp_graph_load:";
+        if (flags & 1u) msg += " edge id out of range;";
+        if (flags & 2u) msg += " edge weight not positive and finite;";
+        if (flags & 4u) msg += " attribute association id out of range;";
+        if (flags & 8u) msg += " attribute value not positive and finite;";
+        throw Failure{-1, msg};
+    }
+    g.unit = !(flags & 16u);
+
+    // Entries of both CSRs.
+    uint32_t *key = nullptr;
+    int32_t *col = nullptr;
+    float *w = nullptr;
+    if (m > 0) {
+        check_hip(hipMalloc(&key, (size_t)m * 4), "entries");
+        check_hip(hipMalloc(&col, (size_t)m * 4), "entries");
+        check_hip(hipMalloc(&w, (size_t)m * 4), "entries");
+    }
+    // fwd: rows U; edges (col v) then associations (col n_v + a).
+    if (m_e > 0)
+        hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_eu, d_ev, d_ew, m_e, 0, 0u, key,
+                           col, w);
+    if (m_a > 0)
+        hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_au, d_aa, d_aw, m_a,
+                           (int32_t)g.n_v, 0u, key + m_e, col + m_e, w + m_e);
+    build_csr(g, g.fwd, g.n_u, key, col, w, m, s);
+    // back: rows V (col u) then attributes (row n_v + a, col n_u + u).
+    if (m_e > 0)
+        hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_ev, d_eu, d_ew, m_e, 0, 0u, key,
+                           col, w);
+    if (m_a > 0)
+        hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_aa, d_au, d_aw, m_a,
+                           (int32_t)g.n_u, (uint32_t)g.n_v, key + m_e, col + m_e, w + m_e);
+    build_csr(g, g.back, g.n_v + g.n_a, key, col, w, m, s);
+    dfree(key);
+    dfree(col);
+    dfree(w);
+    release();
+
+    // Coefficients.
+    g.c_d = (float *)dev_alloc(g, (size_t)std::max<int64_t>(g.n_u, 1) * 4, "c_d");
+    g.c_s = (float *)dev_alloc(g, (size_t)std::max<int64_t>(g.n_u, 1) * 4, "c_s");
+    g.inv_b = (float *)dev_alloc(g, (size_t)std::max<int64_t>(g.n_v + g.n_a, 1) * 4, "inv_b");
+    unsigned long long *d_dang = nullptr;
+    check_hip(hipMalloc(&d_dang, 8), "dangling");
+    check_hip(hipMemsetAsync(d_dang, 0, 8, s), "dangling");
+    if (g.n_u > 0)
+        hipLaunchKernelGGL(k_fwd_coeffs, dim3(grid_for(g.n_u)), dim3(kBlock), 0, s, g.fwd.off, g.fwd.col, g.fwd.w,
+                           g.n_u, g.n_v, (float)g.alpha, (float)g.beta, g.c_d, g.c_s, d_dang);
+    if (g.n_v + g.n_a > 0)
+        hipLaunchKernelGGL(k_back_coeffs, dim3(grid_for(g.n_v + g.n_a)), dim3(kBlock), 0, s, g.back.off, g.back.w,
+                           g.n_v + g.n_a, g.inv_b);
+    check_hip(hipGetLastError(), "coefficient launch");
+    unsigned long long dang = 0;
+    check_hip(hipMemcpyAsync(&dang, d_dang, 8, hipMemcpyDeviceToHost, s), "dangling D2H");
+    check_hip(hipStreamSynchronize(s), "coefficients");
+    dfree(d_dang);
+    g.dangling_u = (int64_t)dang;
+    g.load_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+static void free_csr(DevCsr &c) {
+    dfree(c.off); dfree(c.col); dfree(c.w); dfree(c.items); dfree(c.split_rows); dfree(c.split_cnt);
+    c = DevCsr{};
+}
+
+void free_graph(Graph &g) {
+    free_csr(g.fwd);
+    free_csr(g.back);
+    dfree(g.c_d); dfree(g.c_s); dfree(g.inv_b);
+    dfree(g.q_r); dfree(g.q_pi); dfree(g.q_rho); dfree(g.q_z); dfree(g.q_ctl);
+    dfree(g.tk_scratch);
+    g.c_d = g.c_s = g.inv_b = nullptr;
+    g.q_r = g.q_pi = g.q_rho = g.q_z = nullptr;
+    g.q_ctl = nullptr;
+    g.tk_scratch = nullptr;
+}
+
+}  // namespace ahpp

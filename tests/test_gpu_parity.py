@@ -1,0 +1,210 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Acceptance per query (Theorem 2 with the tolerance of the GPU's float32
+arithmetic): |pi - pi_hat| <= eps + 1e-6, pi_hat >= 0, pi_hat <= pi + 1e-6,
+|sum pi_hat + sum r - 1| <= 1e-5 without dangling nodes, and the top-k list
+inside the band around the exact k-th score.  Index work (top-k of a given
+vector) is compared exactly.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2512_11606_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ahpp(torch_cuda):
+    from paper_2512_11606_amd import ahpp as A
+    A.load_library()
+    return A
+
+
+@pytest.fixture(scope="module")
+def tiny(ahpp, tiny_graph):
+    _say("load tiny graph")
+    g = ahpp.load_graph(tiny_graph)
+    yield g
+    g.free()
+
+
+def _check(torch, res, exact, eps, k=0, source=-1, resid=True):
+    pi = res.pi.cpu().numpy().astype(np.float64)
+    r = res.resid.cpu().numpy().astype(np.float64) if (resid and res.resid is not None) else None
+    ids = res.topk_idx[: int(res.topk_n.item())].cpu().numpy() if k else None
+    return O.check_query(exact, pi, eps, tol=TOL, resid=r, k=k, source=source, topk_ids=ids)
+
+
+def test_lambda_matches_theorem3(tiny, tiny_oracle):
+    lam_o = tiny_oracle.lambda_thm3(T=tiny.info["lambda_iters"])
+    assert tiny.lam >= lam_o
+    assert tiny.lam == pytest.approx(lam_o * (1 + 1e-4), rel=2e-5)
+
+
+def test_graph_info(tiny, tiny_graph):
+    i = tiny.info
+    assert (i["n_u"], i["n_v"], i["n_attr"]) == (tiny_graph.n_u, tiny_graph.n_v, tiny_graph.n_attr)
+    assert i["n_edges"] == tiny_graph.m_e and i["n_assoc"] == tiny_graph.m_a
+    assert i["dangling_u"] == 0
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_tiny_queries_meet_guarantee(torch_cuda, ahpp, tiny, tiny_Pi, tiny_graph, eps):
+    srcs = synth.uniform_queries(tiny_graph, 40, 4242)
+    srcs = np.concatenate([srcs, synth.hub_queries(tiny_graph, 8, 4243)])
+    worst = 0.0
+    for s in srcs.tolist():
+        _say("tiny query", s, eps)
+        res = ahpp.ahpp_query(tiny, s, eps, k=20, want_resid=True)
+        chk = _check(torch_cuda, res, tiny_Pi[s], eps, k=20, source=s)
+        assert chk.ok, (s, chk.detail)
+        assert res.stats[0]["converged"] == 1
+        assert res.stats[0]["max_residual"] <= eps / tiny.lam * (1 + 1e-6)
+        worst = max(worst, chk.max_abs_err)
+    print(f"worst |err| = {worst:.3e} (eps {eps:g})")
+
+
+def test_weighted_graph_against_power_series(torch_cuda, ahpp):
+    g = synth.make_custom(6000, 2500, 60000, 300, 8, seed=515, unit_weights=False)
+    og = O.OracleGraph.from_graph(g)
+    _say("load weighted 6000-node graph")
+    dg = ahpp.load_graph(g)
+    lam_o = og.lambda_thm3(T=dg.info["lambda_iters"])
+    assert dg.lam == pytest.approx(lam_o * (1 + 1e-4), rel=2e-5)
+    for s in synth.degree_queries(g, 6, 99).tolist():
+        for eps in (1e-5, 1e-7):
+            _say("weighted query", s, eps)
+            res = ahpp.ahpp_query(dg, s, eps, k=50, want_resid=True)
+            exact, _ = og.power_series(s)
+            chk = _check(torch_cuda, res, exact, eps, k=50, source=s)
+            assert chk.ok, (s, eps, chk.detail)
+    dg.free()
+
+
+@pytest.mark.parametrize("beta", [0.0, 1.0])
+def test_pure_structure_and_pure_attribute_walks(torch_cuda, ahpp, tiny_graph, beta):
+    og = O.OracleGraph.from_graph(tiny_graph)
+    _say("load tiny beta", beta)
+    dg = ahpp.load_graph(tiny_graph, beta=beta)
+    for s in (3, 1000):
+        res = ahpp.ahpp_query(dg, s, 1e-6, k=10, want_resid=True)
+        exact, _ = og.power_series(s, beta=beta)
+        chk = _check(torch_cuda, res, exact, 1e-6, k=10, source=s)
+        assert chk.ok, chk.detail
+    dg.free()
+
+
+def test_topk_exact_on_given_vector(torch_cuda, ahpp, tiny):
+    torch = torch_cuda
+    rng = np.random.default_rng(7)
+    n = tiny.n_u
+    for trial in range(4):
+        v = (rng.integers(0, 9, size=n) / 7.0).astype(np.float32)  # many ties and zeros
+        if trial == 3:
+            v[:] = 0
+            v[[5, 9, 700]] = [0.5, 0.5, 0.25]
+        t = torch.from_numpy(v).cuda()
+        for k, ex in ((1, -1), (20, 5), (333, 17), (2048, -1)):
+            _say("topk trial", trial, k, ex)
+            ti, tv, tn = ahpp.ahpp_topk(tiny, t, k, ex)
+            torch.cuda.synchronize()
+            ids, vals = O.topk(v.astype(np.float64), k, ex)
+            m = int(tn.item())
+            assert m == len(ids)
+            assert ti[:m].cpu().numpy().tolist() == ids.tolist()
+            assert np.array_equal(tv[:m].cpu().numpy(), vals.astype(np.float32))
+
+
+def test_batch_equals_alone(torch_cuda, ahpp, tiny, tiny_Pi, tiny_graph):
+    srcs = synth.mixed_batch_queries(tiny_graph, 24, 2002)
+    eps = np.array([1e-4, 1e-6, 1e-5, 1e-7] * 6)
+    _say("batch of", len(srcs))
+    res = ahpp.ahpp_query_batch(tiny, srcs, eps, k=20)
+    pis = res.pi.cpu().numpy()
+    for q, s in enumerate(srcs.tolist()):
+        chk = O.check_query(tiny_Pi[s], pis[q].astype(np.float64), eps[q], tol=TOL, k=20, source=s,
+                            topk_ids=res.topk_idx[q, : int(res.topk_n[q].item())].cpu().numpy())
+        assert chk.ok, (q, s, chk.detail)
+        alone = ahpp.ahpp_query(tiny, s, float(eps[q]))
+        assert np.abs(alone.pi.cpu().numpy() - pis[q]).max() <= eps[q] + TOL
+
+
+def test_edge_cases(torch_cuda, ahpp):
+    # A U node with no edge and no attribute (dangling), an attribute-only node,
+    # a graph with no V side at all, and eps so large nothing is pushed.
+    edges = [(0, 0), (1, 0), (1, 1), (2, 1)]
+    assoc = [(0, 0), (1, 0), (3, 1), (2, 1)]
+    import types
+    e = np.array(edges, dtype=np.int32)
+    a = np.array(assoc, dtype=np.int32)
+    g = types.SimpleNamespace(n_u=5, n_v=2, n_attr=2, edge_u=e[:, 0], edge_v=e[:, 1],
+                              edge_w=np.array([1, 2, 0.5, 1], np.float32), assoc_u=a[:, 0], assoc_a=a[:, 1],
+                              assoc_w=np.array([1, 1, 3, 0.25], np.float32))
+    og = O.OracleGraph.from_graph(g)
+    _say("edge-case graph")
+    dg = ahpp.load_graph(g)
+    assert dg.info["dangling_u"] == 2  # node 3 (no edge) and node 4 (nothing)
+    Pi = O.exact_dense(g)
+    for s in range(5):
+        res = ahpp.ahpp_query(dg, s, 1e-7, k=3, want_resid=True)
+        chk = _check(torch_cuda, res, Pi[s], 1e-7, k=3, source=s, resid=False)
+        assert chk.ok, (s, chk.detail)
+    # eps >= lambda: the stop rule holds before any push, pi_hat = 0.
+    res = ahpp.ahpp_query(dg, 0, 10.0 * dg.lam, k=2)
+    assert float(res.pi.abs().max()) == 0.0 and int(res.topk_n.item()) == 0
+    assert res.stats[0]["iters"] == 0
+    dg.free()
+    # Attributes only (no edges).
+    g2 = types.SimpleNamespace(n_u=4, n_v=0, n_attr=2, edge_u=np.zeros(0, np.int32), edge_v=np.zeros(0, np.int32),
+                               edge_w=None, assoc_u=np.array([0, 1, 2, 3, 0], np.int32),
+                               assoc_a=np.array([0, 0, 1, 1, 1], np.int32), assoc_w=None)
+    dg2 = ahpp.load_graph(g2, beta=1.0)
+    Pi2 = O.exact_dense(g2, beta=1.0)
+    for s in range(4):
+        res = ahpp.ahpp_query(dg2, s, 1e-7, want_resid=True)
+        chk = _check(torch_cuda, res, Pi2[s], 1e-7)
+        assert chk.ok, chk.detail
+    dg2.free()
+
+
+def test_errors(torch_cuda, ahpp, tiny, tiny_graph):
+    with pytest.raises(ahpp.AhppError) as e:
+        ahpp.ahpp_query(tiny, tiny.n_u, 1e-6)
+    assert e.value.status == ahpp.ERR_INVALID_ARG
+    with pytest.raises(ahpp.AhppError):
+        ahpp.ahpp_query(tiny, 0, 0.0)
+    with pytest.raises(ahpp.AhppError):
+        ahpp.ahpp_query(tiny, 0, 1e-6, k=5000)
+    with pytest.raises(ahpp.AhppError) as e:
+        ahpp.ahpp_query(tiny, 0, 1e-6, max_iters=1)
+    assert e.value.status == ahpp.ERR_NOT_CONVERGED
+    res = ahpp.ahpp_query(tiny, 0, 1e-6, max_iters=1, allow_not_converged=True)
+    assert res.stats[0]["iters"] == 1 and res.stats[0]["converged"] == 0
+    bad_v = tiny_graph.edge_v.copy()
+    bad_v[3] = tiny_graph.n_v
+    with pytest.raises(ahpp.AhppError) as e:
+        ahpp.ahpp_graph_load(tiny_graph.n_u, tiny_graph.n_v, tiny_graph.n_attr, tiny_graph.edge_u, bad_v,
+                             tiny_graph.edge_w, tiny_graph.assoc_u, tiny_graph.assoc_a, tiny_graph.assoc_w)
+    assert e.value.status == ahpp.ERR_INVALID_ARG and "edge id" in str(e.value)
+    bad_w = tiny_graph.assoc_w.copy()
+    bad_w[0] = 0.0
+    with pytest.raises(ahpp.AhppError):
+        ahpp.ahpp_graph_load(tiny_graph.n_u, tiny_graph.n_v, tiny_graph.n_attr, tiny_graph.edge_u, tiny_graph.edge_v,
+                             tiny_graph.edge_w, tiny_graph.assoc_u, tiny_graph.assoc_a, bad_w)

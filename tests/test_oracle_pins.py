@@ -376,3 +376,13 @@ def test_planted_mistakes_fail_a_pin():
     Pa = O.dense_P(ga)
     pi_bad = (1 - O.ALPHA) * np.linalg.inv(np.eye(4) - O.ALPHA * Pa)[0]
     assert abs(pi_bad[0] - 0.3625) > 1e-3
+
+
+def test_missing_weights_mean_unit_weights():
+    """A weight array left out stands for weight 1 everywhere (C and dense forms)."""
+    g = complete_bipartite(3, 2, private_attr=False)
+    g0 = types.SimpleNamespace(**{**vars(g), "edge_w": None, "assoc_w": None})
+    assert np.array_equal(O.dense_P(g), O.dense_P(g0))
+    a, _ = O.OracleGraph.from_graph(g).power_series(1)
+    b, _ = O.OracleGraph.from_graph(g0).power_series(1)
+    assert np.array_equal(a, b)
