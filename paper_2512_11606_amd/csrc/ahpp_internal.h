@@ -12,19 +12,30 @@ namespace ahpp {
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kBlock = 256;          // threads per workgroup (4 waves)
 constexpr int kItemEdges = 512;      // CSR entries handled by one wave item
-constexpr int kShortRow = 32;        // rows up to this length are packed together
+constexpr int kPerLane = kItemEdges / kWave;
+constexpr int kShortRow = 64;        // rows up to this length are packed together
 constexpr int kMaxRowsPerItem = 256; // rows per packed item
 constexpr int kMaxTopK = 2048;       // largest k the device top-k sorts in LDS
+constexpr int kBlocksPerCu = 8;      // workgroups per CU of the gather kernels
 
 // One unit of SpMV work for one wave.
 //   n > 0 : rows [row, row + n), each at most kShortRow entries, together at
 //           most kItemEdges entries ("packed" item, reduced one row per lane);
 //   n <= 0: chunk -n of row `row` (entries [off[row] + (-n) * kItemEdges, ...)),
-//           reduced by the whole wave.  Rows with more than kItemEdges entries
-//           have several chunks whose partial sums meet through atomics.
+//           reduced by the whole wave.  A row with more than kItemEdges
+//           entries has several chunks; each writes its partial sum to the
+//           item's slot and a fix-up pass adds the slots in chunk order.
 struct WorkItem {
     int32_t row;
     int32_t n;
+};
+
+// A row cut into nch chunks whose items are [first_item, first_item + nch).
+struct SplitRow {
+    int32_t row;
+    int32_t first_item;
+    int32_t nch;
+    int32_t pad;
 };
 
 // A CSR matrix in device memory plus its wave schedule.
@@ -35,14 +46,13 @@ struct DevCsr {
     float *w = nullptr;             // nnz (nullptr when every weight is 1)
     WorkItem *items = nullptr;      // n_items
     int64_t n_items = 0;
-    int32_t *split_rows = nullptr;  // rows cut into several chunks
+    SplitRow *split = nullptr;      // rows cut into several chunks
     int64_t n_split = 0;
-    uint32_t *split_cnt = nullptr;  // n_rows arrival counters (zero between uses)
     int32_t max_row_len = 0;
 };
 
 // Per-query control block, resident in device memory.  Written only by the
-// last workgroup of the U-side kernel of each round; read by every kernel.
+// control kernel at the end of each round; read by every kernel.
 struct Control {
     float theta;          // push threshold of the current round
     float eps_f;          // eps / lambda
@@ -52,8 +62,6 @@ struct Control {
     int32_t switch_iter;  // round after which phase 2 began, -1 if never
     int32_t status;       // 0 running, 1 converged, 2 round cap reached
     int32_t max_iters;
-    uint32_t max_bits;    // float bits of this round's max residue (atomicMax)
-    uint32_t blocks_done; // arrival counter of the U-side kernel
     unsigned long long n_p;  // edge visits (Algorithm 4's n_p, every phase)
     float last_max;       // max_i r(u, u_i) after the last completed round
     float pad0;
@@ -69,6 +77,8 @@ struct Rule {
 // Graph held by a handle.
 struct Graph {
     int device = 0;
+    int n_cu = 256;
+    int grid_cap = 2048;            // workgroups of the gather kernels
     int64_t n_u = 0, n_v = 0, n_a = 0, m_e = 0, m_a = 0;
     double alpha = 0.15, beta = 0.35, lambda = 1.0;
     int32_t lambda_iters = 0;
@@ -81,9 +91,12 @@ struct Graph {
     int64_t dangling_u = 0;
     int64_t device_bytes = 0;
     double load_ms = 0, lambda_ms = 0;
-    // Scratch of the single-query engine (allocated on first use).
+    // Single-query state (allocated at load).
     float *q_r = nullptr, *q_pi = nullptr, *q_rho = nullptr, *q_z = nullptr;
     Control *q_ctl = nullptr;
+    float *part_item = nullptr;            // chunk partial sums, max(n_items) slots
+    float *blk_max = nullptr;              // per-workgroup maxima, 2 * grid_cap
+    unsigned long long *blk_np = nullptr;  // per-workgroup n_p partials, 3 * grid_cap
     // Top-k scratch.
     void *tk_scratch = nullptr;
     size_t tk_scratch_bytes = 0;
@@ -108,6 +121,7 @@ void free_graph(Graph &g);
 
 // push.hip
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
+void alloc_query_state(Graph &g);
 void single_query_init(Graph &g, int32_t source, float eps_f, int32_t max_iters, hipStream_t s);
 void single_query_round(Graph &g, hipStream_t s);
 void single_query_stats(Graph &g, double *sum_r, hipStream_t s);

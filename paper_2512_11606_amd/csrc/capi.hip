@@ -41,15 +41,6 @@ struct DeviceScope {
     }
 };
 
-void ensure_query_scratch(Graph &g) {
-    if (g.q_r) return;
-    g.q_r = (float *)dev_alloc(g, (size_t)std::max<int64_t>(g.n_u, 1) * 4, "query residues");
-    g.q_pi = (float *)dev_alloc(g, (size_t)std::max<int64_t>(g.n_u, 1) * 4, "query reserves");
-    g.q_rho = (float *)dev_alloc(g, (size_t)std::max<int64_t>(2 * g.n_u, 1) * 4, "query push buffer");
-    g.q_z = (float *)dev_alloc(g, (size_t)std::max<int64_t>(g.n_v + g.n_a, 1) * 4, "query V/attribute residues");
-    g.q_ctl = (Control *)dev_alloc(g, sizeof(Control), "query control");
-}
-
 void ensure_topk_scratch(Graph &g, int64_t n_q) {
     size_t need = topk_scratch_bytes(n_q);
     if (g.tk_scratch_bytes >= need) return;
@@ -144,8 +135,12 @@ ahpp_status_t ahpp_graph_load(const ahpp_graph_desc_t *d, ahpp_graph_t **out) {
     try {
         DeviceScope scope(g.device);
         check_hip(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "stream");
+        int n_cu = 0;
+        check_hip(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, g.device), "device attributes");
+        g.n_cu = n_cu > 0 ? n_cu : 1;
+        g.grid_cap = g.n_cu * kBlocksPerCu;
         build_graph(g, d->edge_u, d->edge_v, d->edge_w, d->assoc_u, d->assoc_a, d->assoc_w, s);
-        ensure_query_scratch(g);
+        alloc_query_state(g);
         ensure_topk_scratch(g, 1);
         if (d->lambda > 0) {
             g.lambda = d->lambda;

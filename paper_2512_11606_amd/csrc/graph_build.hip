@@ -193,28 +193,47 @@ __global__ void k_offsets(const uint32_t *key, int64_t n, int64_t n_rows, int64_
     }
 }
 
-// Row sums of fwd: d(u) over columns < n_v, s(u) over the rest.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Row sums of fwd in double precision, one wave per row: d(u) over columns
+// < n_v (Eq. 1 denominator), s(u) over the attribute columns (Eq. 2).
 __global__ void k_fwd_coeffs(const int64_t *off, const int32_t *col, const float *w, int64_t n_u, int64_t n_v,
                              float alpha, float beta, float *c_d, float *c_s, unsigned long long *dangling) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     unsigned long long dang = 0;
-    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n_u; u += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t u = wave0; u < n_u; u += n_waves) {
         double d = 0.0, s = 0.0;
-        for (int64_t p = off[u]; p < off[u + 1]; ++p) {
+        for (int64_t p = off[u] + lane; p < off[u + 1]; p += 64) {
             double x = w ? (double)w[p] : 1.0;
             if (col[p] < n_v) d += x; else s += x;
         }
-        c_d[u] = d > 0 ? (float)((1.0 - beta) * (1.0 - alpha) / d) : 0.0f;
-        c_s[u] = s > 0 ? (float)(beta * (1.0 - alpha) / s) : 0.0f;
-        if (!(d > 0) || !(s > 0)) dang += 1;
+        d = wave_sum_f64(d);
+        s = wave_sum_f64(s);
+        if (lane == 0) {
+            c_d[u] = d > 0 ? (float)((1.0 - beta) * (1.0 - alpha) / d) : 0.0f;
+            c_s[u] = s > 0 ? (float)(beta * (1.0 - alpha) / s) : 0.0f;
+            if (!(d > 0) || !(s > 0)) dang += 1;
+        }
     }
     if (dang) atomicAdd(dangling, dang);
 }
 
+// 1/d(v) for V rows and 1/t(a) for attribute rows, one wave per row.
 __global__ void k_back_coeffs(const int64_t *off, const float *w, int64_t n_rows, float *inv_b) {
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n_rows; r += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t r = wave0; r < n_rows; r += n_waves) {
         double d = 0.0;
-        for (int64_t p = off[r]; p < off[r + 1]; ++p) d += w ? (double)w[p] : 1.0;
-        inv_b[r] = d > 0 ? (float)(1.0 / d) : 0.0f;
+        for (int64_t p = off[r] + lane; p < off[r + 1]; p += 64) d += w ? (double)w[p] : 1.0;
+        d = wave_sum_f64(d);
+        if (lane == 0) inv_b[r] = d > 0 ? (float)(1.0 / d) : 0.0f;
     }
 }
 
@@ -231,7 +250,7 @@ int bits_for(int64_t n) {
 }
 
 // Builds the wave schedule of a CSR from its host copy of the offsets.
-void build_items(const std::vector<int64_t> &off, std::vector<WorkItem> &items, std::vector<int32_t> &split,
+void build_items(const std::vector<int64_t> &off, std::vector<WorkItem> &items, std::vector<SplitRow> &split,
                  int32_t &max_len) {
     const int64_t n_rows = (int64_t)off.size() - 1;
     items.clear();
@@ -243,7 +262,7 @@ void build_items(const std::vector<int64_t> &off, std::vector<WorkItem> &items, 
         max_len = (int32_t)std::max<int64_t>(max_len, len);
         if (len > kShortRow) {
             int64_t chunks = (len + kItemEdges - 1) / kItemEdges;
-            if (chunks > 1) split.push_back((int32_t)r);
+            if (chunks > 1) split.push_back(SplitRow{(int32_t)r, (int32_t)items.size(), (int32_t)chunks, 0});
             for (int64_t c = 0; c < chunks; ++c) items.push_back(WorkItem{(int32_t)r, (int32_t)(-c)});
             ++r;
             continue;
@@ -312,21 +331,19 @@ void build_csr(Graph &g, DevCsr &c, int64_t n_rows, uint32_t *key, int32_t *col,
     check_hip(hipMemcpyAsync(off.data(), c.off, off.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s), "offsets D2H");
     check_hip(hipStreamSynchronize(s), "offsets D2H");
     std::vector<WorkItem> items;
-    std::vector<int32_t> split;
+    std::vector<SplitRow> split;
     build_items(off, items, split, c.max_row_len);
+    if ((int64_t)items.size() > (int64_t)INT32_MAX) throw Failure{-1, "ahpp_graph_load: schedule exceeds int32 items"};
     c.n_items = (int64_t)items.size();
     c.n_split = (int64_t)split.size();
     c.items = (WorkItem *)dev_alloc(g, std::max<size_t>(items.size(), 1) * sizeof(WorkItem), "schedule");
-    c.split_rows = (int32_t *)dev_alloc(g, std::max<size_t>(split.size(), 1) * sizeof(int32_t), "split rows");
-    c.split_cnt = (uint32_t *)dev_alloc(g, (size_t)std::max<int64_t>(n_rows, 1) * sizeof(uint32_t), "split counters");
+    c.split = (SplitRow *)dev_alloc(g, std::max<size_t>(split.size(), 1) * sizeof(SplitRow), "split rows");
     if (!items.empty())
         check_hip(hipMemcpyAsync(c.items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s),
                   "schedule H2D");
     if (!split.empty())
-        check_hip(hipMemcpyAsync(c.split_rows, split.data(), split.size() * sizeof(int32_t), hipMemcpyHostToDevice, s),
+        check_hip(hipMemcpyAsync(c.split, split.data(), split.size() * sizeof(SplitRow), hipMemcpyHostToDevice, s),
                   "split H2D");
-    check_hip(hipMemsetAsync(c.split_cnt, 0, (size_t)std::max<int64_t>(n_rows, 1) * sizeof(uint32_t), s),
-              "split counters");
     check_hip(hipStreamSynchronize(s), "schedule upload");
 }
 
@@ -415,10 +432,10 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
     check_hip(hipMalloc(&d_dang, 8), "dangling");
     check_hip(hipMemsetAsync(d_dang, 0, 8, s), "dangling");
     if (g.n_u > 0)
-        hipLaunchKernelGGL(k_fwd_coeffs, dim3(grid_for(g.n_u)), dim3(kBlock), 0, s, g.fwd.off, g.fwd.col, g.fwd.w,
+        hipLaunchKernelGGL(k_fwd_coeffs, dim3(grid_for(g.n_u * 64)), dim3(kBlock), 0, s, g.fwd.off, g.fwd.col, g.fwd.w,
                            g.n_u, g.n_v, (float)g.alpha, (float)g.beta, g.c_d, g.c_s, d_dang);
     if (g.n_v + g.n_a > 0)
-        hipLaunchKernelGGL(k_back_coeffs, dim3(grid_for(g.n_v + g.n_a)), dim3(kBlock), 0, s, g.back.off, g.back.w,
+        hipLaunchKernelGGL(k_back_coeffs, dim3(grid_for((g.n_v + g.n_a) * 64)), dim3(kBlock), 0, s, g.back.off, g.back.w,
                            g.n_v + g.n_a, g.inv_b);
     check_hip(hipGetLastError(), "coefficient launch");
     unsigned long long dang = 0;
@@ -430,7 +447,7 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
 }
 
 static void free_csr(DevCsr &c) {
-    dfree(c.off); dfree(c.col); dfree(c.w); dfree(c.items); dfree(c.split_rows); dfree(c.split_cnt);
+    dfree(c.off); dfree(c.col); dfree(c.w); dfree(c.items); dfree(c.split);
     c = DevCsr{};
 }
 
@@ -439,6 +456,10 @@ void free_graph(Graph &g) {
     free_csr(g.back);
     dfree(g.c_d); dfree(g.c_s); dfree(g.inv_b);
     dfree(g.q_r); dfree(g.q_pi); dfree(g.q_rho); dfree(g.q_z); dfree(g.q_ctl);
+    dfree(g.part_item); dfree(g.blk_max); dfree(g.blk_np);
+    g.part_item = nullptr;
+    g.blk_max = nullptr;
+    g.blk_np = nullptr;
     dfree(g.tk_scratch);
     g.c_d = g.c_s = g.inv_b = nullptr;
     g.q_r = g.q_pi = g.q_rho = g.q_z = nullptr;
