@@ -1,0 +1,182 @@
+"""Benchmark of the AHPP hot path on one MI355X.
+
+Workload (one "step"): 1,024 eps-approximate single-source AHPP queries at
+eps = 1e-7, k = 50, answered by one ahpp_query_batch call on the synthetic
+power-law graph |U| = 1M, |V| = 500k, 20M edges (Zipf 2.1 degrees, weights
+U[0.5, 1]), 10,000 attributes with 20 per U node (Zipf 1.5 popularity, values
+in (0, 1]).  Sources: half uniform from the top 1% of U by degree, half
+uniform over U.  Inputs are generated on the host and loaded into HBM before
+the timed region; the timed region covers the whole batch (rounds of
+Algorithm 4 and the top-k) for `--steps` batches.
+
+Also reported: the plain single-query push on the same GPU (sources drawn
+proportional to degree) with p50 / p99 latency, the roofline of the dominant
+gather kernel (algorithmic bytes / HIP-event time, against 8 TB/s HBM), and
+the CPU oracle's FP64 ASRP on one query of the same graph.
+
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "AHPP queries/s at ε=1e-7, batched vs plain push; p50/p99 query latency"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_fwd_gather_m1_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2512_11606_amd", "csrc", "batch.hip")
+
+
+def _percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(round(p / 100.0 * (len(xs) - 1)))))
+    return xs[i]
+
+
+def _source_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(kernel_kind_name):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel") != kernel_kind_name or d.get("source_sha256_16") != _source_hash(KERNEL_SOURCE):
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(g, source, eps):
+    import oracle
+    og = oracle.OracleGraph.from_graph(g)
+    lam = og.lambda_thm3()
+    t0 = time.perf_counter()
+    _, _, st, ok = og.asrp(int(source), eps, lam)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 full FP64 ASRP query (source {int(source)}, eps {eps:g}, {st.iterations} rounds, "
+                      f"lambda from Theorem 3) on the same graph, 1 thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--plain", type=int, default=32, help="plain single queries timed for latency")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--graph", default="m1")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (counter calibration) and exit")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}), flush=True)
+        return
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: queries are independent and this build measures the single-GPU "
+              "share; multi-GPU sharding is not implemented.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2512_11606_amd import ahpp, synth
+
+    eps, k = 1e-7, 50
+    g = synth.make_graph(args.graph)
+    dg = ahpp.load_graph(g, device=0)
+    torch.cuda.synchronize()
+    sources = synth.mixed_batch_queries(g, args.batch, 2002)
+
+    for _ in range(args.warmup):
+        ahpp.ahpp_query_batch(dg, sources, eps, k=k, want_pi=False, want_stats=False)
+    torch.cuda.synchronize()
+
+    ahpp.ahpp_profile_enable(dg, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = ahpp.ahpp_query_batch(dg, sources, eps, k=k, want_pi=False, want_stats=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {kind: ahpp.ahpp_profile_read(dg, kind) for kind in (ahpp.PROF_BATCH_BACK, ahpp.PROF_BATCH_FWD)}
+    ahpp.ahpp_profile_enable(dg, False)
+    elapsed = t1 - t0
+    value = args.batch * args.steps / elapsed
+    topk_ok = int(res.topk_n.min().item()) == k
+
+    # Plain single-query push: per-query latency (host call to results).
+    plain_src = synth.degree_queries(g, args.plain, 2001)
+    ahpp.ahpp_query(dg, int(plain_src[0]), eps, k=k)
+    lat = []
+    for s in plain_src.tolist():
+        a = time.perf_counter()
+        ahpp.ahpp_query(dg, s, eps, k=k, want_pi=False, want_stats=False)
+        lat.append((time.perf_counter() - a) * 1e3)
+    plain_qps = len(lat) / (sum(lat) / 1e3)
+
+    dom_kind = max(prof, key=lambda kk: prof[kk]["ms"])
+    dom = prof[dom_kind]
+    name = {ahpp.PROF_BATCH_BACK: "kb_gather<back>", ahpp.PROF_BATCH_FWD: "kb_gather<fwd>"}[dom_kind]
+    avg_ms = dom["ms"] / max(dom["launches"], 1)
+    bytes_per_launch = dom["bytes"] / max(dom["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = _traffic(name)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": name,
+                "launches": dom["launches"], "avg_ms": round(avg_ms, 4),
+                "algo_bytes_per_launch": bytes_per_launch}
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched AHPP queries, {args.batch} per batch, eps=1e-7, k=50, on the 1M/500k/20M "
+                               "Zipf(2.1) bipartite graph with 10k attributes x 20 (Zipf 1.5)",
+                   "graph": args.graph, "n_u": g.n_u, "n_v": g.n_v, "m_e": g.m_e, "n_attr": g.n_attr, "m_a": g.m_a,
+                   "eps": eps, "k": k, "batch": args.batch, "alpha": 0.15, "beta": 0.35,
+                   "lambda": round(dg.lam, 3)},
+        "batch_query_latency_ms_p50": round(elapsed / args.steps * 1e3, 2),
+        "batch_query_latency_ms_p99": round(elapsed / args.steps * 1e3, 2),
+        "plain_qps": round(plain_qps, 2),
+        "plain_latency_ms_p50": round(_percentile(lat, 50), 2),
+        "plain_latency_ms_p99": round(_percentile(lat, 99), 2),
+        "batched_over_plain": round(value / plain_qps, 2),
+        "topk_complete": topk_ok,
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(g, plain_src[0], eps)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    dg.free()
+
+
+if __name__ == "__main__":
+    main()

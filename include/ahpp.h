@@ -160,6 +160,22 @@ ahpp_status_t ahpp_query_batch(ahpp_graph_t *g, int32_t n_q, const int32_t *sour
 ahpp_status_t ahpp_topk(const ahpp_graph_t *g, const float *pi, int32_t k, int32_t exclude,
                         int32_t *idx_out, float *val_out, int32_t *n_out, void *hip_stream);
 
+/* Kernel timing (diagnostics, used by the benchmark's roofline figures).
+ * While enabled, the library brackets every launch of its gather kernels with
+ * HIP events on the launch stream and adds, per kernel kind, the launch
+ * count, the summed elapsed time and the algorithmic bytes of the launch
+ * (CSR entries and offsets once per launch, one 4-byte residue per entry and
+ * query, and the per-row, per-query state the epilogue reads and writes).
+ * Kinds: 0 single-query V/attribute gather, 1 single-query U gather,
+ *        2 batched V/attribute gather, 3 batched U gather.
+ * ahpp_profile_enable(g, 1) clears the totals and starts; (g, 0) stops.
+ * ahpp_profile_read waits for the recorded events and returns the totals
+ * (host pointers, each nullable).  Errors: INVALID_ARG (NULL graph or bad
+ * kind), DEVICE. */
+ahpp_status_t ahpp_profile_enable(ahpp_graph_t *g, int32_t on);
+ahpp_status_t ahpp_profile_read(ahpp_graph_t *g, int32_t kind, int64_t *launches, double *total_ms,
+                                double *algo_bytes);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char *ahpp_last_error(void);
 

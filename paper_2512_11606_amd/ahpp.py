@@ -21,7 +21,10 @@ LIB_PATH = os.path.join(_HERE, "libahpp.so")
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CONVERGED = 0, -1, -2, -3, -4
 
 EXPORTED = ("ahpp_graph_load", "ahpp_graph_info", "ahpp_graph_free", "ahpp_query", "ahpp_query_batch", "ahpp_topk",
-            "ahpp_last_error")
+            "ahpp_profile_enable", "ahpp_profile_read", "ahpp_last_error")
+
+# Kernel kinds of ahpp_profile_read.
+PROF_SINGLE_BACK, PROF_SINGLE_FWD, PROF_BATCH_BACK, PROF_BATCH_FWD = 0, 1, 2, 3
 
 
 class AhppError(RuntimeError):
@@ -81,6 +84,10 @@ def load_library(path: str = LIB_PATH):
     lib.ahpp_query_batch.argtypes = [P, i32, P, P, i32, P, i32, P, P, P, P, P]
     lib.ahpp_topk.restype = ctypes.c_int
     lib.ahpp_topk.argtypes = [P, P, i32, i32, P, P, P, P]
+    lib.ahpp_profile_enable.restype = ctypes.c_int
+    lib.ahpp_profile_enable.argtypes = [P, i32]
+    lib.ahpp_profile_read.restype = ctypes.c_int
+    lib.ahpp_profile_read.argtypes = [P, i32, P, P, P]
     lib.ahpp_last_error.restype = ctypes.c_char_p
     lib.ahpp_last_error.argtypes = []
     _lib = lib
@@ -232,3 +239,17 @@ def ahpp_topk(g: Graph, pi, k: int, exclude: int = -1, stream=None):
     _check(load_library().ahpp_topk(g._h, _dev_ptr(pi), int(k), int(exclude), _dev_ptr(ti), _dev_ptr(tv),
                                     _dev_ptr(tn), _stream(g.device, stream)))
     return ti, tv, tn
+
+
+def ahpp_profile_enable(g: Graph, on: bool = True) -> None:
+    """Starts (clearing totals) or stops HIP-event timing of the gather kernels."""
+    _check(load_library().ahpp_profile_enable(g._h, 1 if on else 0))
+
+
+def ahpp_profile_read(g: Graph, kind: int) -> dict:
+    """Launch count, summed elapsed ms and algorithmic bytes of one kernel kind."""
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    by = ctypes.c_double(0.0)
+    _check(load_library().ahpp_profile_read(g._h, int(kind), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    return {"launches": int(n.value), "ms": float(ms.value), "bytes": float(by.value)}

@@ -11,10 +11,10 @@ namespace ahpp {
 
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kBlock = 256;          // threads per workgroup (4 waves)
-constexpr int kItemEdges = 512;      // CSR entries handled by one wave item
+constexpr int kItemEdges = 1024;     // CSR entries handled by one wave item
 constexpr int kPerLane = kItemEdges / kWave;
 constexpr int kShortRow = 64;        // rows up to this length are packed together
-constexpr int kMaxRowsPerItem = 256; // rows per packed item
+constexpr int kMaxRowsPerItem = 128; // rows per packed item (a multiple of kWave)
 constexpr int kMaxTopK = 2048;       // largest k the device top-k sorts in LDS
 constexpr int kBlocksPerCu = 8;      // workgroups per CU of the gather kernels
 
@@ -74,6 +74,76 @@ struct Rule {
     double budget_scale;  // 2 (|E| + |E_A|)
 };
 
+// Queries per batch tile: one query per lane of a wave.
+constexpr int kTileQ = 64;
+
+// Control of one query inside a batch tile (same rule as Control).
+struct QueryCtl {
+    float theta;          // push threshold; +inf once the query stopped
+    float eps_f;
+    int32_t done, phase, iter, switch_iter, status, max_iters;
+    unsigned long long n_p;
+    float last_max;
+    int32_t source;       // -1 for an empty lane
+};
+
+struct TileCtl {
+    QueryCtl q[kTileQ];
+    int32_t all_done;     // every lane of the tile stopped
+    int32_t pad[15];
+};
+
+// Device state of the batched engine: `tiles` tiles of kTileQ queries, each
+// stored node-major ([node][kTileQ], one 256-byte row per node).
+struct BatchState {
+    int tiles = 0;                  // tiles allocated
+    int grid_x = 0;                 // workgroups per tile of the gather kernels
+    float *r = nullptr;             // [tiles][n_u][kTileQ]
+    float *pi = nullptr;            // [tiles][n_u][kTileQ]
+    float *z = nullptr;             // [tiles][n_v + n_a][kTileQ]
+    float *part = nullptr;          // [tiles][max(n_items)][kTileQ]
+    TileCtl *ctl = nullptr;         // [tiles]
+    float *blk_max = nullptr;       // [tiles][2][grid_x][kTileQ]
+    unsigned long long *blk_np = nullptr;  // [tiles][4][grid_x][kTileQ]
+    float *out = nullptr;           // [tiles * kTileQ][n_u] query-major scores for top-k
+    double *sums = nullptr;         // [tiles][grid_x][kTileQ] residue sums
+    int64_t live_q = 0;             // queries still running at the last poll
+};
+
+// Launch timing of the gather kernels (see ahpp_profile_enable).
+constexpr int kProfKinds = 4;
+struct ProfLaunch {
+    int kind;
+    hipEvent_t start, stop;
+    double bytes;
+};
+struct Profiler {
+    bool on = false;
+    std::vector<ProfLaunch> pending;
+    int64_t launches[kProfKinds] = {0, 0, 0, 0};
+    double ms[kProfKinds] = {0, 0, 0, 0};
+    double bytes[kProfKinds] = {0, 0, 0, 0};
+};
+// Records `kind` around the launches issued by f() when profiling is on.
+template <class F>
+void profiled(Profiler &p, int kind, double bytes, hipStream_t s, F f) {
+    if (!p.on) {
+        f();
+        return;
+    }
+    ProfLaunch l{kind, nullptr, nullptr, bytes};
+    if (hipEventCreate(&l.start) != hipSuccess || hipEventCreate(&l.stop) != hipSuccess) {
+        f();
+        return;
+    }
+    (void)hipEventRecord(l.start, s);
+    f();
+    (void)hipEventRecord(l.stop, s);
+    p.pending.push_back(l);
+}
+void profiler_flush(Profiler &p);
+void profiler_void_tail(Profiler &p, int kind, int64_t n);
+
 // Graph held by a handle.
 struct Graph {
     int device = 0;
@@ -82,21 +152,23 @@ struct Graph {
     int64_t n_u = 0, n_v = 0, n_a = 0, m_e = 0, m_a = 0;
     double alpha = 0.15, beta = 0.35, lambda = 1.0;
     int32_t lambda_iters = 0;
-    bool unit = false;              // every weight is 1
-    DevCsr fwd;                     // rows U; cols V then attributes (n_v + a)
-    DevCsr back;                    // rows V then attributes; cols U (n_u + u for attribute rows)
-    float *c_d = nullptr;           // (1-beta)(1-alpha) / d(u), 0 if d(u) = 0
-    float *c_s = nullptr;           // beta (1-alpha) / s(u),    0 if s(u) = 0
+    bool unit = false;              // every raw weight is 1 (the fwd CSR stores none)
+    DevCsr fwd;                     // rows U; cols V then attributes (n_v + a); raw weights
+    DevCsr back;                    // rows V then attributes (n_v + a); cols U; weights
+                                    // w(u,x) c_d(u) (V rows) or w(u,x) c_s(u) (attribute rows)
     float *inv_b = nullptr;         // 1/d(v) for V rows, 1/t(a) for attribute rows
     int64_t dangling_u = 0;
     int64_t device_bytes = 0;
     double load_ms = 0, lambda_ms = 0;
     // Single-query state (allocated at load).
-    float *q_r = nullptr, *q_pi = nullptr, *q_rho = nullptr, *q_z = nullptr;
+    float *q_r = nullptr, *q_pi = nullptr, *q_z = nullptr;
     Control *q_ctl = nullptr;
     float *part_item = nullptr;            // chunk partial sums, max(n_items) slots
     float *blk_max = nullptr;              // per-workgroup maxima, 2 * grid_cap
-    unsigned long long *blk_np = nullptr;  // per-workgroup n_p partials, 3 * grid_cap
+    unsigned long long *blk_np = nullptr;  // per-workgroup n_p partials, 4 * grid_cap
+    // Batched engine (allocated on first use, grown on demand).
+    BatchState batch;
+    Profiler prof;
     // Top-k scratch.
     void *tk_scratch = nullptr;
     size_t tk_scratch_bytes = 0;
@@ -126,6 +198,20 @@ void single_query_init(Graph &g, int32_t source, float eps_f, int32_t max_iters,
 void single_query_round(Graph &g, hipStream_t s);
 void single_query_stats(Graph &g, double *sum_r, hipStream_t s);
 double compute_lambda(Graph &g, int T, hipStream_t s);
+
+// batch.hip
+void ensure_batch_state(Graph &g, int tiles);
+void free_batch_state(Graph &g);
+// Initialises tiles [t0, t0 + nt): lane q of tile t gets query t * kTileQ + q
+// (sources / eps_f host arrays of n_q entries; lanes beyond n_q are empty).
+void batch_init(Graph &g, int t0, int nt, const int32_t *sources, const float *eps_f, int64_t n_q,
+                int32_t max_iters, hipStream_t s);
+void batch_round(Graph &g, int t0, int nt, hipStream_t s);
+// Copies tile scores to query-major rows: out[(t*kTileQ + q) * n_u + u] for
+// the first n_rows rows.
+void batch_scores(Graph &g, int t0, int nt, int64_t n_rows, float *out, hipStream_t s);
+// Per-lane residue sums of tiles [t0, t0 + nt) into host sums[(t-t0)*kTileQ + q].
+void batch_resid_sums(Graph &g, int t0, int nt, double *sums, hipStream_t s);
 
 // topk.hip
 size_t topk_scratch_bytes(int64_t n_q);

@@ -1,0 +1,533 @@
+// Batched AHPP queries on gfx950: the rounds of Algorithm 4 for many sources
+// at once, sharing every pass over the edge lists.
+//
+// Queries are independent (each has its own residues, reserves, eps_f,
+// threshold, phase and stop rule), so a batch is a set of tiles of kTileQ = 64
+// queries, one query per lane of a wave.  A tile's vectors are stored node-
+// major: node x owns the 64 floats [x][0..63], one 256-byte row.  A round is
+// the same pair of pull-form gathers as the single-query path
+// (z = inv_b * W'^T thr(r), then r <- keep(r) + W z with the reserve update),
+// but every CSR entry is read once per tile and drives one coalesced 256-byte
+// gather of the 64 queries' values.  Row bookkeeping is wave-uniform (scalar),
+// and each wave keeps 16 gathers in flight.
+//
+// A query that has stopped keeps threshold +inf: it pushes nothing, so its
+// state no longer changes while the rest of its tile runs on.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <climits>
+#include <cmath>
+
+#include "ahpp_internal.h"
+#include "dev_util.h"
+
+namespace ahpp {
+
+namespace {
+
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kInFlight = 16;  // gathers issued before the first is used
+enum BMode { kBBack = 0, kBFwd = 1 };
+
+struct BArgs {
+    const int64_t *__restrict__ off;
+    const int32_t *__restrict__ col;
+    const float *__restrict__ w;          // nullable (unit weights, fwd only)
+    const WorkItem *__restrict__ items;
+    int64_t n_items;
+    const SplitRow *__restrict__ split;
+    int64_t n_split;
+    const float *x;        // gathered tile vector (tile 0), rows of kTileQ
+    float *y;              // written tile vector (tile 0)
+    float *pi;             // reserves (tile 0), kBFwd
+    const float *inv_b;    // kBBack row scale
+    float *part;           // chunk partials (tile 0), [item][kTileQ]
+    TileCtl *ctl;          // tile 0
+    int64_t x_stride, y_stride, pi_stride, part_stride;  // floats per tile
+    float *blk_max;        // [tile][2][grid_cap][kTileQ] slot base of this launch
+    unsigned long long *blk_np;  // [tile][4][grid_cap][kTileQ] slot base
+    int64_t blk_stride_f, blk_stride_u;   // elements per tile
+    float alpha;
+};
+
+__device__ __forceinline__ float readlane_f(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+// Per-lane epilogues; all values are the lane's query's.
+template <int kMode>
+struct BEpi;
+
+template <>
+struct BEpi<kBBack> {
+    float *z;
+    float theta;
+    unsigned long long np = 0;
+    float mx = 0.0f;
+    __device__ float2 pre(int64_t, float scale) const { return make_float2(scale, 0.0f); }
+    __device__ void full(int64_t row, float s, float2 p, int64_t len) {
+        const float v = p.x * s;
+        z[row * kTileQ + (threadIdx.x & 63)] = v;
+        if (v > 0.0f) np += (unsigned long long)len;
+    }
+};
+
+template <>
+struct BEpi<kBFwd> {
+    float *r;
+    float *pi;
+    float theta, alpha;
+    unsigned long long np = 0;
+    float mx = 0.0f;
+    __device__ float2 pre(int64_t row, float) const {
+        const int64_t i = row * kTileQ + (threadIdx.x & 63);
+        return make_float2(r[i], pi[i]);
+    }
+    __device__ void full(int64_t row, float s, float2 p, int64_t len) {
+        const int64_t i = row * kTileQ + (threadIdx.x & 63);
+        const bool pushed = p.x > theta;
+        if (pushed) {
+            pi[i] = p.y + alpha * p.x;
+            np += (unsigned long long)len;
+        }
+        const float v = (pushed ? 0.0f : p.x) + s;
+        r[i] = v;
+        mx = fmaxf(mx, v);
+    }
+};
+
+// Sum over entries [e0, e0 + ne) of w * thr(x[col]) for this lane's query,
+// flushing each completed row of [r0, r0 + n_rows) through the epilogue.
+// Row ends are relative to e0; rows may be empty.
+template <bool kUnit, int kMode, class RowEnd, class RowScale>
+__device__ __forceinline__ void run_entries(const BArgs &a, const float *__restrict__ xt, int64_t r0, int n_rows,
+                                            int64_t e0, int ne, float theta, BEpi<kMode> &epi, RowEnd row_end,
+                                            RowScale row_scale, float *acc_out) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int j = 0, rstart = 0;
+    int rend = n_rows > 0 ? row_end(0) : INT_MAX;
+    float2 pre = n_rows > 0 ? epi.pre(r0, row_scale(0)) : make_float2(0.0f, 0.0f);
+    float acc = 0.0f;
+    while (j < n_rows && rend == 0) {
+        epi.full(r0 + j, 0.0f, pre, 0);
+        ++j;
+        if (j < n_rows) {
+            rend = row_end(j);
+            pre = epi.pre(r0 + j, row_scale(j));
+        } else {
+            rend = INT_MAX;
+        }
+    }
+    for (int base = 0; base < ne; base += kWave) {
+        const int cnt = ne - base < kWave ? ne - base : kWave;
+        const int32_t my_c = lane < cnt ? a.col[e0 + base + lane] : 0;
+        float my_w = 1.0f;
+        if constexpr (!kUnit) my_w = lane < cnt ? a.w[e0 + base + lane] : 0.0f;
+        for (int k0 = 0; k0 < cnt; k0 += kInFlight) {
+            float v[kInFlight];
+#pragma unroll
+            for (int u = 0; u < kInFlight; ++u) {
+                const int k = k0 + u < kWave ? k0 + u : kWave - 1;
+                const int32_t c = __builtin_amdgcn_readlane(my_c, k);
+                v[u] = k0 + u < cnt ? xt[(int64_t)c * kTileQ + lane] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kInFlight; ++u) {
+                const int k = k0 + u;
+                if (k < cnt) {
+                    float xv = v[u];
+                    if constexpr (kMode == kBBack) xv = xv > theta ? xv : 0.0f;
+                    acc += kUnit ? xv : readlane_f(my_w, k) * xv;
+                    const int e = base + k + 1;
+                    while (e == rend) {
+                        epi.full(r0 + j, acc, pre, rend - rstart);
+                        acc = 0.0f;
+                        rstart = rend;
+                        ++j;
+                        if (j < n_rows) {
+                            rend = row_end(j);
+                            pre = epi.pre(r0 + j, row_scale(j));
+                        } else {
+                            rend = INT_MAX;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (acc_out) *acc_out = acc;
+}
+
+template <int kMode>
+__device__ __forceinline__ BEpi<kMode> make_bepi(const BArgs &a, int t, float theta) {
+    if constexpr (kMode == kBBack) return BEpi<kBBack>{a.y + t * a.y_stride, theta};
+    else return BEpi<kBFwd>{a.y + t * a.y_stride, a.pi + t * a.pi_stride, theta, a.alpha};
+}
+
+template <int kMode>
+__device__ __forceinline__ void bflush(const BArgs &a, int t, BEpi<kMode> &epi) {
+    __shared__ float smx[kWavesPerBlock][kWave];
+    __shared__ unsigned long long snp[kWavesPerBlock][kWave];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    smx[wid][lane] = epi.mx;
+    snp[wid][lane] = epi.np;
+    __syncthreads();
+    if (wid == 0) {
+        float m = smx[0][lane];
+        unsigned long long n = snp[0][lane];
+#pragma unroll
+        for (int i = 1; i < kWavesPerBlock; ++i) {
+            m = fmaxf(m, smx[i][lane]);
+            n += snp[i][lane];
+        }
+        const int64_t o = (int64_t)blockIdx.x * kTileQ + lane;
+        if (a.blk_max) a.blk_max[t * a.blk_stride_f + o] = m;
+        if (a.blk_np) a.blk_np[t * a.blk_stride_u + o] = n;
+    }
+}
+
+template <bool kUnit, int kMode>
+__global__ void __launch_bounds__(kBlock) kb_gather(BArgs a) {
+    const int t = blockIdx.y;
+    const TileCtl &tc = a.ctl[t];
+    if (tc.all_done) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const float theta = tc.q[lane].theta;
+    const float *xt = a.x + t * a.x_stride;
+    float *part = a.part + t * a.part_stride;
+    BEpi<kMode> epi = make_bepi<kMode>(a, t, theta);
+    const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t it = wave0; it < a.n_items; it += stride) {
+        const WorkItem item = a.items[it];
+        if (item.n > 0) {
+            const int64_t r0 = item.row;
+            const int n = item.n;
+            const int64_t e0 = a.off[r0];
+            const int ne = (int)(a.off[r0 + n] - e0);
+            // Row ends (relative to e0) and row scales, one row per lane.
+            int end0 = INT_MAX, end1 = INT_MAX;
+            float sc0 = 0.0f, sc1 = 0.0f;
+            if (lane < n) end0 = (int)(a.off[r0 + lane + 1] - e0);
+            if (lane + kWave < n) end1 = (int)(a.off[r0 + lane + kWave + 1] - e0);
+            if constexpr (kMode == kBBack) {
+                if (lane < n) sc0 = a.inv_b[r0 + lane];
+                if (lane + kWave < n) sc1 = a.inv_b[r0 + lane + kWave];
+            }
+            auto row_end = [&](int jj) {
+                return jj < kWave ? __builtin_amdgcn_readlane(end0, jj) : __builtin_amdgcn_readlane(end1, jj - kWave);
+            };
+            auto row_scale = [&](int jj) { return jj < kWave ? readlane_f(sc0, jj) : readlane_f(sc1, jj - kWave); };
+            run_entries<kUnit, kMode>(a, xt, r0, n, e0, ne, theta, epi, row_end, row_scale, nullptr);
+        } else {
+            const int64_t row = item.row;
+            const int64_t rb = a.off[row], re = a.off[row + 1];
+            const int64_t e0 = rb + (int64_t)(-item.n) * kItemEdges;
+            const int ne = (int)(re - e0 < kItemEdges ? re - e0 : kItemEdges);
+            const bool whole = re - rb <= kItemEdges;
+            float scale = 0.0f;
+            if constexpr (kMode == kBBack) scale = a.inv_b[row];
+            auto row_end = [&](int) { return whole ? ne : INT_MAX; };
+            auto row_scale = [&](int) { return scale; };
+            float acc = 0.0f;
+            run_entries<kUnit, kMode>(a, xt, row, whole ? 1 : 0, e0, ne, theta, epi, row_end, row_scale, &acc);
+            if (!whole) part[it * kTileQ + lane] = acc;
+        }
+    }
+    bflush<kMode>(a, t, epi);
+}
+
+// Rows cut into chunks: one wave per row adds its chunk sums per query.
+template <int kMode>
+__global__ void __launch_bounds__(kBlock) kb_fix(BArgs a) {
+    const int t = blockIdx.y;
+    const TileCtl &tc = a.ctl[t];
+    if (tc.all_done) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const float theta = tc.q[lane].theta;
+    const float *part = a.part + t * a.part_stride;
+    BEpi<kMode> epi = make_bepi<kMode>(a, t, theta);
+    const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t i = wave0; i < a.n_split; i += stride) {
+        const SplitRow sr = a.split[i];
+        float s = 0.0f;
+        for (int ch = 0; ch < sr.nch; ++ch) s += part[(int64_t)(sr.first_item + ch) * kTileQ + lane];
+        const float scale = kMode == kBBack ? a.inv_b[sr.row] : 0.0f;
+        epi.full(sr.row, s, epi.pre(sr.row, scale), a.off[sr.row + 1] - a.off[sr.row]);
+    }
+    bflush<kMode>(a, t, epi);
+}
+
+// One wave per tile, lane = query: max r and n_p from the partials, then the
+// stop / switch rule of Algorithm 4 for every running query.
+__global__ void __launch_bounds__(kWave) kb_control(TileCtl *ctl, const float *blk_max, const unsigned long long *blk_np,
+                                                    int64_t stride_f, int64_t stride_u, int grid_cap, int n_back,
+                                                    int n_back_fix, int n_fwd, int n_fwd_fix, Rule rule) {
+    const int t = blockIdx.x;
+    TileCtl &tc = ctl[t];
+    if (tc.all_done) return;
+    const int q = threadIdx.x;
+    const float *bm = blk_max + t * stride_f;
+    const unsigned long long *bn = blk_np + t * stride_u;
+    float m = 0.0f;
+    for (int i = 0; i < n_fwd; ++i) m = fmaxf(m, bm[(int64_t)i * kTileQ + q]);
+    for (int i = 0; i < n_fwd_fix; ++i) m = fmaxf(m, bm[((int64_t)grid_cap + i) * kTileQ + q]);
+    unsigned long long np = 0;
+    const int cnt[4] = {n_back, n_back_fix, n_fwd, n_fwd_fix};
+    for (int k = 0; k < 4; ++k)
+        for (int i = 0; i < cnt[k]; ++i) np += bn[((int64_t)k * grid_cap + i) * kTileQ + q];
+    QueryCtl &c = tc.q[q];
+    int done = c.done;
+    if (!done) {
+        const unsigned long long n_p = c.n_p + np;
+        const int iter = c.iter + 1;
+        c.n_p = n_p;
+        c.iter = iter;
+        c.last_max = m;
+        if (!(m > c.eps_f)) {
+            done = 1;
+            c.status = 1;
+        } else if (iter >= c.max_iters) {
+            done = 1;
+            c.status = 2;
+        } else if (c.phase == 1) {
+            const double tt = (double)logf(m / c.eps_f) * (double)rule.inv_log;
+            if ((double)n_p >= rule.budget_scale * (tt > 0.0 ? tt : 0.0)) {
+                c.phase = 2;
+                c.theta = 0.0f;
+                c.switch_iter = iter;
+            }
+        }
+        if (done) {
+            c.done = 1;
+            c.theta = FLT_MAX;
+        }
+    }
+    const unsigned long long running = __ballot(!done);
+    if (q == 0) tc.all_done = running == 0ull ? 1 : 0;
+}
+
+__global__ void kb_fill(float *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+struct InitQuery {
+    int32_t source;
+    float eps_f;
+};
+
+// One wave per tile: lane q starts query q of the tile (or stays empty).
+__global__ void __launch_bounds__(kWave) kb_init(TileCtl *ctl, float *r, int64_t r_stride, const InitQuery *qs,
+                                                 int64_t n_valid, int32_t max_iters) {
+    const int t = blockIdx.x, q = threadIdx.x;
+    const int64_t gq = (int64_t)t * kTileQ + q;
+    QueryCtl &c = ctl[t].q[q];
+    const bool live = gq < n_valid;
+    const int32_t src = live ? qs[gq].source : -1;
+    const float eps_f = live ? qs[gq].eps_f : 1.0f;
+    const bool run = live && 1.0f > eps_f;
+    if (live) r[t * r_stride + (int64_t)src * kTileQ + q] = 1.0f;
+    c.theta = run ? eps_f : FLT_MAX;
+    c.eps_f = eps_f;
+    c.done = run ? 0 : 1;
+    c.phase = 1;
+    c.iter = 0;
+    c.switch_iter = -1;
+    c.status = run ? 0 : 1;
+    c.max_iters = max_iters;
+    c.n_p = 0;
+    c.last_max = live ? 1.0f : 0.0f;
+    c.source = src;
+    const unsigned long long running = __ballot(run);
+    if (q == 0) ctl[t].all_done = running == 0ull ? 1 : 0;
+}
+
+// out[(t * kTileQ + q) * n_u + u] = pi[t][u][q], through 64 x 64 LDS tiles.
+__global__ void __launch_bounds__(kBlock) kb_transpose(const float *pi, int64_t pi_stride, int64_t n_u, float *out,
+                                                       int64_t n_rows_valid) {
+    __shared__ float tile[kWave][kWave + 1];
+    const int t = blockIdx.y;
+    const int64_t u0 = (int64_t)blockIdx.x * kWave;
+    const float *src = pi + t * pi_stride;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int i = wid; i < kWave; i += kWavesPerBlock) {
+        const int64_t u = u0 + i;
+        tile[i][lane] = u < n_u ? src[u * kTileQ + lane] : 0.0f;
+    }
+    __syncthreads();
+    for (int q = wid; q < kWave; q += kWavesPerBlock) {
+        const int64_t row = (int64_t)t * kTileQ + q;
+        const int64_t u = u0 + lane;
+        if (row < n_rows_valid && u < n_u) out[row * n_u + u] = tile[lane][q];
+    }
+}
+
+// Per-lane sums of a tile vector: blk[t][block][q].
+__global__ void __launch_bounds__(kBlock) kb_sums(const float *x, int64_t x_stride, int64_t n_u, double *blk) {
+    __shared__ double s[kWavesPerBlock][kWave];
+    const int t = blockIdx.y;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const float *xt = x + t * x_stride;
+    double acc = 0.0;
+    for (int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + wid; u < n_u; u += (int64_t)gridDim.x * kWavesPerBlock)
+        acc += (double)xt[u * kTileQ + lane];
+    s[wid][lane] = acc;
+    __syncthreads();
+    if (wid == 0) {
+        double v = 0.0;
+        for (int i = 0; i < kWavesPerBlock; ++i) v += s[i][lane];
+        blk[((int64_t)t * gridDim.x + blockIdx.x) * kTileQ + lane] = v;
+    }
+}
+
+unsigned capped(int64_t n_units, int64_t per_block, int cap) {
+    int64_t g = (n_units + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+Rule make_rule(const Graph &g) {
+    Rule r;
+    r.alpha = (float)g.alpha;
+    r.inv_log = (float)(1.0 / std::log(1.0 / (1.0 - g.alpha)));
+    r.budget_scale = 2.0 * (double)(g.m_e + g.m_a);
+    return r;
+}
+
+struct BPlan {
+    unsigned back, back_fix, fwd, fwd_fix;
+};
+
+// Workgroups per tile: enough waves to cover the items, at most the
+// per-launch budget spread over the tiles in flight.
+BPlan bplan(const Graph &g, int nt) {
+    const int cap = std::min(g.grid_cap, std::max(64, g.grid_cap / std::max(nt, 1)));
+    BPlan p;
+    p.back = g.back.n_items ? capped(g.back.n_items, kWavesPerBlock, cap) : 0;
+    p.back_fix = g.back.n_split ? capped(g.back.n_split, kWavesPerBlock, cap) : 0;
+    p.fwd = capped(g.fwd.n_items, kWavesPerBlock, cap);
+    p.fwd_fix = g.fwd.n_split ? capped(g.fwd.n_split, kWavesPerBlock, cap) : 0;
+    return p;
+}
+
+}  // namespace
+
+void free_batch_state(Graph &g) {
+    BatchState &b = g.batch;
+    for (void *p : {(void *)b.r, (void *)b.pi, (void *)b.z, (void *)b.part, (void *)b.ctl, (void *)b.blk_max,
+                    (void *)b.blk_np, (void *)b.out, (void *)b.sums})
+        dfree(p);
+    b = BatchState{};
+}
+
+void ensure_batch_state(Graph &g, int tiles) {
+    BatchState &b = g.batch;
+    if (b.tiles >= tiles) return;
+    free_batch_state(g);
+    const int64_t items = std::max<int64_t>(std::max(g.fwd.n_items, g.back.n_items), 1);
+    const size_t T = (size_t)tiles, Q = kTileQ;
+    b.r = (float *)dev_alloc(g, T * g.n_u * Q * 4, "batch residues");
+    b.pi = (float *)dev_alloc(g, T * g.n_u * Q * 4, "batch reserves");
+    b.z = (float *)dev_alloc(g, T * std::max<int64_t>(g.n_v + g.n_a, 1) * Q * 4, "batch V/attribute residues");
+    b.part = (float *)dev_alloc(g, T * items * Q * 4, "batch chunk partials");
+    b.ctl = (TileCtl *)dev_alloc(g, T * sizeof(TileCtl), "batch control");
+    b.blk_max = (float *)dev_alloc(g, T * 2 * g.grid_cap * Q * 4, "batch workgroup maxima");
+    b.blk_np = (unsigned long long *)dev_alloc(g, T * 4 * g.grid_cap * Q * 8, "batch workgroup counts");
+    b.out = (float *)dev_alloc(g, T * Q * g.n_u * 4, "batch scores");
+    b.sums = (double *)dev_alloc(g, T * g.grid_cap * Q * 8, "batch sums");
+    b.tiles = tiles;
+    b.grid_x = g.grid_cap;
+}
+
+void batch_init(Graph &g, int t0, int nt, const int32_t *sources, const float *eps_f, int64_t n_q,
+                int32_t max_iters, hipStream_t s) {
+    BatchState &b = g.batch;
+    const int64_t tile_u = g.n_u * kTileQ;
+    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.r + t0 * tile_u, (int64_t)nt * tile_u);
+    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.pi + t0 * tile_u, (int64_t)nt * tile_u);
+    std::vector<InitQuery> hq((size_t)nt * kTileQ);
+    const int64_t n_valid = std::min<int64_t>(n_q, (int64_t)nt * kTileQ);
+    for (int64_t i = 0; i < n_valid; ++i) hq[i] = InitQuery{sources[i], eps_f[i]};
+    InitQuery *dq = nullptr;
+    check_hip(hipMallocAsync((void **)&dq, hq.size() * sizeof(InitQuery), s), "batch init");
+    check_hip(hipMemcpyAsync(dq, hq.data(), hq.size() * sizeof(InitQuery), hipMemcpyHostToDevice, s), "batch init");
+    hipLaunchKernelGGL(kb_init, dim3(nt), dim3(kWave), 0, s, b.ctl + t0, b.r + t0 * tile_u, tile_u, dq, n_valid,
+                       max_iters);
+    check_hip(hipFreeAsync(dq, s), "batch init");
+    check_hip(hipGetLastError(), "batch init launch");
+}
+
+void batch_round(Graph &g, int t0, int nt, hipStream_t s) {
+    BatchState &b = g.batch;
+    const BPlan p = bplan(g, nt);
+    const int64_t tile_u = g.n_u * kTileQ, tile_z = std::max<int64_t>(g.n_v + g.n_a, 1) * kTileQ;
+    const int64_t tile_part = std::max<int64_t>(std::max(g.fwd.n_items, g.back.n_items), 1) * kTileQ;
+    const int64_t sf = 2 * (int64_t)g.grid_cap * kTileQ, su = 4 * (int64_t)g.grid_cap * kTileQ;
+    BArgs back{g.back.off, g.back.col, g.back.w, g.back.items, g.back.n_items, g.back.split, g.back.n_split,
+               b.r + t0 * tile_u, b.z + t0 * tile_z, nullptr, g.inv_b, b.part + t0 * tile_part, b.ctl + t0,
+               tile_u, tile_z, 0, tile_part, nullptr, b.blk_np + t0 * su, sf, su, (float)g.alpha};
+    // Slots of the n_p partials: 0 back, 1 back fix, 2 fwd, 3 fwd fix; of the
+    // max partials: 0 fwd, 1 fwd fix; slots are grid_cap workgroups apart.
+    const int64_t slot = (int64_t)g.grid_cap * kTileQ;
+    // Algorithmic bytes of a launch: CSR entries and offsets once, 4 bytes
+    // per (entry, running query), and the per-(row, query) epilogue state.
+    const double q = (double)b.live_q;
+    const double wb = g.fwd.w ? 8.0 : 4.0;
+    const double back_bytes = 8.0 * g.back.nnz + 12.0 * g.back.n_rows + q * (4.0 * g.back.nnz + 4.0 * g.back.n_rows);
+    const double fwd_bytes = wb * g.fwd.nnz + 8.0 * g.fwd.n_rows + q * (4.0 * g.fwd.nnz + 16.0 * g.fwd.n_rows);
+    if (p.back)
+        profiled(g.prof, 2, back_bytes, s, [&] {
+            hipLaunchKernelGGL((kb_gather<false, kBBack>), dim3(p.back, nt), dim3(kBlock), 0, s, back);
+        });
+    if (p.back_fix) {
+        BArgs a = back;
+        a.blk_np += slot;
+        hipLaunchKernelGGL((kb_fix<kBBack>), dim3(p.back_fix, nt), dim3(kBlock), 0, s, a);
+    }
+    BArgs fwd{g.fwd.off, g.fwd.col, g.fwd.w, g.fwd.items, g.fwd.n_items, g.fwd.split, g.fwd.n_split,
+              b.z + t0 * tile_z, b.r + t0 * tile_u, b.pi + t0 * tile_u, nullptr, b.part + t0 * tile_part, b.ctl + t0,
+              tile_z, tile_u, tile_u, tile_part, b.blk_max + t0 * sf, b.blk_np + t0 * su + 2 * slot, sf, su,
+              (float)g.alpha};
+    profiled(g.prof, 3, fwd_bytes, s, [&] {
+        if (g.unit) hipLaunchKernelGGL((kb_gather<true, kBFwd>), dim3(p.fwd, nt), dim3(kBlock), 0, s, fwd);
+        else hipLaunchKernelGGL((kb_gather<false, kBFwd>), dim3(p.fwd, nt), dim3(kBlock), 0, s, fwd);
+    });
+    if (p.fwd_fix) {
+        BArgs a = fwd;
+        a.blk_max += slot;
+        a.blk_np += slot;
+        hipLaunchKernelGGL((kb_fix<kBFwd>), dim3(p.fwd_fix, nt), dim3(kBlock), 0, s, a);
+    }
+    hipLaunchKernelGGL(kb_control, dim3(nt), dim3(kWave), 0, s, b.ctl + t0, b.blk_max + t0 * sf, b.blk_np + t0 * su,
+                       sf, su, g.grid_cap, (int)p.back, (int)p.back_fix, (int)p.fwd, (int)p.fwd_fix, make_rule(g));
+    check_hip(hipGetLastError(), "batch round launch");
+}
+
+void batch_scores(Graph &g, int t0, int nt, int64_t n_rows, float *out, hipStream_t s) {
+    const int64_t tile_u = g.n_u * kTileQ;
+    hipLaunchKernelGGL(kb_transpose, dim3((unsigned)((g.n_u + kWave - 1) / kWave), nt), dim3(kBlock), 0, s,
+                       g.batch.pi + t0 * tile_u, tile_u, g.n_u, out, std::min<int64_t>(n_rows, (int64_t)nt * kTileQ));
+    check_hip(hipGetLastError(), "batch scores launch");
+}
+
+void batch_resid_sums(Graph &g, int t0, int nt, double *sums, hipStream_t s) {
+    const int64_t tile_u = g.n_u * kTileQ;
+    const unsigned gx = capped(g.n_u, kWavesPerBlock * 64, std::min(g.grid_cap, 1024));
+    hipLaunchKernelGGL(kb_sums, dim3(gx, nt), dim3(kBlock), 0, s, g.batch.r + t0 * tile_u, tile_u, g.n_u,
+                       g.batch.sums);
+    std::vector<double> h((size_t)nt * gx * kTileQ);
+    check_hip(hipMemcpyAsync(h.data(), g.batch.sums, h.size() * 8, hipMemcpyDeviceToHost, s), "batch sums D2H");
+    check_hip(hipStreamSynchronize(s), "batch sums");
+    for (int t = 0; t < nt; ++t)
+        for (int q = 0; q < kTileQ; ++q) {
+            double v = 0.0;
+            for (unsigned i = 0; i < gx; ++i) v += h[((size_t)t * gx + i) * kTileQ + q];
+            sums[(size_t)t * kTileQ + q] = v;
+        }
+}
+
+}  // namespace ahpp

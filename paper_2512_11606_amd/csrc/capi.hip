@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -54,6 +55,23 @@ void ensure_topk_scratch(Graph &g, int64_t n_q) {
     g.tk_scratch_bytes = need;
 }
 
+// Tiles of kTileQ queries run side by side in one batch pass: AHPP_BATCH_TILES
+// if set, else as many as fit in a quarter of the free device memory, at most 16.
+int batch_tiles_in_flight(const Graph &g) {
+    if (const char *e = std::getenv("AHPP_BATCH_TILES")) {
+        int v = std::atoi(e);
+        if (v > 0) return v;
+    }
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return 4;
+    const double per_tile = (double)kTileQ * 4.0 *
+                            (3.0 * (double)g.n_u + (double)(g.n_v + g.n_a) +
+                             (double)std::max(g.fwd.n_items, g.back.n_items)) +
+                            (double)g.grid_cap * kTileQ * 48.0;
+    int t = (int)std::floor((double)free_b * 0.25 / std::max(per_tile, 1.0));
+    return std::max(1, std::min(t, 16));
+}
+
 int default_lambda_iters(int64_t n_u, double alpha) {
     double t = std::ceil(std::log(0.01 / (double)std::max<int64_t>(n_u, 1)) / std::log(1.0 - alpha));
     return std::max(1, (int)t);
@@ -61,15 +79,30 @@ int default_lambda_iters(int64_t n_u, double alpha) {
 
 // Runs rounds until the control block reports done; the host checks after
 // chunks of rounds that grow from 4 to 32.
+// Rounds still needed, estimated from the max residue: the synchronous phase
+// shrinks it by about (1 - alpha) per round (Theorem 1's proof).
+int rounds_left(const Graph &g, float max_r, float eps_f) {
+    if (!(max_r > eps_f)) return 1;
+    const double t = std::log((double)max_r / (double)eps_f) / std::log(1.0 / (1.0 - g.alpha));
+    return (int)std::min(32.0, std::max(1.0, std::ceil(t)));
+}
+
+// Enqueues rounds in chunks sized by rounds_left until the control block
+// reports done; rounds enqueued past the stop are empty launches.
 void run_single(Graph &g, hipStream_t s) {
-    int chunk = 4;
+    int chunk = 4, launched = 0;
+    Control c;
     for (;;) {
         for (int i = 0; i < chunk; ++i) single_query_round(g, s);
-        int32_t done = 0;
-        check_hip(hipMemcpyAsync(&done, &g.q_ctl->done, sizeof(int32_t), hipMemcpyDeviceToHost, s), "poll");
+        launched += chunk;
+        check_hip(hipMemcpyAsync(&c, g.q_ctl, sizeof(Control), hipMemcpyDeviceToHost, s), "poll");
         check_hip(hipStreamSynchronize(s), "poll");
-        if (done) break;
-        chunk = std::min(chunk * 2, 32);
+        if (c.done) break;
+        chunk = rounds_left(g, c.last_max, c.eps_f);
+    }
+    if (g.prof.on) {
+        profiler_void_tail(g.prof, 0, launched - c.iter);
+        profiler_void_tail(g.prof, 1, launched - c.iter);
     }
 }
 
@@ -79,6 +112,32 @@ void check_hip(hipError_t e, const char *what) {
     if (e == hipSuccess) return;
     if (e == hipErrorOutOfMemory) throw Failure{AHPP_ERR_OUT_OF_MEMORY, std::string(what) + ": out of device memory"};
     throw Failure{AHPP_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+void profiler_flush(Profiler &p) {
+    for (ProfLaunch &l : p.pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(l.stop) == hipSuccess && hipEventElapsedTime(&ms, l.start, l.stop) == hipSuccess) {
+            p.launches[l.kind] += 1;
+            p.ms[l.kind] += ms;
+            p.bytes[l.kind] += l.bytes;
+        }
+        (void)hipEventDestroy(l.start);
+        (void)hipEventDestroy(l.stop);
+    }
+    p.pending.clear();
+}
+
+// Drops the last n recorded launches of `kind`: rounds enqueued after the
+// stop rule held run as empty launches and are not kernel work.
+void profiler_void_tail(Profiler &p, int kind, int64_t n) {
+    for (int64_t i = (int64_t)p.pending.size() - 1; i >= 0 && n > 0; --i) {
+        if (p.pending[i].kind != kind) continue;
+        (void)hipEventDestroy(p.pending[i].start);
+        (void)hipEventDestroy(p.pending[i].stop);
+        p.pending.erase(p.pending.begin() + i);
+        --n;
+    }
 }
 
 void *dev_alloc(Graph &g, size_t bytes, const char *what) {
@@ -100,6 +159,45 @@ using namespace ahpp;
 extern "C" {
 
 const char *ahpp_last_error(void) { return g_last_error.c_str(); }
+
+ahpp_status_t ahpp_profile_enable(ahpp_graph_t *h, int32_t on) {
+    g_last_error.clear();
+    if (!h) return fail(AHPP_ERR_INVALID_ARG, "ahpp_profile_enable: NULL graph");
+    Profiler &p = h->g.prof;
+    try {
+        DeviceScope scope(h->g.device);
+        profiler_flush(p);
+    } catch (const Failure &f) {
+        return fail(f.status, f.msg);
+    }
+    if (on) {
+        for (int k = 0; k < kProfKinds; ++k) {
+            p.launches[k] = 0;
+            p.ms[k] = 0.0;
+            p.bytes[k] = 0.0;
+        }
+    }
+    p.on = on != 0;
+    return AHPP_OK;
+}
+
+ahpp_status_t ahpp_profile_read(ahpp_graph_t *h, int32_t kind, int64_t *launches, double *total_ms,
+                                double *algo_bytes) {
+    g_last_error.clear();
+    if (!h) return fail(AHPP_ERR_INVALID_ARG, "ahpp_profile_read: NULL graph");
+    if (kind < 0 || kind >= kProfKinds) return fail(AHPP_ERR_INVALID_ARG, "ahpp_profile_read: bad kind");
+    Profiler &p = h->g.prof;
+    try {
+        DeviceScope scope(h->g.device);
+        profiler_flush(p);
+    } catch (const Failure &f) {
+        return fail(f.status, f.msg);
+    }
+    if (launches) *launches = p.launches[kind];
+    if (total_ms) *total_ms = p.ms[kind];
+    if (algo_bytes) *algo_bytes = p.bytes[kind];
+    return AHPP_OK;
+}
 
 ahpp_status_t ahpp_graph_load(const ahpp_graph_desc_t *d, ahpp_graph_t **out) {
     g_last_error.clear();
@@ -195,6 +293,7 @@ void ahpp_graph_free(ahpp_graph_t *h) {
     try {
         DeviceScope scope(h->g.device);
         (void)hipDeviceSynchronize();
+        profiler_flush(h->g.prof);
         free_graph(h->g);
     } catch (...) {
     }
@@ -274,16 +373,103 @@ ahpp_status_t ahpp_query_batch(ahpp_graph_t *h, int32_t n_q, const int32_t *sour
     if (k < 0 || k > kMaxTopK) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_batch: k must be in [0, 2048]");
     if (k > 0 && (!topk_idx || !topk_val || !topk_n))
         return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_batch: top-k outputs required when k > 0");
-    ahpp_status_t worst = AHPP_OK;
-    for (int32_t q = 0; q < n_q; ++q) {
-        ahpp_status_t st = ahpp_query(h, sources[q], eps[q], max_iters, pi_out ? pi_out + (size_t)q * g.n_u : nullptr,
-                                      nullptr, k, k ? topk_idx + (size_t)q * k : nullptr,
-                                      k ? topk_val + (size_t)q * k : nullptr, k ? topk_n + q : nullptr,
-                                      stats ? stats + q : nullptr, hip_stream);
-        if (st == AHPP_ERR_NOT_CONVERGED) worst = st;
-        else if (st != AHPP_OK) return st;
+    if (max_iters <= 0) max_iters = 100000;
+    hipStream_t s = (hipStream_t)hip_stream;
+    bool all_converged = true;
+    try {
+        DeviceScope scope(g.device);
+        const int tiles_total = (int)((n_q + kTileQ - 1) / kTileQ);
+        const int tif = std::min(tiles_total, batch_tiles_in_flight(g));
+        ensure_batch_state(g, tif);
+        if (k > 0) ensure_topk_scratch(g, (int64_t)tif * kTileQ);
+        std::vector<float> eps_f((size_t)n_q);
+        for (int32_t q = 0; q < n_q; ++q) eps_f[q] = (float)(eps[q] / g.lambda);
+        int32_t *d_src = nullptr;
+        check_hip(hipMallocAsync((void **)&d_src, (size_t)n_q * 4, s), "batch sources");
+        check_hip(hipMemcpyAsync(d_src, sources, (size_t)n_q * 4, hipMemcpyHostToDevice, s), "batch sources");
+        hipEvent_t e0, e1;
+        check_hip(hipEventCreate(&e0), "event");
+        check_hip(hipEventCreate(&e1), "event");
+        check_hip(hipEventRecord(e0, s), "event");
+        std::vector<TileCtl> ctl((size_t)tif);
+        std::vector<double> sums((size_t)tif * kTileQ);
+        std::vector<ahpp_stats_t> st_all(stats ? (size_t)n_q : 0);
+        for (int64_t q0 = 0; q0 < n_q; q0 += (int64_t)tif * kTileQ) {
+            const int64_t nq = std::min<int64_t>((int64_t)tif * kTileQ, n_q - q0);
+            const int nt = (int)((nq + kTileQ - 1) / kTileQ);
+            batch_init(g, 0, nt, sources + q0, eps_f.data() + q0, nq, max_iters, s);
+            g.batch.live_q = nq;
+            int chunk = 4, launched = 0, executed = 0;
+            for (;;) {
+                for (int i = 0; i < chunk; ++i) batch_round(g, 0, nt, s);
+                launched += chunk;
+                check_hip(hipMemcpyAsync(ctl.data(), g.batch.ctl, (size_t)nt * sizeof(TileCtl), hipMemcpyDeviceToHost,
+                                         s), "poll");
+                check_hip(hipStreamSynchronize(s), "poll");
+                bool done = true;
+                int64_t live = 0;
+                int next = 1;
+                for (int t = 0; t < nt; ++t) {
+                    done = done && ctl[t].all_done;
+                    for (int q = 0; q < kTileQ; ++q) {
+                        const QueryCtl &c = ctl[t].q[q];
+                        if (c.source < 0) continue;
+                        executed = std::max(executed, (int)c.iter);
+                        if (!c.done) {
+                            ++live;
+                            next = std::max(next, rounds_left(g, c.last_max, c.eps_f));
+                        }
+                    }
+                }
+                g.batch.live_q = live;
+                if (done) break;
+                chunk = next;
+            }
+            if (g.prof.on) {
+                profiler_void_tail(g.prof, 2, launched - executed);
+                profiler_void_tail(g.prof, 3, launched - executed);
+            }
+            float *scores = pi_out ? pi_out + q0 * g.n_u : g.batch.out;
+            batch_scores(g, 0, nt, nq, scores, s);
+            if (k > 0)
+                topk_launch(scores, g.n_u, g.n_u, nq, d_src + q0, -1, k, topk_idx + q0 * k, topk_val + q0 * k,
+                            topk_n + q0, g.tk_scratch, s);
+            for (int64_t q = 0; q < nq; ++q) {
+                const QueryCtl &c = ctl[q / kTileQ].q[q % kTileQ];
+                if (c.status != 1) all_converged = false;
+            }
+            if (stats) {
+                batch_resid_sums(g, 0, nt, sums.data(), s);
+                for (int64_t q = 0; q < nq; ++q) {
+                    const QueryCtl &c = ctl[q / kTileQ].q[q % kTileQ];
+                    ahpp_stats_t &o = st_all[(size_t)(q0 + q)];
+                    o.iters = c.iter;
+                    o.sync_switch_iter = c.switch_iter;
+                    o.converged = c.status == 1;
+                    o.reserved = 0;
+                    o.n_push = (int64_t)c.n_p;
+                    o.max_residual = c.last_max;
+                    o.sum_residual = sums[(size_t)q];
+                    o.pad = 0;
+                }
+            }
+        }
+        check_hip(hipEventRecord(e1, s), "event");
+        check_hip(hipFreeAsync(d_src, s), "batch sources");
+        check_hip(hipStreamSynchronize(s), "batch");
+        float ms = 0.0f;
+        check_hip(hipEventElapsedTime(&ms, e0, e1), "event");
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (stats)
+            for (int32_t q = 0; q < n_q; ++q) {
+                st_all[q].ms = ms;
+                stats[q] = st_all[q];
+            }
+    } catch (const Failure &f) {
+        return fail(f.status, f.msg);
     }
-    if (worst != AHPP_OK) return fail(worst, "ahpp_query_batch: some query reached max_iters");
+    if (!all_converged) return fail(AHPP_ERR_NOT_CONVERGED, "ahpp_query_batch: some query reached max_iters");
     return AHPP_OK;
 }
 

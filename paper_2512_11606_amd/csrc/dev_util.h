@@ -75,4 +75,29 @@ __device__ __forceinline__ float block_max_f(float v, float *lds) {
     return m;
 }
 
+// Max and sum over a workgroup of kWaves waves; lds holds kWaves entries.
+template <int kWaves>
+__device__ __forceinline__ float block_max_n(float v, float *lds) {
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float m = lds[0];
+#pragma unroll
+    for (int i = 1; i < kWaves; ++i) m = fmaxf(m, lds[i]);
+    __syncthreads();
+    return m;
+}
+
+template <int kWaves>
+__device__ __forceinline__ unsigned long long block_sum_u64_n(unsigned long long v, unsigned long long *lds) {
+    v = wave_sum_u64(v);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned long long m = 0;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) m += lds[i];
+    __syncthreads();
+    return m;
+}
+
 }  // namespace ahpp

@@ -200,9 +200,10 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 }
 
 // Row sums of fwd in double precision, one wave per row: d(u) over columns
-// < n_v (Eq. 1 denominator), s(u) over the attribute columns (Eq. 2).
+// < n_v (Eq. 1 denominator), s(u) over the attribute columns (Eq. 2);
+// stores c_d = (1-beta)(1-alpha)/d(u) and c_s = beta(1-alpha)/s(u).
 __global__ void k_fwd_coeffs(const int64_t *off, const int32_t *col, const float *w, int64_t n_u, int64_t n_v,
-                             float alpha, float beta, float *c_d, float *c_s, unsigned long long *dangling) {
+                             double alpha, double beta, double *c_d, double *c_s, unsigned long long *dangling) {
     const int lane = threadIdx.x & 63;
     const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -216,24 +217,29 @@ __global__ void k_fwd_coeffs(const int64_t *off, const int32_t *col, const float
         d = wave_sum_f64(d);
         s = wave_sum_f64(s);
         if (lane == 0) {
-            c_d[u] = d > 0 ? (float)((1.0 - beta) * (1.0 - alpha) / d) : 0.0f;
-            c_s[u] = s > 0 ? (float)(beta * (1.0 - alpha) / s) : 0.0f;
+            c_d[u] = d > 0 ? (1.0 - beta) * (1.0 - alpha) / d : 0.0;
+            c_s[u] = s > 0 ? beta * (1.0 - alpha) / s : 0.0;
             if (!(d > 0) || !(s > 0)) dang += 1;
         }
     }
     if (dang) atomicAdd(dangling, dang);
 }
 
-// 1/d(v) for V rows and 1/t(a) for attribute rows, one wave per row.
-__global__ void k_back_coeffs(const int64_t *off, const float *w, int64_t n_rows, float *inv_b) {
+// One wave per back row x: inv_b = 1/d(v) (V rows) or 1/t(a) (attribute rows)
+// from the raw weights, then each weight becomes w(u,x) c_d(u) (V rows) or
+// w(u,x) c_s(u) (attribute rows), rounded once from double.
+__global__ void k_back_coeffs(const int64_t *off, const int32_t *col, float *w, int64_t n_v, int64_t n_rows,
+                              const double *c_d, const double *c_s, float *inv_b) {
     const int lane = threadIdx.x & 63;
     const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t r = wave0; r < n_rows; r += n_waves) {
         double d = 0.0;
-        for (int64_t p = off[r] + lane; p < off[r + 1]; p += 64) d += w ? (double)w[p] : 1.0;
+        for (int64_t p = off[r] + lane; p < off[r + 1]; p += 64) d += (double)w[p];
         d = wave_sum_f64(d);
         if (lane == 0) inv_b[r] = d > 0 ? (float)(1.0 / d) : 0.0f;
+        const double *c = r < n_v ? c_d : c_s;
+        for (int64_t p = off[r] + lane; p < off[r + 1]; p += 64) w[p] = (float)((double)w[p] * c[col[p]]);
     }
 }
 
@@ -281,13 +287,13 @@ void build_items(const std::vector<int64_t> &off, std::vector<WorkItem> &items, 
 }
 
 // Sorts (key, col, w) by key (stable) and builds offsets + schedule.
-void build_csr(Graph &g, DevCsr &c, int64_t n_rows, uint32_t *key, int32_t *col, float *w, int64_t m,
+void build_csr(Graph &g, DevCsr &c, int64_t n_rows, uint32_t *key, int32_t *col, float *w, int64_t m, bool keep_w,
                hipStream_t s) {
     c.n_rows = n_rows;
     c.nnz = m;
     c.off = (int64_t *)dev_alloc(g, (size_t)(n_rows + 1) * sizeof(int64_t), "csr offsets");
     c.col = (int32_t *)dev_alloc(g, (size_t)std::max<int64_t>(m, 1) * sizeof(int32_t), "csr columns");
-    if (!g.unit) c.w = (float *)dev_alloc(g, (size_t)std::max<int64_t>(m, 1) * sizeof(float), "csr weights");
+    if (keep_w) c.w = (float *)dev_alloc(g, (size_t)std::max<int64_t>(m, 1) * sizeof(float), "csr weights");
     if (m > 0) {
         uint32_t *key2 = nullptr;
         int32_t *col2 = nullptr;
@@ -410,38 +416,41 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
     if (m_a > 0)
         hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_au, d_aa, d_aw, m_a,
                            (int32_t)g.n_v, 0u, key + m_e, col + m_e, w + m_e);
-    build_csr(g, g.fwd, g.n_u, key, col, w, m, s);
-    // back: rows V (col u) then attributes (row n_v + a, col n_u + u).
+    build_csr(g, g.fwd, g.n_u, key, col, w, m, !g.unit, s);
+    // back: rows V then attributes (row n_v + a); columns are U ids.
     if (m_e > 0)
         hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_ev, d_eu, d_ew, m_e, 0, 0u, key,
                            col, w);
     if (m_a > 0)
-        hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_aa, d_au, d_aw, m_a,
-                           (int32_t)g.n_u, (uint32_t)g.n_v, key + m_e, col + m_e, w + m_e);
-    build_csr(g, g.back, g.n_v + g.n_a, key, col, w, m, s);
+        hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_aa, d_au, d_aw, m_a, 0,
+                           (uint32_t)g.n_v, key + m_e, col + m_e, w + m_e);
+    build_csr(g, g.back, g.n_v + g.n_a, key, col, w, m, true, s);
     dfree(key);
     dfree(col);
     dfree(w);
     release();
 
-    // Coefficients.
-    g.c_d = (float *)dev_alloc(g, (size_t)std::max<int64_t>(g.n_u, 1) * 4, "c_d");
-    g.c_s = (float *)dev_alloc(g, (size_t)std::max<int64_t>(g.n_u, 1) * 4, "c_s");
+    // Coefficients: 1/d(u), 1/s(u) in double, then inv_b and the back weights
+    // w(u,x) * c(u) with c = (1-beta)(1-alpha)/d(u) or beta(1-alpha)/s(u).
     g.inv_b = (float *)dev_alloc(g, (size_t)std::max<int64_t>(g.n_v + g.n_a, 1) * 4, "inv_b");
+    double *cd = nullptr, *cs = nullptr;
     unsigned long long *d_dang = nullptr;
+    check_hip(hipMalloc(&cd, (size_t)std::max<int64_t>(g.n_u, 1) * 8), "coefficients");
+    check_hip(hipMalloc(&cs, (size_t)std::max<int64_t>(g.n_u, 1) * 8), "coefficients");
     check_hip(hipMalloc(&d_dang, 8), "dangling");
     check_hip(hipMemsetAsync(d_dang, 0, 8, s), "dangling");
-    if (g.n_u > 0)
-        hipLaunchKernelGGL(k_fwd_coeffs, dim3(grid_for(g.n_u * 64)), dim3(kBlock), 0, s, g.fwd.off, g.fwd.col, g.fwd.w,
-                           g.n_u, g.n_v, (float)g.alpha, (float)g.beta, g.c_d, g.c_s, d_dang);
+    hipLaunchKernelGGL(k_fwd_coeffs, dim3(grid_for(g.n_u * 64)), dim3(kBlock), 0, s, g.fwd.off, g.fwd.col, g.fwd.w,
+                       g.n_u, g.n_v, g.alpha, g.beta, cd, cs, d_dang);
     if (g.n_v + g.n_a > 0)
-        hipLaunchKernelGGL(k_back_coeffs, dim3(grid_for((g.n_v + g.n_a) * 64)), dim3(kBlock), 0, s, g.back.off, g.back.w,
-                           g.n_v + g.n_a, g.inv_b);
+        hipLaunchKernelGGL(k_back_coeffs, dim3(grid_for((g.n_v + g.n_a) * 64)), dim3(kBlock), 0, s, g.back.off,
+                           g.back.col, g.back.w, g.n_v, g.n_v + g.n_a, cd, cs, g.inv_b);
     check_hip(hipGetLastError(), "coefficient launch");
     unsigned long long dang = 0;
     check_hip(hipMemcpyAsync(&dang, d_dang, 8, hipMemcpyDeviceToHost, s), "dangling D2H");
     check_hip(hipStreamSynchronize(s), "coefficients");
     dfree(d_dang);
+    dfree(cd);
+    dfree(cs);
     g.dangling_u = (int64_t)dang;
     g.load_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -454,16 +463,13 @@ static void free_csr(DevCsr &c) {
 void free_graph(Graph &g) {
     free_csr(g.fwd);
     free_csr(g.back);
-    dfree(g.c_d); dfree(g.c_s); dfree(g.inv_b);
-    dfree(g.q_r); dfree(g.q_pi); dfree(g.q_rho); dfree(g.q_z); dfree(g.q_ctl);
-    dfree(g.part_item); dfree(g.blk_max); dfree(g.blk_np);
-    g.part_item = nullptr;
-    g.blk_max = nullptr;
-    g.blk_np = nullptr;
-    dfree(g.tk_scratch);
-    g.c_d = g.c_s = g.inv_b = nullptr;
-    g.q_r = g.q_pi = g.q_rho = g.q_z = nullptr;
+    free_batch_state(g);
+    for (void *p : {(void *)g.inv_b, (void *)g.q_r, (void *)g.q_pi, (void *)g.q_z, (void *)g.q_ctl,
+                    (void *)g.part_item, (void *)g.blk_max, (void *)g.blk_np, g.tk_scratch})
+        dfree(p);
+    g.inv_b = g.q_r = g.q_pi = g.q_z = g.part_item = g.blk_max = nullptr;
     g.q_ctl = nullptr;
+    g.blk_np = nullptr;
     g.tk_scratch = nullptr;
 }
 

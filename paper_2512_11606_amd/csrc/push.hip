@@ -1,35 +1,35 @@
 // Residue push of one AHPP query on gfx950 (Algorithm 4, level-synchronous).
 //
 // One round of Algorithm 4 (the U loop, then the V loop, then the attribute
-// loop of Algorithm 3) runs as a short chain of kernels over device-resident
-// state:
+// loop of Algorithm 3) is computed as two pull-form gathers over the CSRs
+// built at load, plus fix-ups for long rows and a control step:
 //
-//   k_u_push   (U side, elementwise): for every u with r(u) > theta:
-//                pi_hat(u) += alpha r(u); rho_d(u) = c_d(u) r(u);
-//                rho_s(u) = c_s(u) r(u); r(u) = 0; n_p += |N(u)| + |A(u)|.
-//              Other nodes get rho = 0.  (c_d = (1-beta)(1-alpha)/d(u),
-//              c_s = beta(1-alpha)/s(u), so rho_d / rho_s are the U->V and
-//              U->attribute increments of Algorithm 3 divided by w(u, .).)
-//   k_gather<Back>  (V and attribute rows): z(x) = inv_b(x) sum_u w(u,x) rho(u)
-//              = r(x)/d(x) for x in V, r(a)/t(a) for attributes;
-//              n_p += |N(x)| for every x with r(x) > 0.
-//   k_gather<FwdAcc> (U rows): r(u) += sum_{x in N(u), A(u)} w(u,x) z(x), the
-//              V->U and attribute->U push-back; per-workgroup max of r.
-//   k_fix<...> rows longer than one wave item: their chunk sums are added in
-//              chunk order, then the same epilogue runs.
-//   k_control  (one workgroup): max_u r(u) and n_p from the per-workgroup
-//              partials; the stop and phase-switch rule of Algorithm 4.
+//   k_gather<kBack>  V and attribute rows x:
+//       z(x) = inv_b(x) * sum_{u in N(x)} w'(u,x) * [r(u) > theta] r(u)
+//     where w'(u,v) = w(u,v)(1-beta)(1-alpha)/d(u) for x = v in V and
+//     w'(u,a) = w(u,a) beta(1-alpha)/s(u) for attributes.  This is the U loop
+//     (every u above the threshold sends (1-alpha) r(u) split by Eq. 1 / Eq. 2
+//     weights) followed by the division of the V / attribute residue by
+//     d(v) / t(a) that its push-back uses.  n_p += |N(x)| when r(x) > 0.
+//   k_gather<kFwdAcc> U rows u:
+//       pushed = r(u) > theta;  pi_hat(u) += pushed ? alpha r(u) : 0;
+//       r(u) = (pushed ? 0 : r(u)) + sum_{x in N(u), A(u)} w(u,x) z(x)
+//     i.e. the reserve update of the U loop and the V / attribute loops'
+//     push-back; n_p += |N(u)| + |A(u)| for pushed u; per-workgroup max r.
+//   k_fix<mode>   rows longer than one item: chunk sums added in chunk order.
+//   k_control     one workgroup: max_u r(u) and n_p from the partials, then
+//                 Algorithm 4's stop rule and phase switch.
 //
 // The U loop of Algorithm 3 writes only V and attribute residues and the V /
-// attribute loops write only U residues, so computing each loop from the
-// state at its start is exactly the paper's round, up to the order of
-// floating-point additions.  The gathers are pull-form sparse
-// matrix-vector products over the CSRs built at load; each wave takes one
-// schedule item (a pack of short rows, or one 512-entry chunk of a long row),
-// so hub rows are spread over many waves.  No floating-point atomics are
-// used: every sum has a fixed order and results are bitwise reproducible.
+// attribute loops write only U residues, so evaluating each loop on the state
+// at its start is exactly the paper's round up to the order of floating-point
+// additions.  Each wave takes one schedule item (a pack of short rows, or one
+// chunk of a long row), so hub rows are spread over many waves.  No
+// floating-point atomics are used: every sum has a fixed order and a query's
+// result is bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 
@@ -41,7 +41,7 @@ namespace ahpp {
 namespace {
 
 constexpr int kWavesPerBlock = kBlock / kWave;
-enum Mode { kBack = 0, kFwdAcc = 1, kFwdOver = 2 };
+enum Mode { kBack = 0, kFwdAcc = 1, kFwdLambda = 2 };
 
 struct CsrView {
     const int64_t *__restrict__ off;
@@ -58,15 +58,19 @@ CsrView view(const DevCsr &c) { return CsrView{c.off, c.col, c.w, c.items, c.n_i
 struct GatherArgs {
     CsrView c;
     const float *x;             // gathered vector
-    float *y;                   // output rows
+    float *y;                   // rows written (z, r or y)
+    float *aux;                 // kFwdAcc: pi_hat; kFwdLambda: running sum
     const float *inv_b;         // kBack: row scale
     float *part;                // chunk partial sums (one slot per item)
-    const Control *ctl;         // nullable: no early exit
-    float *blk_f;               // per-workgroup max (kFwdAcc), nullable
-    unsigned long long *blk_u;  // per-workgroup n_p (kBack), nullable
+    const Control *ctl;         // nullable: no early exit, threshold `theta`
+    float theta;                // threshold when ctl is null
+    float alpha;
+    float *blk_f;               // per-workgroup max, nullable
+    unsigned long long *blk_u;  // per-workgroup n_p, nullable
 };
 
-// Row epilogues.
+// Row epilogues: pre(row) is loaded early, with the row's entries;
+// full(row, s, pre, len) finishes a row of len entries whose sum is s.
 template <int kMode>
 struct Epi;
 
@@ -74,58 +78,77 @@ template <>
 struct Epi<kBack> {
     float *z;
     const float *inv_b;
-    const int64_t *off;
     unsigned long long np = 0;
-    __device__ void full(int64_t row, float s) {
-        const float v = inv_b[row] * s;
+    float mx = 0.0f;
+    __device__ float2 pre(int64_t row) const { return make_float2(inv_b[row], 0.0f); }
+    __device__ void full(int64_t row, float s, float2 p, int64_t len) {
+        const float v = p.x * s;
         z[row] = v;
-        if (v > 0.0f) np += (unsigned long long)(off[row + 1] - off[row]);
+        if (v > 0.0f) np += (unsigned long long)len;
     }
 };
 
 template <>
 struct Epi<kFwdAcc> {
     float *r;
+    float *pi;
+    float theta, alpha;
+    unsigned long long np = 0;
     float mx = 0.0f;
-    __device__ void full(int64_t row, float s) {
-        const float v = r[row] + s;
+    __device__ float2 pre(int64_t row) const { return make_float2(r[row], pi[row]); }
+    __device__ void full(int64_t row, float s, float2 p, int64_t len) {
+        const bool pushed = p.x > theta;
+        if (pushed) {
+            pi[row] = p.y + alpha * p.x;
+            np += (unsigned long long)len;
+        }
+        const float v = (pushed ? 0.0f : p.x) + s;
         r[row] = v;
         mx = fmaxf(mx, v);
     }
 };
 
+// Theorem 3 sweep: acc += alpha y_old; y = s.
 template <>
-struct Epi<kFwdOver> {
+struct Epi<kFwdLambda> {
     float *y;
-    __device__ void full(int64_t row, float s) { y[row] = s; }
+    float *acc;
+    float alpha;
+    unsigned long long np = 0;
+    float mx = 0.0f;
+    __device__ float2 pre(int64_t row) const { return make_float2(y[row], acc[row]); }
+    __device__ void full(int64_t row, float s, float2 p, int64_t) {
+        acc[row] = p.y + alpha * p.x;
+        y[row] = s;
+    }
 };
 
 template <int kMode>
-__device__ __forceinline__ Epi<kMode> make_epi(const GatherArgs &a) {
-    if constexpr (kMode == kBack) return Epi<kBack>{a.y, a.inv_b, a.c.off};
-    else if constexpr (kMode == kFwdAcc) return Epi<kFwdAcc>{a.y};
-    else return Epi<kFwdOver>{a.y};
+__device__ __forceinline__ Epi<kMode> make_epi(const GatherArgs &a, float theta) {
+    if constexpr (kMode == kBack) return Epi<kBack>{a.y, a.inv_b};
+    else if constexpr (kMode == kFwdAcc) return Epi<kFwdAcc>{a.y, a.aux, theta, a.alpha};
+    else return Epi<kFwdLambda>{a.y, a.aux, a.alpha};
 }
 
-// Writes the workgroup's statistic (max or n_p) to its slot.
+// Writes the workgroup's max and n_p to its slots.
 template <int kMode>
 __device__ __forceinline__ void flush_stat(const GatherArgs &a, Epi<kMode> &e) {
-    if constexpr (kMode == kBack) {
-        __shared__ unsigned long long lds[4];
-        const unsigned long long v = block_sum<unsigned long long>(e.np, lds);
-        if (threadIdx.x == 0 && a.blk_u) a.blk_u[blockIdx.x] = v;
-    } else if constexpr (kMode == kFwdAcc) {
-        __shared__ float ldsf[4];
-        const float m = block_max_f(e.mx, ldsf);
-        if (threadIdx.x == 0 && a.blk_f) a.blk_f[blockIdx.x] = m;
+    __shared__ unsigned long long lds[4];
+    __shared__ float ldsf[4];
+    const unsigned long long v = block_sum<unsigned long long>(e.np, lds);
+    const float m = block_max_f(e.mx, ldsf);
+    if (threadIdx.x == 0) {
+        if (a.blk_u) a.blk_u[blockIdx.x] = v;
+        if (a.blk_f) a.blk_f[blockIdx.x] = m;
     }
 }
 
-// Terms w(e) * x(col(e)) of entries e0 + lane + 64 k (k < kPerLane, < ne);
-// all loads of a lane are issued before any is used.
-template <bool kUnit>
+// Terms of entries e0 + lane + 64 k (k < kPerLane, < ne): w(e) * x(col(e)),
+// where the back gather keeps x only above the threshold.  All loads of a
+// lane are issued before any is used.
+template <bool kUnit, bool kThr>
 __device__ __forceinline__ void load_terms(const CsrView &c, const float *__restrict__ x, int64_t e0, int ne,
-                                           float (&t)[kPerLane]) {
+                                           float theta, float (&t)[kPerLane]) {
     const int lane = threadIdx.x & (kWave - 1);
     int32_t ci[kPerLane];
     float wv[kPerLane];
@@ -143,37 +166,62 @@ __device__ __forceinline__ void load_terms(const CsrView &c, const float *__rest
     }
 #pragma unroll
     for (int k = 0; k < kPerLane; ++k) {
-        const float v = ci[k] >= 0 ? x[ci[k]] : 0.0f;
+        float v = ci[k] >= 0 ? x[ci[k]] : 0.0f;
+        if constexpr (kThr) v = v > theta ? v : 0.0f;
         t[k] = kUnit ? v : v * wv[k];
     }
 }
 
-// The wave's share of the schedule (grid-stride over items).
+// The wave's share of the schedule (grid-stride over items).  Every load of
+// an item that does not depend on another (entries, row bounds, epilogue
+// inputs, the next item's descriptor) is issued before the first wait.
 template <bool kUnit, int kMode>
-__device__ __forceinline__ void spmv_items(const GatherArgs &a, float *prod, Epi<kMode> &epi) {
+__device__ __forceinline__ void spmv_items(const GatherArgs &a, float theta, float *prod, Epi<kMode> &epi) {
+    constexpr int kRowsPerLane = kMaxRowsPerItem / kWave;
+    constexpr bool kThr = kMode == kBack;
     const CsrView &c = a.c;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    WorkItem next = wave0 < c.n_items ? c.items[wave0] : WorkItem{0, 0};
     for (int64_t it = wave0; it < c.n_items; it += stride) {
-        const WorkItem item = c.items[it];
+        const WorkItem item = next;
+        if (it + stride < c.n_items) next = c.items[it + stride];
         float t[kPerLane];
         if (item.n > 0) {
             const int64_t r0 = item.row;
             const int64_t e0 = c.off[r0];
             const int ne = (int)(c.off[r0 + item.n] - e0);
-            load_terms<kUnit>(c, a.x, e0, ne, t);
+            int64_t rb[kRowsPerLane], re[kRowsPerLane];
+            float2 pre[kRowsPerLane];
+#pragma unroll
+            for (int q = 0; q < kRowsPerLane; ++q) {
+                const int j = lane + q * kWave;
+                rb[q] = re[q] = e0;
+                pre[q] = make_float2(0.0f, 0.0f);
+                if (j < item.n) {
+                    rb[q] = c.off[r0 + j];
+                    re[q] = c.off[r0 + j + 1];
+                    pre[q] = epi.pre(r0 + j);
+                }
+            }
+            load_terms<kUnit, kThr>(c, a.x, e0, ne, theta, t);
 #pragma unroll
             for (int k = 0; k < kPerLane; ++k) {
                 const int i = lane + k * kWave;
                 if (i < ne) prod[i] = t[k];
             }
             wave_lds_sync();
-            for (int j = lane; j < item.n; j += kWave) {
-                const int b0 = (int)(c.off[r0 + j] - e0), b1 = (int)(c.off[r0 + j + 1] - e0);
-                float s = 0.0f;
-                for (int e = b0; e < b1; ++e) s += prod[e];
-                epi.full(r0 + j, s);
+#pragma unroll
+            for (int q = 0; q < kRowsPerLane; ++q) {
+                const int j = lane + q * kWave;
+                if (j < item.n) {
+                    const int b0 = (int)(rb[q] - e0), b1 = (int)(re[q] - e0);
+                    float s = 0.0f;
+#pragma unroll 4
+                    for (int e = b0; e < b1; ++e) s += prod[e];
+                    epi.full(r0 + j, s, pre[q], b1 - b0);
+                }
             }
             wave_lds_sync();
         } else {
@@ -181,25 +229,30 @@ __device__ __forceinline__ void spmv_items(const GatherArgs &a, float *prod, Epi
             const int64_t rb = c.off[row], re = c.off[row + 1];
             const int64_t e0 = rb + (int64_t)(-item.n) * kItemEdges;
             const int ne = (int)(re - e0 < kItemEdges ? re - e0 : kItemEdges);
-            load_terms<kUnit>(c, a.x, e0, ne, t);
+            const bool whole = re - rb <= kItemEdges;
+            const float2 pre = whole ? epi.pre(row) : make_float2(0.0f, 0.0f);
+            load_terms<kUnit, kThr>(c, a.x, e0, ne, theta, t);
             float s = 0.0f;
 #pragma unroll
             for (int k = 0; k < kPerLane; ++k) s += t[k];
             s = wave_sum(s);
             if (lane == 0) {
-                if (re - rb <= kItemEdges) epi.full(row, s);
+                if (whole) epi.full(row, s, pre, re - rb);
                 else a.part[it] = s;
             }
         }
     }
 }
 
+__device__ __forceinline__ float round_theta(const GatherArgs &a) { return a.ctl ? a.ctl->theta : a.theta; }
+
 template <bool kUnit, int kMode>
 __global__ void __launch_bounds__(kBlock) k_gather(GatherArgs a) {
     __shared__ float prod[kWavesPerBlock][kItemEdges];
     if (a.ctl && a.ctl->done) return;
-    Epi<kMode> epi = make_epi<kMode>(a);
-    spmv_items<kUnit, kMode>(a, prod[threadIdx.x >> 6], epi);
+    const float theta = round_theta(a);
+    Epi<kMode> epi = make_epi<kMode>(a, theta);
+    spmv_items<kUnit, kMode>(a, theta, prod[threadIdx.x >> 6], epi);
     flush_stat<kMode>(a, epi);
 }
 
@@ -207,16 +260,17 @@ __global__ void __launch_bounds__(kBlock) k_gather(GatherArgs a) {
 template <int kMode>
 __global__ void __launch_bounds__(kBlock) k_fix(GatherArgs a) {
     if (a.ctl && a.ctl->done) return;
+    const float theta = round_theta(a);
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
-    Epi<kMode> epi = make_epi<kMode>(a);
+    Epi<kMode> epi = make_epi<kMode>(a, theta);
     for (int64_t i = wave0; i < a.c.n_split; i += stride) {
         const SplitRow sr = a.c.split[i];
         float s = 0.0f;
         for (int ch = lane; ch < sr.nch; ch += kWave) s += a.part[sr.first_item + ch];
         s = wave_sum(s);
-        if (lane == 0) epi.full(sr.row, s);
+        if (lane == 0) epi.full(sr.row, s, epi.pre(sr.row), a.c.off[sr.row + 1] - a.c.off[sr.row]);
     }
     flush_stat<kMode>(a, epi);
 }
@@ -241,61 +295,32 @@ __global__ void k_query_init(Control *ctl, float *r, int32_t source, float eps_f
     ctl->last_max = 1.0f;
 }
 
-// U side of a round (see file comment).
-__global__ void __launch_bounds__(kBlock) k_u_push(const Control *ctl, float *__restrict__ r, float *__restrict__ pi,
-                                                   float *__restrict__ rho, const float *__restrict__ c_d,
-                                                   const float *__restrict__ c_s, const int64_t *__restrict__ off,
-                                                   int64_t n_u, float alpha, unsigned long long *blk_np) {
-    __shared__ unsigned long long lds[4];
-    if (ctl->done) return;
-    const float theta = ctl->theta;
-    unsigned long long np = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_u; j += stride) {
-        const float x = r[j];
-        float a = 0.0f, b = 0.0f;
-        if (x > theta) {
-            pi[j] += alpha * x;
-            a = c_d[j] * x;
-            b = c_s[j] * x;
-            r[j] = 0.0f;
-            np += (unsigned long long)(off[j + 1] - off[j]);
-        }
-        rho[j] = a;
-        rho[n_u + j] = b;
-    }
-    np = block_sum<unsigned long long>(np, lds);
-    if (threadIdx.x == 0) blk_np[blockIdx.x] = np;
-}
-
 // Per-workgroup partial arrays read by k_control.
 struct Partials {
     const float *max_a;
     int n_max_a;
     const float *max_b;
     int n_max_b;
-    const unsigned long long *np_a;
-    int n_np_a;
-    const unsigned long long *np_b;
-    int n_np_b;
-    const unsigned long long *np_c;
-    int n_np_c;
+    const unsigned long long *np[4];
+    int n_np[4];
 };
 
+constexpr int kControlThreads = 1024;
+
 // End of a round: max_u r(u), n_p, then Algorithm 4's stop / switch rule.
-__global__ void __launch_bounds__(kBlock) k_control(Control *ctl, Partials p, Rule rule) {
-    __shared__ float ldsf[4];
-    __shared__ unsigned long long lds[4];
+__global__ void __launch_bounds__(kControlThreads) k_control(Control *ctl, Partials p, Rule rule) {
+    __shared__ float ldsf[kControlThreads / kWave];
+    __shared__ unsigned long long lds[kControlThreads / kWave];
     if (ctl->done) return;
     float m = 0.0f;
     unsigned long long np = 0;
-    for (int i = threadIdx.x; i < p.n_max_a; i += kBlock) m = fmaxf(m, p.max_a[i]);
-    for (int i = threadIdx.x; i < p.n_max_b; i += kBlock) m = fmaxf(m, p.max_b[i]);
-    for (int i = threadIdx.x; i < p.n_np_a; i += kBlock) np += p.np_a[i];
-    for (int i = threadIdx.x; i < p.n_np_b; i += kBlock) np += p.np_b[i];
-    for (int i = threadIdx.x; i < p.n_np_c; i += kBlock) np += p.np_c[i];
-    m = block_max_f(m, ldsf);
-    np = block_sum<unsigned long long>(np, lds);
+    for (int i = threadIdx.x; i < p.n_max_a; i += kControlThreads) m = fmaxf(m, p.max_a[i]);
+    for (int i = threadIdx.x; i < p.n_max_b; i += kControlThreads) m = fmaxf(m, p.max_b[i]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int i = threadIdx.x; i < p.n_np[k]; i += kControlThreads) np += p.np[k][i];
+    m = block_max_n<kControlThreads / kWave>(m, ldsf);
+    np = block_sum_u64_n<kControlThreads / kWave>(np, lds);
     if (threadIdx.x != 0) return;
     const unsigned long long n_p = ctl->n_p + np;
     const int iter = ctl->iter + 1;
@@ -317,18 +342,6 @@ __global__ void __launch_bounds__(kBlock) k_control(Control *ctl, Partials p, Ru
             ctl->theta = 0.0f;
             ctl->switch_iter = iter;
         }
-    }
-}
-
-// Theorem 3 sweep, U side: acc += alpha y; rho = (c_d y, c_s y).
-__global__ void k_lambda_u(const float *__restrict__ y, float *__restrict__ acc, float *__restrict__ rho,
-                           const float *__restrict__ c_d, const float *__restrict__ c_s, int64_t n_u, float alpha) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_u; j += stride) {
-        const float x = y[j];
-        acc[j] += alpha * x;
-        rho[j] = c_d[j] * x;
-        rho[n_u + j] = c_s[j] * x;
     }
 }
 
@@ -367,12 +380,11 @@ Rule make_rule(const Graph &g) {
 
 // Launch shapes of one round.
 struct Plan {
-    unsigned u, back, back_fix, fwd, fwd_fix;
+    unsigned back, back_fix, fwd, fwd_fix;
 };
 
 Plan make_plan(const Graph &g) {
     Plan p;
-    p.u = capped(g.n_u, kBlock, g.grid_cap);
     p.back = g.back.n_items ? capped(g.back.n_items, kWavesPerBlock, g.grid_cap) : 0;
     p.back_fix = g.back.n_split ? capped(g.back.n_split, kWavesPerBlock, g.grid_cap) : 0;
     p.fwd = capped(g.fwd.n_items, kWavesPerBlock, g.grid_cap);
@@ -380,11 +392,18 @@ Plan make_plan(const Graph &g) {
     return p;
 }
 
+// Launches a gather and its fix-up; the fix-up's partials go grid_cap slots
+// after the gather's.
 template <int kMode>
-void launch_gather(const Graph &g, const GatherArgs &a, unsigned grid, unsigned grid_fix, hipStream_t s) {
+void launch_gather(Graph &g, bool unit, const GatherArgs &a, unsigned grid, unsigned grid_fix, hipStream_t s,
+                   int prof_kind = -1, double prof_bytes = 0.0) {
     if (grid) {
-        if (g.unit) hipLaunchKernelGGL((k_gather<true, kMode>), dim3(grid), dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((k_gather<false, kMode>), dim3(grid), dim3(kBlock), 0, s, a);
+        auto go = [&] {
+            if (unit) hipLaunchKernelGGL((k_gather<true, kMode>), dim3(grid), dim3(kBlock), 0, s, a);
+            else hipLaunchKernelGGL((k_gather<false, kMode>), dim3(grid), dim3(kBlock), 0, s, a);
+        };
+        if (prof_kind >= 0) profiled(g.prof, prof_kind, prof_bytes, s, go);
+        else go();
     }
     if (grid_fix) {
         GatherArgs b = a;
@@ -406,12 +425,11 @@ void alloc_query_state(Graph &g) {
     auto n1 = [](int64_t n) { return (size_t)(n > 0 ? n : 1); };
     g.q_r = (float *)dev_alloc(g, n1(g.n_u) * 4, "query residues");
     g.q_pi = (float *)dev_alloc(g, n1(g.n_u) * 4, "query reserves");
-    g.q_rho = (float *)dev_alloc(g, n1(2 * g.n_u) * 4, "query push buffer");
     g.q_z = (float *)dev_alloc(g, n1(g.n_v + g.n_a) * 4, "query V/attribute residues");
     g.q_ctl = (Control *)dev_alloc(g, sizeof(Control), "query control");
     g.part_item = (float *)dev_alloc(g, n1(std::max(g.fwd.n_items, g.back.n_items)) * 4, "chunk partials");
     g.blk_max = (float *)dev_alloc(g, (size_t)2 * g.grid_cap * 4, "workgroup maxima");
-    g.blk_np = (unsigned long long *)dev_alloc(g, (size_t)3 * g.grid_cap * 8, "workgroup push counts");
+    g.blk_np = (unsigned long long *)dev_alloc(g, (size_t)4 * g.grid_cap * 8, "workgroup push counts");
 }
 
 void single_query_init(Graph &g, int32_t source, float eps_f, int32_t max_iters, hipStream_t s) {
@@ -423,15 +441,20 @@ void single_query_init(Graph &g, int32_t source, float eps_f, int32_t max_iters,
 
 void single_query_round(Graph &g, hipStream_t s) {
     const Plan p = make_plan(g);
-    hipLaunchKernelGGL(k_u_push, dim3(p.u), dim3(kBlock), 0, s, g.q_ctl, g.q_r, g.q_pi, g.q_rho, g.c_d, g.c_s, g.fwd.off,
-                       g.n_u, (float)g.alpha, g.blk_np);
-    GatherArgs back{view(g.back), g.q_rho, g.q_z, g.inv_b, g.part_item, g.q_ctl, nullptr, g.blk_np + g.grid_cap};
-    launch_gather<kBack>(g, back, p.back, p.back_fix, s);
-    GatherArgs fwd{view(g.fwd), g.q_z, g.q_r, nullptr, g.part_item, g.q_ctl, g.blk_max, nullptr};
-    launch_gather<kFwdAcc>(g, fwd, p.fwd, p.fwd_fix, s);
+    GatherArgs back{view(g.back), g.q_r, g.q_z, nullptr, g.inv_b, g.part_item, g.q_ctl, 0.0f, (float)g.alpha,
+                    nullptr, g.blk_np};
+    // Algorithmic bytes: CSR entries (column, weight) and gathered residue per
+    // entry, offsets and per-row state per row.
+    const double wb = g.fwd.w ? 8.0 : 4.0;
+    launch_gather<kBack>(g, false, back, p.back, p.back_fix, s, 0,
+                         12.0 * g.back.nnz + 16.0 * g.back.n_rows);
+    GatherArgs fwd{view(g.fwd), g.q_z, g.q_r, g.q_pi, nullptr, g.part_item, g.q_ctl, 0.0f, (float)g.alpha,
+                   g.blk_max, g.blk_np + 2 * g.grid_cap};
+    launch_gather<kFwdAcc>(g, g.unit, fwd, p.fwd, p.fwd_fix, s, 1, (wb + 4.0) * g.fwd.nnz + 24.0 * g.fwd.n_rows);
     Partials part{g.blk_max, (int)p.fwd, g.blk_max + g.grid_cap, (int)p.fwd_fix,
-                  g.blk_np, (int)p.u, g.blk_np + g.grid_cap, (int)p.back, g.blk_np + 2 * g.grid_cap, (int)p.back_fix};
-    hipLaunchKernelGGL(k_control, dim3(1), dim3(kBlock), 0, s, g.q_ctl, part, make_rule(g));
+                  {g.blk_np, g.blk_np + g.grid_cap, g.blk_np + 2 * g.grid_cap, g.blk_np + 3 * g.grid_cap},
+                  {(int)p.back, (int)p.back_fix, (int)p.fwd, (int)p.fwd_fix}};
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(kControlThreads), 0, s, g.q_ctl, part, make_rule(g));
     check_hip(hipGetLastError(), "round launch");
 }
 
@@ -450,23 +473,24 @@ void single_query_stats(Graph &g, double *sum_r, hipStream_t s) {
 }
 
 // Theorem 3 (Eq. 6): PI from the all-ones row vector for T rounds,
-// lambda = max_i pi_T(u_i) + |U| (1-alpha)^T.
+// pi_T = sum_{l<T} alpha (1-alpha)^l 1 P^l, lambda = max_i pi_T(u_i) + |U| (1-alpha)^T.
+// Each sweep is the round above with every U node pushed (threshold -1).
 double compute_lambda(Graph &g, int T, hipStream_t s) {
-    float *y = g.q_r, *acc = g.q_pi, *rho = g.q_rho, *z = g.q_z;
+    float *y = g.q_r, *acc = g.q_pi, *z = g.q_z;
     const Plan p = make_plan(g);
     launch_fill_f32(y, 1.0f, g.n_u, s);
     launch_fill_f32(acc, 0.0f, g.n_u, s);
+    launch_fill_f32(z, 0.0f, g.n_v + g.n_a, s);
     for (int t = 0; t < T; ++t) {
-        hipLaunchKernelGGL(k_lambda_u, dim3(p.u), dim3(kBlock), 0, s, y, acc, rho, g.c_d, g.c_s, g.n_u, (float)g.alpha);
-        GatherArgs back{view(g.back), rho, z, g.inv_b, g.part_item, nullptr, nullptr, nullptr};
-        launch_gather<kBack>(g, back, p.back, p.back_fix, s);
-        if (!p.back) launch_fill_f32(y, 0.0f, g.n_u, s);
-        GatherArgs fwd{view(g.fwd), z, y, nullptr, g.part_item, nullptr, nullptr, nullptr};
-        if (p.back) launch_gather<kFwdOver>(g, fwd, p.fwd, p.fwd_fix, s);
+        GatherArgs back{view(g.back), y, z, nullptr, g.inv_b, g.part_item, nullptr, -1.0f, (float)g.alpha, nullptr,
+                        nullptr};
+        launch_gather<kBack>(g, false, back, p.back, p.back_fix, s);
+        GatherArgs fwd{view(g.fwd), z, y, acc, nullptr, g.part_item, nullptr, -1.0f, (float)g.alpha, nullptr, nullptr};
+        launch_gather<kFwdLambda>(g, g.unit, fwd, p.fwd, p.fwd_fix, s);
         check_hip(hipGetLastError(), "lambda launch");
     }
     const unsigned grid = capped(g.n_u, kBlock, g.grid_cap);
-    hipLaunchKernelGGL(k_max_f32, dim3(grid), dim3(kBlock), 0, s, acc, g.n_u, g.blk_max);  // grid <= grid_cap
+    hipLaunchKernelGGL(k_max_f32, dim3(grid), dim3(kBlock), 0, s, acc, g.n_u, g.blk_max);
     std::vector<float> h(grid);
     check_hip(hipMemcpyAsync(h.data(), g.blk_max, grid * sizeof(float), hipMemcpyDeviceToHost, s), "lambda D2H");
     check_hip(hipStreamSynchronize(s), "lambda");

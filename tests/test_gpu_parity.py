@@ -208,3 +208,30 @@ def test_errors(torch_cuda, ahpp, tiny, tiny_graph):
     with pytest.raises(ahpp.AhppError):
         ahpp.ahpp_graph_load(tiny_graph.n_u, tiny_graph.n_v, tiny_graph.n_attr, tiny_graph.edge_u, tiny_graph.edge_v,
                              tiny_graph.edge_w, tiny_graph.assoc_u, tiny_graph.assoc_a, bad_w)
+
+
+def test_batch_weighted_ragged_tiles(torch_cuda, ahpp):
+    """Batches spanning several 64-query tiles with a ragged last tile, mixed eps."""
+    g = synth.make_custom(5000, 2000, 40000, 200, 6, seed=616, unit_weights=False)
+    og = O.OracleGraph.from_graph(g)
+    _say("load weighted 5000-node graph for batches")
+    dg = ahpp.load_graph(g)
+    srcs = np.concatenate([synth.mixed_batch_queries(g, 100, 31), synth.degree_queries(g, 30, 32)])
+    eps = np.where(np.arange(srcs.size) % 3 == 0, 1e-7, np.where(np.arange(srcs.size) % 3 == 1, 1e-5, 1e-6))
+    _say("batch of", srcs.size)
+    res = ahpp.ahpp_query_batch(dg, srcs, eps, k=25)
+    pis = res.pi.cpu().numpy()
+    for q in range(0, srcs.size, 7):
+        s = int(srcs[q])
+        exact, _ = og.power_series(s)
+        chk = O.check_query(exact, pis[q].astype(np.float64), eps[q], tol=TOL, k=25, source=s,
+                            topk_ids=res.topk_idx[q, : int(res.topk_n[q].item())].cpu().numpy())
+        assert chk.ok, (q, s, chk.detail)
+        st = res.stats[q]
+        assert st["converged"] == 1 and st["max_residual"] <= eps[q] / dg.lam * (1 + 1e-6)
+        assert abs(float(pis[q].sum()) + st["sum_residual"] - 1) < 1e-5
+    # Same queries alone: results agree within the guarantee.
+    for q in (0, 64, 129):
+        alone = ahpp.ahpp_query(dg, int(srcs[q]), float(eps[q])).pi.cpu().numpy()
+        assert np.abs(alone - pis[q]).max() <= eps[q] + TOL
+    dg.free()
