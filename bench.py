@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "AHPP queries/s at ε=1e-7, batched vs plain push; p50/p99 query latency"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_fwd_gather_m1_traffic.json")
+TRAFFIC_FILES = {"kb_gather<back>": os.path.join(ROOT, "profiles", "kb_gather_back_m1_traffic.json"),
+                 "kb_gather<fwd>": os.path.join(ROOT, "profiles", "kb_gather_fwd_m1_traffic.json")}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2512_11606_amd", "csrc", "batch.hip")
 
 
@@ -51,10 +52,11 @@ def _source_hash(path):
 def _traffic(kernel_kind_name):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel source; else None."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES.get(kernel_kind_name)
+    if not path or not os.path.exists(path):
         return None
     try:
-        d = json.load(open(TRAFFIC_FILE))
+        d = json.load(open(path))
     except (OSError, ValueError):
         return None
     if d.get("kernel") != kernel_kind_name or d.get("source_sha256_16") != _source_hash(KERNEL_SOURCE):
