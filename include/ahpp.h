@@ -160,6 +160,51 @@ ahpp_status_t ahpp_query_batch(ahpp_graph_t *g, int32_t n_q, const int32_t *sour
 ahpp_status_t ahpp_topk(const ahpp_graph_t *g, const float *pi, int32_t k, int32_t exclude,
                         int32_t *idx_out, float *val_out, int32_t *n_out, void *hip_stream);
 
+/* Serving engine: queries that arrive over time share the device with
+ * continuous batching.  The engine holds `slots` concurrent queries (lanes of
+ * 64-query tiles, each with its own residues, reserves, threshold, phase and
+ * stop rule, exactly as ahpp_query_batch); a query waits in a host queue
+ * until a slot is free, then runs in the same rounds as every other running
+ * query, and leaves its slot as soon as its stop rule holds.  Results are the
+ * eps-approximate vectors of Eq. 4 (same guarantee as ahpp_query) reduced to
+ * their top-k.  One thread at a time per server. */
+typedef struct ahpp_server ahpp_server_t;
+
+/* Creates a server on graph g (which must outlive it).
+ *   max_device_bytes: budget for per-query device state; slots = 64 * the
+ *     number of tiles that fit (<= 0: a quarter of the free memory), >= 64.
+ *   k: top-k size of every result, 1..2048.  max_iters: round cap per query
+ *     (<= 0: 100000).  keep_pi: nonzero keeps each finished query's full
+ *     vector until its result is read (ahpp_server_results pi_out).
+ * Errors: INVALID_ARG, OUT_OF_MEMORY (budget below one tile), DEVICE. */
+ahpp_status_t ahpp_server_create(ahpp_graph_t *g, int64_t max_device_bytes, int32_t k, int32_t max_iters,
+                                 int32_t keep_pi, ahpp_server_t **out);
+void ahpp_server_free(ahpp_server_t *s);
+
+/* Queues one query (host only, no device work): source in U, eps > 0 (Eq. 4);
+ * `tag` comes back with its result. */
+ahpp_status_t ahpp_server_submit(ahpp_server_t *s, int64_t tag, int32_t source, double eps);
+
+/* One scheduling step on hip_stream: admit queued queries into free slots,
+ * run `rounds` rounds of Algorithm 4 for every running query, then collect
+ * the queries whose stop rule held (top-k on the device, copied to the host).
+ * Blocks until the step is done.  *n_ready (nullable): results waiting. */
+ahpp_status_t ahpp_server_step(ahpp_server_t *s, int32_t rounds, int32_t *n_ready, void *hip_stream);
+
+/* Pops up to max_n finished queries in completion order into host arrays:
+ * tags[max_n], topk_idx[max_n * k], topk_val[max_n * k], topk_n[max_n],
+ * stats[max_n] (nullable; ms = wall time from the step that admitted the
+ * query to the end of the step that collected it),
+ * pi_out (device float[max_n * n_u], nullable; requires keep_pi).
+ * *n_out = number popped. */
+ahpp_status_t ahpp_server_results(ahpp_server_t *s, int32_t max_n, int64_t *tags, int32_t *topk_idx,
+                                  float *topk_val, int32_t *topk_n, ahpp_stats_t *stats, float *pi_out,
+                                  int32_t *n_out, void *hip_stream);
+
+/* Current counts (host pointers, each nullable). */
+ahpp_status_t ahpp_server_info(const ahpp_server_t *s, int32_t *slots, int32_t *running, int32_t *queued,
+                               int32_t *ready);
+
 /* Kernel timing (diagnostics, used by the benchmark's roofline figures).
  * While enabled, the library brackets every launch of its gather kernels with
  * HIP events on the launch stream and adds, per kernel kind, the launch

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libahpp.so")
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CONVERGED = 0, -1, -2, -3, -4
 
 EXPORTED = ("ahpp_graph_load", "ahpp_graph_info", "ahpp_graph_free", "ahpp_query", "ahpp_query_batch", "ahpp_topk",
-            "ahpp_profile_enable", "ahpp_profile_read", "ahpp_last_error")
+            "ahpp_server_create", "ahpp_server_free", "ahpp_server_submit", "ahpp_server_step",
+            "ahpp_server_results", "ahpp_server_info", "ahpp_profile_enable", "ahpp_profile_read", "ahpp_last_error")
 
 # Kernel kinds of ahpp_profile_read.
 PROF_SINGLE_BACK, PROF_SINGLE_FWD, PROF_BATCH_BACK, PROF_BATCH_FWD = 0, 1, 2, 3
@@ -84,6 +85,18 @@ def load_library(path: str = LIB_PATH):
     lib.ahpp_query_batch.argtypes = [P, i32, P, P, i32, P, i32, P, P, P, P, P]
     lib.ahpp_topk.restype = ctypes.c_int
     lib.ahpp_topk.argtypes = [P, P, i32, i32, P, P, P, P]
+    lib.ahpp_server_create.restype = ctypes.c_int
+    lib.ahpp_server_create.argtypes = [P, i64, i32, i32, i32, ctypes.POINTER(ctypes.c_void_p)]
+    lib.ahpp_server_free.restype = None
+    lib.ahpp_server_free.argtypes = [P]
+    lib.ahpp_server_submit.restype = ctypes.c_int
+    lib.ahpp_server_submit.argtypes = [P, i64, i32, dbl]
+    lib.ahpp_server_step.restype = ctypes.c_int
+    lib.ahpp_server_step.argtypes = [P, i32, P, P]
+    lib.ahpp_server_results.restype = ctypes.c_int
+    lib.ahpp_server_results.argtypes = [P, i32, P, P, P, P, P, P, P, P]
+    lib.ahpp_server_info.restype = ctypes.c_int
+    lib.ahpp_server_info.argtypes = [P, P, P, P, P]
     lib.ahpp_profile_enable.restype = ctypes.c_int
     lib.ahpp_profile_enable.argtypes = [P, i32]
     lib.ahpp_profile_read.restype = ctypes.c_int
@@ -253,3 +266,65 @@ def ahpp_profile_read(g: Graph, kind: int) -> dict:
     by = ctypes.c_double(0.0)
     _check(load_library().ahpp_profile_read(g._h, int(kind), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
     return {"launches": int(n.value), "ms": float(ms.value), "bytes": float(by.value)}
+
+
+class Server:
+    """Continuous-batching server over a loaded graph (ahpp_server_* in ahpp.h)."""
+
+    def __init__(self, g: Graph, k: int, max_device_bytes: int = 0, max_iters: int = 0, keep_pi: bool = False):
+        self.g = g
+        self.k = int(k)
+        self.keep_pi = bool(keep_pi)
+        h = ctypes.c_void_p()
+        _check(load_library().ahpp_server_create(g._h, int(max_device_bytes), self.k, int(max_iters),
+                                                 1 if keep_pi else 0, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h:
+            load_library().ahpp_server_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, tag: int, source: int, eps: float) -> None:
+        _check(load_library().ahpp_server_submit(self._h, int(tag), int(source), float(eps)))
+
+    def step(self, rounds: int, stream=None) -> int:
+        n = ctypes.c_int32(0)
+        _check(load_library().ahpp_server_step(self._h, int(rounds), ctypes.byref(n), _stream(self.g.device, stream)))
+        return int(n.value)
+
+    def info(self) -> dict:
+        v = [ctypes.c_int32(0) for _ in range(4)]
+        _check(load_library().ahpp_server_info(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("slots", "running", "queued", "ready"), (int(x.value) for x in v)))
+
+    def results(self, max_n: int = 1024, want_pi: bool = False, stream=None) -> list:
+        """Finished queries: list of dicts (tag, topk_idx, topk_val, stats, pi)."""
+        import torch
+        max_n = int(max_n)
+        tags = np.zeros(max_n, np.int64)
+        idx = np.zeros((max_n, self.k), np.int32)
+        val = np.zeros((max_n, self.k), np.float32)
+        tn = np.zeros(max_n, np.int32)
+        st = (Stats * max(max_n, 1))()
+        pi = None
+        if want_pi:
+            if not self.keep_pi:
+                raise ValueError("server was created without keep_pi")
+            pi = torch.empty((max_n, self.g.n_u), dtype=torch.float32, device=torch.device("cuda", self.g.device))
+        n = ctypes.c_int32(0)
+        _check(load_library().ahpp_server_results(self._h, max_n, _np_ptr(tags), _np_ptr(idx), _np_ptr(val),
+                                                  _np_ptr(tn), ctypes.cast(st, ctypes.c_void_p), _dev_ptr(pi),
+                                                  ctypes.byref(n), _stream(self.g.device, stream)))
+        out = []
+        for i in range(int(n.value)):
+            m = int(tn[i])
+            out.append({"tag": int(tags[i]), "topk_idx": idx[i, :m].copy(), "topk_val": val[i, :m].copy(),
+                        "stats": st[i].as_dict(), "pi": None if pi is None else pi[i]})
+        return out

@@ -4,8 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <deque>
 #include <string>
 #include <vector>
+
+#include "../../include/ahpp.h"
 
 namespace ahpp {
 
@@ -200,18 +203,77 @@ void single_query_stats(Graph &g, double *sum_r, hipStream_t s);
 double compute_lambda(Graph &g, int T, hipStream_t s);
 
 // batch.hip
-void ensure_batch_state(Graph &g, int tiles);
-void free_batch_state(Graph &g);
-// Initialises tiles [t0, t0 + nt): lane q of tile t gets query t * kTileQ + q
+struct AdmitReq {
+    int32_t tile, lane, source;
+    float eps_f;
+};
+// Device bytes of one tile (with or without the query-major score buffer).
+int64_t batch_tile_bytes(const Graph &g, bool with_out);
+void ensure_batch_state(Graph &g, BatchState &b, int tiles, bool with_out);
+void free_batch_state(BatchState &b);
+// Initialises tiles [0, nt): lane q of tile t gets query t * kTileQ + q
 // (sources / eps_f host arrays of n_q entries; lanes beyond n_q are empty).
-void batch_init(Graph &g, int t0, int nt, const int32_t *sources, const float *eps_f, int64_t n_q,
+void batch_init(Graph &g, BatchState &b, int nt, const int32_t *sources, const float *eps_f, int64_t n_q,
                 int32_t max_iters, hipStream_t s);
-void batch_round(Graph &g, int t0, int nt, hipStream_t s);
+void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s);
 // Copies tile scores to query-major rows: out[(t*kTileQ + q) * n_u + u] for
 // the first n_rows rows.
-void batch_scores(Graph &g, int t0, int nt, int64_t n_rows, float *out, hipStream_t s);
+void batch_scores(Graph &g, BatchState &b, int nt, int64_t n_rows, float *out, hipStream_t s);
 // Per-lane residue sums of tiles [t0, t0 + nt) into host sums[(t-t0)*kTileQ + q].
-void batch_resid_sums(Graph &g, int t0, int nt, double *sums, hipStream_t s);
+void batch_resid_sums(Graph &g, BatchState &b, int t0, int nt, double *sums, hipStream_t s);
+// Serving: all lanes empty; admit queries into lanes (clears their columns);
+// copy selected lanes of one tile to query-major rows.
+void batch_empty(Graph &g, BatchState &b, int nt, hipStream_t s);
+void batch_admit(Graph &g, BatchState &b, const std::vector<AdmitReq> &reqs, int32_t max_iters, hipStream_t s);
+void batch_lanes_out(Graph &g, BatchState &b, int tile, const int32_t *d_lanes, int n_sel, float *out,
+                     hipStream_t s);
+
+// serve.hip: continuous batching over the lanes of a private batch state.
+class Server {
+  public:
+    Server(Graph &g, int64_t max_device_bytes, int32_t k, int32_t max_iters, bool keep_pi);
+    ~Server();
+    void submit(int64_t tag, int32_t source, double eps);
+    int step(int rounds, hipStream_t s);
+    int results(int max_n, int64_t *tags, int32_t *topk_idx, float *topk_val, int32_t *topk_n, ahpp_stats_t *stats,
+                float *pi_out, hipStream_t s);
+    void info(int32_t *slots, int32_t *running, int32_t *queued, int32_t *ready) const;
+    Graph &graph() { return g_; }
+
+  private:
+    struct Pending {
+        int64_t tag;
+        int32_t source;
+        double eps;
+    };
+    struct Lane {
+        bool busy = false;
+        int64_t tag = 0;
+        int32_t source = -1;
+        double t_admit = 0.0;
+    };
+    struct Result {
+        int64_t tag;
+        std::vector<int32_t> idx;
+        std::vector<float> val;
+        ahpp_stats_t st;
+        float *d_pi;
+    };
+    Graph &g_;
+    BatchState b_;
+    int32_t k_, max_iters_;
+    bool keep_pi_;
+    std::vector<Lane> lanes_;
+    std::deque<Pending> queue_;
+    std::deque<Result> ready_;
+    float *d_scores_ = nullptr;     // [kTileQ][n_u]
+    int32_t *d_sel_ = nullptr;      // [2][kTileQ]: lanes, then sources
+    int32_t *d_idx_ = nullptr;      // [kTileQ][k]
+    float *d_val_ = nullptr;        // [kTileQ][k]
+    int32_t *d_n_ = nullptr;        // [kTileQ]
+    void *d_tk_ = nullptr;
+    int64_t own_bytes_ = 0;
+};
 
 // topk.hip
 size_t topk_scratch_bytes(int64_t n_q);

@@ -345,6 +345,62 @@ __global__ void __launch_bounds__(kWave) kb_init(TileCtl *ctl, float *r, int64_t
     if (q == 0) ctl[t].all_done = running == 0ull ? 1 : 0;
 }
 
+// Zeroes the residue and reserve of the lanes set in masks[t] (every row).
+__global__ void __launch_bounds__(kBlock) kb_clear_lanes(float *r, float *pi, int64_t tile_u, int64_t n_u,
+                                                         const unsigned long long *masks) {
+    const int t = blockIdx.y;
+    const unsigned long long m = masks[t];
+    if (m == 0ull) return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (!((m >> lane) & 1ull)) return;
+    float *rt = r + t * tile_u, *pt = pi + t * tile_u;
+    for (int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + wid; u < n_u; u += (int64_t)gridDim.x * kWavesPerBlock) {
+        rt[u * kTileQ + lane] = 0.0f;
+        pt[u * kTileQ + lane] = 0.0f;
+    }
+}
+
+// Starts admitted queries: unit residue at the source and a fresh control.
+__global__ void kb_admit(TileCtl *ctl, float *r, int64_t tile_u, const AdmitReq *req, int n, int32_t max_iters) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const AdmitReq a = req[i];
+    TileCtl &tc = ctl[a.tile];
+    QueryCtl &c = tc.q[a.lane];
+    const bool run = 1.0f > a.eps_f;
+    r[a.tile * tile_u + (int64_t)a.source * kTileQ + a.lane] = 1.0f;
+    c.theta = run ? a.eps_f : FLT_MAX;
+    c.eps_f = a.eps_f;
+    c.done = run ? 0 : 1;
+    c.phase = 1;
+    c.iter = 0;
+    c.switch_iter = -1;
+    c.status = run ? 0 : 1;
+    c.max_iters = max_iters;
+    c.n_p = 0;
+    c.last_max = 1.0f;
+    c.source = a.source;
+    if (run) tc.all_done = 0;
+}
+
+// out[j * n_u + u] = pi[u][lanes[j]] for the j < n_sel selected lanes of one tile.
+__global__ void __launch_bounds__(kBlock) kb_gather_lanes(const float *pi, int64_t n_u, const int32_t *lanes, int n_sel,
+                                                          float *out) {
+    __shared__ float tile[kWave][kWave + 1];
+    const int64_t u0 = (int64_t)blockIdx.x * kWave;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int i = wid; i < kWave; i += kWavesPerBlock) {
+        const int64_t u = u0 + i;
+        tile[i][lane] = u < n_u ? pi[u * kTileQ + lane] : 0.0f;
+    }
+    __syncthreads();
+    for (int j = wid; j < n_sel; j += kWavesPerBlock) {
+        const int q = lanes[j];
+        const int64_t u = u0 + lane;
+        if (u < n_u) out[(int64_t)j * n_u + u] = tile[lane][q];
+    }
+}
+
 // out[(t * kTileQ + q) * n_u + u] = pi[t][u][q], through 64 x 64 LDS tiles.
 __global__ void __launch_bounds__(kBlock) kb_transpose(const float *pi, int64_t pi_stride, int64_t n_u, float *out,
                                                        int64_t n_rows_valid) {
@@ -416,18 +472,23 @@ BPlan bplan(const Graph &g, int nt) {
 
 }  // namespace
 
-void free_batch_state(Graph &g) {
-    BatchState &b = g.batch;
+void free_batch_state(BatchState &b) {
     for (void *p : {(void *)b.r, (void *)b.pi, (void *)b.z, (void *)b.part, (void *)b.ctl, (void *)b.blk_max,
                     (void *)b.blk_np, (void *)b.out, (void *)b.sums})
         dfree(p);
     b = BatchState{};
 }
 
-void ensure_batch_state(Graph &g, int tiles) {
-    BatchState &b = g.batch;
-    if (b.tiles >= tiles) return;
-    free_batch_state(g);
+int64_t batch_tile_bytes(const Graph &g, bool with_out) {
+    const int64_t items = std::max<int64_t>(std::max(g.fwd.n_items, g.back.n_items), 1);
+    const int64_t Q = kTileQ;
+    return Q * 4 * (2 * g.n_u + std::max<int64_t>(g.n_v + g.n_a, 1) + items + (with_out ? g.n_u : 0)) +
+           (int64_t)sizeof(TileCtl) + (int64_t)g.grid_cap * Q * (2 * 4 + 4 * 8 + 8);
+}
+
+void ensure_batch_state(Graph &g, BatchState &b, int tiles, bool with_out) {
+    if (b.tiles >= tiles && (b.out || !with_out)) return;
+    free_batch_state(b);
     const int64_t items = std::max<int64_t>(std::max(g.fwd.n_items, g.back.n_items), 1);
     const size_t T = (size_t)tiles, Q = kTileQ;
     b.r = (float *)dev_alloc(g, T * g.n_u * Q * 4, "batch residues");
@@ -437,39 +498,36 @@ void ensure_batch_state(Graph &g, int tiles) {
     b.ctl = (TileCtl *)dev_alloc(g, T * sizeof(TileCtl), "batch control");
     b.blk_max = (float *)dev_alloc(g, T * 2 * g.grid_cap * Q * 4, "batch workgroup maxima");
     b.blk_np = (unsigned long long *)dev_alloc(g, T * 4 * g.grid_cap * Q * 8, "batch workgroup counts");
-    b.out = (float *)dev_alloc(g, T * Q * g.n_u * 4, "batch scores");
+    if (with_out) b.out = (float *)dev_alloc(g, T * Q * g.n_u * 4, "batch scores");
     b.sums = (double *)dev_alloc(g, T * g.grid_cap * Q * 8, "batch sums");
     b.tiles = tiles;
     b.grid_x = g.grid_cap;
 }
 
-void batch_init(Graph &g, int t0, int nt, const int32_t *sources, const float *eps_f, int64_t n_q,
+void batch_init(Graph &g, BatchState &b, int nt, const int32_t *sources, const float *eps_f, int64_t n_q,
                 int32_t max_iters, hipStream_t s) {
-    BatchState &b = g.batch;
     const int64_t tile_u = g.n_u * kTileQ;
-    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.r + t0 * tile_u, (int64_t)nt * tile_u);
-    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.pi + t0 * tile_u, (int64_t)nt * tile_u);
+    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.r, (int64_t)nt * tile_u);
+    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.pi, (int64_t)nt * tile_u);
     std::vector<InitQuery> hq((size_t)nt * kTileQ);
     const int64_t n_valid = std::min<int64_t>(n_q, (int64_t)nt * kTileQ);
     for (int64_t i = 0; i < n_valid; ++i) hq[i] = InitQuery{sources[i], eps_f[i]};
     InitQuery *dq = nullptr;
     check_hip(hipMallocAsync((void **)&dq, hq.size() * sizeof(InitQuery), s), "batch init");
     check_hip(hipMemcpyAsync(dq, hq.data(), hq.size() * sizeof(InitQuery), hipMemcpyHostToDevice, s), "batch init");
-    hipLaunchKernelGGL(kb_init, dim3(nt), dim3(kWave), 0, s, b.ctl + t0, b.r + t0 * tile_u, tile_u, dq, n_valid,
-                       max_iters);
+    hipLaunchKernelGGL(kb_init, dim3(nt), dim3(kWave), 0, s, b.ctl, b.r, tile_u, dq, n_valid, max_iters);
     check_hip(hipFreeAsync(dq, s), "batch init");
     check_hip(hipGetLastError(), "batch init launch");
 }
 
-void batch_round(Graph &g, int t0, int nt, hipStream_t s) {
-    BatchState &b = g.batch;
+void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
     const BPlan p = bplan(g, nt);
     const int64_t tile_u = g.n_u * kTileQ, tile_z = std::max<int64_t>(g.n_v + g.n_a, 1) * kTileQ;
     const int64_t tile_part = std::max<int64_t>(std::max(g.fwd.n_items, g.back.n_items), 1) * kTileQ;
     const int64_t sf = 2 * (int64_t)g.grid_cap * kTileQ, su = 4 * (int64_t)g.grid_cap * kTileQ;
     BArgs back{g.back.off, g.back.col, g.back.w, g.back.items, g.back.n_items, g.back.split, g.back.n_split,
-               b.r + t0 * tile_u, b.z + t0 * tile_z, nullptr, g.inv_b, b.part + t0 * tile_part, b.ctl + t0,
-               tile_u, tile_z, 0, tile_part, nullptr, b.blk_np + t0 * su, sf, su, (float)g.alpha};
+               b.r, b.z, nullptr, g.inv_b, b.part, b.ctl, tile_u, tile_z, 0, tile_part, nullptr, b.blk_np, sf, su,
+               (float)g.alpha};
     // Slots of the n_p partials: 0 back, 1 back fix, 2 fwd, 3 fwd fix; of the
     // max partials: 0 fwd, 1 fwd fix; slots are grid_cap workgroups apart.
     const int64_t slot = (int64_t)g.grid_cap * kTileQ;
@@ -489,9 +547,8 @@ void batch_round(Graph &g, int t0, int nt, hipStream_t s) {
         hipLaunchKernelGGL((kb_fix<kBBack>), dim3(p.back_fix, nt), dim3(kBlock), 0, s, a);
     }
     BArgs fwd{g.fwd.off, g.fwd.col, g.fwd.w, g.fwd.items, g.fwd.n_items, g.fwd.split, g.fwd.n_split,
-              b.z + t0 * tile_z, b.r + t0 * tile_u, b.pi + t0 * tile_u, nullptr, b.part + t0 * tile_part, b.ctl + t0,
-              tile_z, tile_u, tile_u, tile_part, b.blk_max + t0 * sf, b.blk_np + t0 * su + 2 * slot, sf, su,
-              (float)g.alpha};
+              b.z, b.r, b.pi, nullptr, b.part, b.ctl, tile_z, tile_u, tile_u, tile_part, b.blk_max,
+              b.blk_np + 2 * slot, sf, su, (float)g.alpha};
     profiled(g.prof, 3, fwd_bytes, s, [&] {
         if (g.unit) hipLaunchKernelGGL((kb_gather<true, kBFwd>), dim3(p.fwd, nt), dim3(kBlock), 0, s, fwd);
         else hipLaunchKernelGGL((kb_gather<false, kBFwd>), dim3(p.fwd, nt), dim3(kBlock), 0, s, fwd);
@@ -502,25 +559,24 @@ void batch_round(Graph &g, int t0, int nt, hipStream_t s) {
         a.blk_np += slot;
         hipLaunchKernelGGL((kb_fix<kBFwd>), dim3(p.fwd_fix, nt), dim3(kBlock), 0, s, a);
     }
-    hipLaunchKernelGGL(kb_control, dim3(nt), dim3(kWave), 0, s, b.ctl + t0, b.blk_max + t0 * sf, b.blk_np + t0 * su,
-                       sf, su, g.grid_cap, (int)p.back, (int)p.back_fix, (int)p.fwd, (int)p.fwd_fix, make_rule(g));
+    hipLaunchKernelGGL(kb_control, dim3(nt), dim3(kWave), 0, s, b.ctl, b.blk_max, b.blk_np, sf, su, g.grid_cap,
+                       (int)p.back, (int)p.back_fix, (int)p.fwd, (int)p.fwd_fix, make_rule(g));
     check_hip(hipGetLastError(), "batch round launch");
 }
 
-void batch_scores(Graph &g, int t0, int nt, int64_t n_rows, float *out, hipStream_t s) {
+void batch_scores(Graph &g, BatchState &b, int nt, int64_t n_rows, float *out, hipStream_t s) {
     const int64_t tile_u = g.n_u * kTileQ;
-    hipLaunchKernelGGL(kb_transpose, dim3((unsigned)((g.n_u + kWave - 1) / kWave), nt), dim3(kBlock), 0, s,
-                       g.batch.pi + t0 * tile_u, tile_u, g.n_u, out, std::min<int64_t>(n_rows, (int64_t)nt * kTileQ));
+    hipLaunchKernelGGL(kb_transpose, dim3((unsigned)((g.n_u + kWave - 1) / kWave), nt), dim3(kBlock), 0, s, b.pi,
+                       tile_u, g.n_u, out, std::min<int64_t>(n_rows, (int64_t)nt * kTileQ));
     check_hip(hipGetLastError(), "batch scores launch");
 }
 
-void batch_resid_sums(Graph &g, int t0, int nt, double *sums, hipStream_t s) {
+void batch_resid_sums(Graph &g, BatchState &b, int t0, int nt, double *sums, hipStream_t s) {
     const int64_t tile_u = g.n_u * kTileQ;
     const unsigned gx = capped(g.n_u, kWavesPerBlock * 64, std::min(g.grid_cap, 1024));
-    hipLaunchKernelGGL(kb_sums, dim3(gx, nt), dim3(kBlock), 0, s, g.batch.r + t0 * tile_u, tile_u, g.n_u,
-                       g.batch.sums);
+    hipLaunchKernelGGL(kb_sums, dim3(gx, nt), dim3(kBlock), 0, s, b.r + t0 * tile_u, tile_u, g.n_u, b.sums);
     std::vector<double> h((size_t)nt * gx * kTileQ);
-    check_hip(hipMemcpyAsync(h.data(), g.batch.sums, h.size() * 8, hipMemcpyDeviceToHost, s), "batch sums D2H");
+    check_hip(hipMemcpyAsync(h.data(), b.sums, h.size() * 8, hipMemcpyDeviceToHost, s), "batch sums D2H");
     check_hip(hipStreamSynchronize(s), "batch sums");
     for (int t = 0; t < nt; ++t)
         for (int q = 0; q < kTileQ; ++q) {
@@ -528,6 +584,44 @@ void batch_resid_sums(Graph &g, int t0, int nt, double *sums, hipStream_t s) {
             for (unsigned i = 0; i < gx; ++i) v += h[((size_t)t * gx + i) * kTileQ + q];
             sums[(size_t)t * kTileQ + q] = v;
         }
+}
+
+void batch_empty(Graph &g, BatchState &b, int nt, hipStream_t s) {
+    const int64_t tile_u = g.n_u * kTileQ;
+    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.r, (int64_t)nt * tile_u);
+    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.pi, (int64_t)nt * tile_u);
+    hipLaunchKernelGGL(kb_init, dim3(nt), dim3(kWave), 0, s, b.ctl, b.r, tile_u, (const InitQuery *)nullptr,
+                       (int64_t)0, (int32_t)1);
+    check_hip(hipGetLastError(), "batch empty launch");
+}
+
+void batch_admit(Graph &g, BatchState &b, const std::vector<AdmitReq> &reqs, int32_t max_iters, hipStream_t s) {
+    if (reqs.empty()) return;
+    const int64_t tile_u = g.n_u * kTileQ;
+    std::vector<unsigned long long> masks((size_t)b.tiles, 0ull);
+    for (const AdmitReq &a : reqs) masks[a.tile] |= 1ull << a.lane;
+    unsigned long long *dm = nullptr;
+    AdmitReq *dr = nullptr;
+    check_hip(hipMallocAsync((void **)&dm, masks.size() * 8, s), "admit");
+    check_hip(hipMallocAsync((void **)&dr, reqs.size() * sizeof(AdmitReq), s), "admit");
+    check_hip(hipMemcpyAsync(dm, masks.data(), masks.size() * 8, hipMemcpyHostToDevice, s), "admit");
+    check_hip(hipMemcpyAsync(dr, reqs.data(), reqs.size() * sizeof(AdmitReq), hipMemcpyHostToDevice, s), "admit");
+    const unsigned gx = capped(g.n_u, kWavesPerBlock * 16, 1024);
+    hipLaunchKernelGGL(kb_clear_lanes, dim3(gx, b.tiles), dim3(kBlock), 0, s, b.r, b.pi, tile_u, g.n_u, dm);
+    hipLaunchKernelGGL(kb_admit, dim3(capped((int64_t)reqs.size(), kBlock, 1 << 20)), dim3(kBlock), 0, s, b.ctl, b.r,
+                       tile_u, dr, (int)reqs.size(), max_iters);
+    check_hip(hipFreeAsync(dm, s), "admit");
+    check_hip(hipFreeAsync(dr, s), "admit");
+    check_hip(hipGetLastError(), "admit launch");
+}
+
+void batch_lanes_out(Graph &g, BatchState &b, int tile, const int32_t *d_lanes, int n_sel, float *out,
+                     hipStream_t s) {
+    if (n_sel <= 0) return;
+    const int64_t tile_u = g.n_u * kTileQ;
+    hipLaunchKernelGGL(kb_gather_lanes, dim3((unsigned)((g.n_u + kWave - 1) / kWave)), dim3(kBlock), 0, s,
+                       b.pi + tile * tile_u, g.n_u, d_lanes, n_sel, out);
+    check_hip(hipGetLastError(), "lanes out launch");
 }
 
 }  // namespace ahpp

@@ -18,6 +18,10 @@ struct ahpp_graph {
     ahpp::Graph g;
 };
 
+struct ahpp_server {
+    ahpp::Server *impl;
+};
+
 namespace ahpp {
 
 namespace {
@@ -64,10 +68,7 @@ int batch_tiles_in_flight(const Graph &g) {
     }
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return 4;
-    const double per_tile = (double)kTileQ * 4.0 *
-                            (3.0 * (double)g.n_u + (double)(g.n_v + g.n_a) +
-                             (double)std::max(g.fwd.n_items, g.back.n_items)) +
-                            (double)g.grid_cap * kTileQ * 48.0;
+    const double per_tile = (double)batch_tile_bytes(g, true);
     int t = (int)std::floor((double)free_b * 0.25 / std::max(per_tile, 1.0));
     return std::max(1, std::min(t, 16));
 }
@@ -159,6 +160,92 @@ using namespace ahpp;
 extern "C" {
 
 const char *ahpp_last_error(void) { return g_last_error.c_str(); }
+
+ahpp_status_t ahpp_server_create(ahpp_graph_t *h, int64_t max_device_bytes, int32_t k, int32_t max_iters,
+                                 int32_t keep_pi, ahpp_server_t **out) {
+    g_last_error.clear();
+    if (!h || !out) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_create: NULL argument");
+    *out = nullptr;
+    if (k < 1 || k > kMaxTopK) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_create: k must be in [1, 2048]");
+    ahpp_server *srv = new (std::nothrow) ahpp_server{nullptr};
+    if (!srv) return fail(AHPP_ERR_OUT_OF_MEMORY, "ahpp_server_create: host allocation failed");
+    try {
+        DeviceScope scope(h->g.device);
+        srv->impl = new Server(h->g, max_device_bytes, k, max_iters, keep_pi != 0);
+    } catch (const Failure &f) {
+        delete srv;
+        return fail(f.status, f.msg);
+    } catch (const std::exception &e) {
+        delete srv;
+        return fail(AHPP_ERR_OUT_OF_MEMORY, std::string("ahpp_server_create: ") + e.what());
+    }
+    *out = srv;
+    return AHPP_OK;
+}
+
+void ahpp_server_free(ahpp_server_t *srv) {
+    if (!srv) return;
+    try {
+        if (srv->impl) {
+            DeviceScope scope(srv->impl->graph().device);
+            (void)hipDeviceSynchronize();
+            delete srv->impl;
+        }
+    } catch (...) {
+    }
+    delete srv;
+}
+
+ahpp_status_t ahpp_server_submit(ahpp_server_t *srv, int64_t tag, int32_t source, double eps) {
+    g_last_error.clear();
+    if (!srv || !srv->impl) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_submit: NULL server");
+    if (source < 0 || source >= srv->impl->graph().n_u)
+        return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_submit: source out of range");
+    if (!(eps > 0.0) || std::isinf(eps)) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_submit: eps must be > 0");
+    try {
+        srv->impl->submit(tag, source, eps);
+    } catch (const std::exception &e) {
+        return fail(AHPP_ERR_OUT_OF_MEMORY, std::string("ahpp_server_submit: ") + e.what());
+    }
+    return AHPP_OK;
+}
+
+ahpp_status_t ahpp_server_step(ahpp_server_t *srv, int32_t rounds, int32_t *n_ready, void *hip_stream) {
+    g_last_error.clear();
+    if (!srv || !srv->impl) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_step: NULL server");
+    if (rounds < 0) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_step: rounds < 0");
+    try {
+        DeviceScope scope(srv->impl->graph().device);
+        const int n = srv->impl->step(rounds, (hipStream_t)hip_stream);
+        if (n_ready) *n_ready = n;
+    } catch (const Failure &f) {
+        return fail(f.status, f.msg);
+    }
+    return AHPP_OK;
+}
+
+ahpp_status_t ahpp_server_results(ahpp_server_t *srv, int32_t max_n, int64_t *tags, int32_t *topk_idx,
+                                  float *topk_val, int32_t *topk_n, ahpp_stats_t *stats, float *pi_out,
+                                  int32_t *n_out, void *hip_stream) {
+    g_last_error.clear();
+    if (!srv || !srv->impl || !n_out) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_results: NULL argument");
+    if (max_n < 0) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_results: max_n < 0");
+    try {
+        DeviceScope scope(srv->impl->graph().device);
+        *n_out = srv->impl->results(max_n, tags, topk_idx, topk_val, topk_n, stats, pi_out, (hipStream_t)hip_stream);
+    } catch (const Failure &f) {
+        return fail(f.status, f.msg);
+    }
+    return AHPP_OK;
+}
+
+ahpp_status_t ahpp_server_info(const ahpp_server_t *srv, int32_t *slots, int32_t *running, int32_t *queued,
+                               int32_t *ready) {
+    g_last_error.clear();
+    if (!srv || !srv->impl) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_info: NULL server");
+    srv->impl->info(slots, running, queued, ready);
+    return AHPP_OK;
+}
 
 ahpp_status_t ahpp_profile_enable(ahpp_graph_t *h, int32_t on) {
     g_last_error.clear();
@@ -380,7 +467,8 @@ ahpp_status_t ahpp_query_batch(ahpp_graph_t *h, int32_t n_q, const int32_t *sour
         DeviceScope scope(g.device);
         const int tiles_total = (int)((n_q + kTileQ - 1) / kTileQ);
         const int tif = std::min(tiles_total, batch_tiles_in_flight(g));
-        ensure_batch_state(g, tif);
+        // The query-major score buffer is needed only when pi_out is absent.
+        ensure_batch_state(g, g.batch, tif, pi_out == nullptr);
         if (k > 0) ensure_topk_scratch(g, (int64_t)tif * kTileQ);
         std::vector<float> eps_f((size_t)n_q);
         for (int32_t q = 0; q < n_q; ++q) eps_f[q] = (float)(eps[q] / g.lambda);
@@ -397,11 +485,11 @@ ahpp_status_t ahpp_query_batch(ahpp_graph_t *h, int32_t n_q, const int32_t *sour
         for (int64_t q0 = 0; q0 < n_q; q0 += (int64_t)tif * kTileQ) {
             const int64_t nq = std::min<int64_t>((int64_t)tif * kTileQ, n_q - q0);
             const int nt = (int)((nq + kTileQ - 1) / kTileQ);
-            batch_init(g, 0, nt, sources + q0, eps_f.data() + q0, nq, max_iters, s);
+            batch_init(g, g.batch, nt, sources + q0, eps_f.data() + q0, nq, max_iters, s);
             g.batch.live_q = nq;
             int chunk = 4, launched = 0, executed = 0;
             for (;;) {
-                for (int i = 0; i < chunk; ++i) batch_round(g, 0, nt, s);
+                for (int i = 0; i < chunk; ++i) batch_round(g, g.batch, nt, s);
                 launched += chunk;
                 check_hip(hipMemcpyAsync(ctl.data(), g.batch.ctl, (size_t)nt * sizeof(TileCtl), hipMemcpyDeviceToHost,
                                          s), "poll");
@@ -430,7 +518,7 @@ ahpp_status_t ahpp_query_batch(ahpp_graph_t *h, int32_t n_q, const int32_t *sour
                 profiler_void_tail(g.prof, 3, launched - executed);
             }
             float *scores = pi_out ? pi_out + q0 * g.n_u : g.batch.out;
-            batch_scores(g, 0, nt, nq, scores, s);
+            batch_scores(g, g.batch, nt, nq, scores, s);
             if (k > 0)
                 topk_launch(scores, g.n_u, g.n_u, nq, d_src + q0, -1, k, topk_idx + q0 * k, topk_val + q0 * k,
                             topk_n + q0, g.tk_scratch, s);
@@ -439,7 +527,7 @@ ahpp_status_t ahpp_query_batch(ahpp_graph_t *h, int32_t n_q, const int32_t *sour
                 if (c.status != 1) all_converged = false;
             }
             if (stats) {
-                batch_resid_sums(g, 0, nt, sums.data(), s);
+                batch_resid_sums(g, g.batch, 0, nt, sums.data(), s);
                 for (int64_t q = 0; q < nq; ++q) {
                     const QueryCtl &c = ctl[q / kTileQ].q[q % kTileQ];
                     ahpp_stats_t &o = st_all[(size_t)(q0 + q)];

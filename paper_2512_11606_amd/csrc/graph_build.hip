@@ -463,7 +463,7 @@ static void free_csr(DevCsr &c) {
 void free_graph(Graph &g) {
     free_csr(g.fwd);
     free_csr(g.back);
-    free_batch_state(g);
+    free_batch_state(g.batch);
     for (void *p : {(void *)g.inv_b, (void *)g.q_r, (void *)g.q_pi, (void *)g.q_z, (void *)g.q_ctl,
                     (void *)g.part_item, (void *)g.blk_max, (void *)g.blk_np, g.tk_scratch})
         dfree(p);

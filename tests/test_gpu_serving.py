@@ -1,0 +1,123 @@
+"""Serving engine: continuous batching keeps every result what the query
+computes alone (within the tolerance), queries wait for free slots instead of
+failing, and the Poisson driver completes every query."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2512_11606_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+EPS_SET = (1e-5, 1e-6, 1e-7, 1e-8)
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_11606_amd import ahpp
+    g = synth.make_custom(5000, 2000, 40000, 200, 6, seed=717, unit_weights=False)
+    _say("load serving test graph")
+    dg = ahpp.load_graph(g)
+    yield g, dg, ahpp, torch
+    dg.free()
+
+
+def _one_tile_budget(ahpp, dg):
+    b = 1 << 20
+    while True:
+        try:
+            s = ahpp.Server(dg, k=25, max_device_bytes=b)
+        except ahpp.AhppError as e:
+            assert e.status == ahpp.ERR_OUT_OF_MEMORY
+            b *= 2
+            continue
+        slots = s.info()["slots"]
+        s.close()
+        return b, slots
+
+
+def test_same_alone_and_in_the_mix(env):
+    g, dg, ahpp, torch = env
+    budget, slots = _one_tile_budget(ahpp, dg)
+    assert slots >= 64
+    _say("server with", slots, "slots")
+    srv = ahpp.Server(dg, k=25, max_device_bytes=budget, keep_pi=True)
+    srcs = np.concatenate([synth.mixed_batch_queries(g, 100, 41), synth.degree_queries(g, 50, 42)])
+    eps = np.array([EPS_SET[i % 4] for i in range(srcs.size)])
+    results = {}
+    waited = False
+    waves = [(0, 30, 3), (30, 90, 2), (90, 150, 1)]
+    for a, b, rounds in waves:
+        for i in range(a, b):
+            srv.submit(i, int(srcs[i]), float(eps[i]))
+        waited = waited or srv.info()["queued"] > 0
+        srv.step(rounds)
+        for r in srv.results(want_pi=True):
+            results[r["tag"]] = r
+    guard = 0
+    while len(results) < srcs.size:
+        waited = waited or srv.info()["queued"] > 0
+        srv.step(4)
+        for r in srv.results(want_pi=True):
+            results[r["tag"]] = r
+        guard += 1
+        assert guard < 10000
+    assert waited or slots >= srcs.size
+    og = O.OracleGraph.from_graph(g)
+    exact = {}
+    for i in range(srcs.size):
+        s, e = int(srcs[i]), float(eps[i])
+        if s not in exact:
+            exact[s], _ = og.power_series(s)
+        r = results[i]
+        mix = r["pi"].cpu().numpy().astype(np.float64)
+        chk = O.check_query(exact[s], mix, e, tol=TOL, k=25, source=s, topk_ids=r["topk_idx"])
+        assert chk.ok, (i, s, e, chk.detail)
+        assert r["stats"]["converged"] == 1
+        assert abs(mix.sum() + r["stats"]["sum_residual"] - 1.0) < 1e-5
+        alone = ahpp.ahpp_query(dg, s, e).pi.cpu().numpy().astype(np.float64)
+        assert np.abs(alone - mix).max() <= e + TOL, (i, s, e)
+    srv.close()
+
+
+def test_budget_and_argument_errors(env):
+    g, dg, ahpp, torch = env
+    with pytest.raises(ahpp.AhppError) as e:
+        ahpp.Server(dg, k=25, max_device_bytes=1024)
+    assert e.value.status == ahpp.ERR_OUT_OF_MEMORY
+    with pytest.raises(ahpp.AhppError):
+        ahpp.Server(dg, k=0)
+    srv = ahpp.Server(dg, k=10, max_device_bytes=1 << 30)
+    with pytest.raises(ahpp.AhppError):
+        srv.submit(0, g.n_u, 1e-6)
+    with pytest.raises(ahpp.AhppError):
+        srv.submit(0, 0, -1.0)
+    # eps >= lambda: stopped before any push, empty result.
+    srv.submit(7, 3, 10.0 * dg.lam)
+    srv.step(1)
+    r = srv.results()
+    assert len(r) == 1 and r[0]["tag"] == 7 and r[0]["topk_idx"].size == 0 and r[0]["stats"]["iters"] == 0
+    srv.close()
+
+
+def test_poisson_driver_completes(env):
+    g, dg, ahpp, torch = env
+    from paper_2512_11606_amd import serve
+    srv = ahpp.Server(dg, k=25, max_device_bytes=1 << 30)
+    srcs = synth.degree_queries(g, 120, 43)
+    eps = [EPS_SET[i % 4] for i in range(srcs.size)]
+    summary, res = serve.run(srv, srcs, eps, rate_qps=3000.0, rounds_per_step=4)
+    assert summary["completed"] == srcs.size and len(res) == srcs.size
+    assert summary["latency_ms_p50"] > 0 and summary["latency_ms_p99"] >= summary["latency_ms_p50"]
+    for t, r in res.items():
+        assert r["stats"]["converged"] == 1 and int(srcs[t]) not in r["topk_idx"].tolist()
+    srv.close()
