@@ -77,8 +77,10 @@ struct Rule {
     double budget_scale;  // 2 (|E| + |E_A|)
 };
 
-// Queries per batch tile: one query per lane of a wave.
-constexpr int kTileQ = 64;
+// Queries per batch tile: kVec queries per lane of a wave, so a node's row of
+// the tile is kTileQ floats (1 KB) and one gather reads one contiguous row.
+constexpr int kVec = 4;
+constexpr int kTileQ = kWave * kVec;
 
 // Control of one query inside a batch tile (same rule as Control).
 struct QueryCtl {
@@ -97,7 +99,7 @@ struct TileCtl {
 };
 
 // Device state of the batched engine: `tiles` tiles of kTileQ queries, each
-// stored node-major ([node][kTileQ], one 256-byte row per node).
+// stored node-major ([node][kTileQ], one 1 KB row per node).
 struct BatchState {
     int tiles = 0;                  // tiles allocated
     int grid_x = 0;                 // workgroups per tile of the gather kernels

@@ -2,14 +2,16 @@
 // at once, sharing every pass over the edge lists.
 //
 // Queries are independent (each has its own residues, reserves, eps_f,
-// threshold, phase and stop rule), so a batch is a set of tiles of kTileQ = 64
-// queries, one query per lane of a wave.  A tile's vectors are stored node-
-// major: node x owns the 64 floats [x][0..63], one 256-byte row.  A round is
-// the same pair of pull-form gathers as the single-query path
-// (z = inv_b * W'^T thr(r), then r <- keep(r) + W z with the reserve update),
-// but every CSR entry is read once per tile and drives one coalesced 256-byte
-// gather of the 64 queries' values.  Row bookkeeping is wave-uniform (scalar),
-// and each wave keeps 16 gathers in flight.
+// threshold, phase and stop rule), so a batch is a set of tiles of kTileQ
+// queries, kVec consecutive queries per lane of a wave.  A tile's vectors are
+// stored node-major: node x owns the kTileQ floats [x][0..kTileQ), one 1 KB
+// row.  A round is the same pair of pull-form gathers as the single-query
+// path (z = inv_b * W'^T thr(r), then r <- keep(r) + W z with the reserve
+// update), but every CSR entry is read once per tile and drives one
+// contiguous 1 KB gather of all the tile's queries (random 1 KB reads run
+// near HBM speed on MI355X, 256-byte ones at about half of it).  Row
+// bookkeeping is wave-uniform (scalar), and each wave keeps kInFlight
+// gathers in flight.
 //
 // A query that has stopped keeps threshold +inf: it pushes nothing, so its
 // state no longer changes while the rest of its tile runs on.
@@ -26,9 +28,54 @@ namespace ahpp {
 
 namespace {
 
+static_assert(kVec == 4 || kVec == 2 || kVec == 1, "kVec must be 1, 2 or 4");
+static_assert(kTileQ <= kBlock, "one workgroup thread per tile query");
+
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kInFlight = 16;  // gathers issued before the first is used
+constexpr int kInFlight = 8;  // gathers issued before the first is used
+constexpr int kMaskWords = kTileQ / 64;
 enum BMode { kBBack = 0, kBFwd = 1 };
+
+// The kVec queries of one lane.
+struct QV {
+    float v[kVec];
+};
+
+__device__ __forceinline__ QV qv_zero() {
+    QV a;
+#pragma unroll
+    for (int j = 0; j < kVec; ++j) a.v[j] = 0.0f;
+    return a;
+}
+
+__device__ __forceinline__ QV qv_load(const float *p) {
+    QV a;
+    if constexpr (kVec == 4) {
+        const float4 t = *reinterpret_cast<const float4 *>(p);
+        a.v[0] = t.x;
+        a.v[kVec > 1 ? 1 : 0] = t.y;
+        a.v[kVec > 2 ? 2 : 0] = t.z;
+        a.v[kVec > 3 ? 3 : 0] = t.w;
+    } else if constexpr (kVec == 2) {
+        const float2 t = *reinterpret_cast<const float2 *>(p);
+        a.v[0] = t.x;
+        a.v[kVec - 1] = t.y;
+    } else {
+        a.v[0] = p[0];
+    }
+    return a;
+}
+
+__device__ __forceinline__ void qv_store(float *p, const QV &a) {
+    if constexpr (kVec == 4) {
+        *reinterpret_cast<float4 *>(p) = make_float4(a.v[0], a.v[kVec > 1 ? 1 : 0], a.v[kVec > 2 ? 2 : 0],
+                                                     a.v[kVec > 3 ? 3 : 0]);
+    } else if constexpr (kVec == 2) {
+        *reinterpret_cast<float2 *>(p) = make_float2(a.v[0], a.v[kVec - 1]);
+    } else {
+        p[0] = a.v[0];
+    }
+}
 
 struct BArgs {
     const int64_t *__restrict__ off;
@@ -55,62 +102,80 @@ __device__ __forceinline__ float readlane_f(float v, int k) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
 }
 
-// Per-lane epilogues; all values are the lane's query's.
+__device__ __forceinline__ int64_t lane_col() { return (int64_t)(threadIdx.x & 63) * kVec; }
+
+// Per-lane epilogues over the lane's kVec queries.
 template <int kMode>
 struct BEpi;
 
 template <>
 struct BEpi<kBBack> {
+    struct Pre {
+        float scale;
+    };
     float *z;
-    float theta;
-    unsigned long long np = 0;
-    float mx = 0.0f;
-    __device__ float2 pre(int64_t, float scale) const { return make_float2(scale, 0.0f); }
-    __device__ void full(int64_t row, float s, float2 p, int64_t len) {
-        const float v = p.x * s;
-        z[row * kTileQ + (threadIdx.x & 63)] = v;
-        if (v > 0.0f) np += (unsigned long long)len;
+    QV theta;
+    unsigned long long np[kVec];
+    float mx[kVec];
+    __device__ Pre pre(int64_t, float scale) const { return Pre{scale}; }
+    __device__ void full(int64_t row, const QV &s, const Pre &p, int64_t len) {
+        QV v;
+#pragma unroll
+        for (int j = 0; j < kVec; ++j) {
+            v.v[j] = p.scale * s.v[j];
+            if (v.v[j] > 0.0f) np[j] += (unsigned long long)len;
+        }
+        qv_store(z + row * kTileQ + lane_col(), v);
     }
 };
 
 template <>
 struct BEpi<kBFwd> {
+    struct Pre {
+        QV r, pi;
+    };
     float *r;
     float *pi;
-    float theta, alpha;
-    unsigned long long np = 0;
-    float mx = 0.0f;
-    __device__ float2 pre(int64_t row, float) const {
-        const int64_t i = row * kTileQ + (threadIdx.x & 63);
-        return make_float2(r[i], pi[i]);
+    QV theta;
+    float alpha;
+    unsigned long long np[kVec];
+    float mx[kVec];
+    __device__ Pre pre(int64_t row, float) const {
+        const int64_t i = row * kTileQ + lane_col();
+        return Pre{qv_load(r + i), qv_load(pi + i)};
     }
-    __device__ void full(int64_t row, float s, float2 p, int64_t len) {
-        const int64_t i = row * kTileQ + (threadIdx.x & 63);
-        const bool pushed = p.x > theta;
-        if (pushed) {
-            pi[i] = p.y + alpha * p.x;
-            np += (unsigned long long)len;
+    __device__ void full(int64_t row, const QV &s, const Pre &p, int64_t len) {
+        const int64_t i = row * kTileQ + lane_col();
+        QV nr, np_;
+#pragma unroll
+        for (int j = 0; j < kVec; ++j) {
+            const bool pushed = p.r.v[j] > theta.v[j];
+            np_.v[j] = pushed ? p.pi.v[j] + alpha * p.r.v[j] : p.pi.v[j];
+            if (pushed) np[j] += (unsigned long long)len;
+            nr.v[j] = (pushed ? 0.0f : p.r.v[j]) + s.v[j];
+            mx[j] = fmaxf(mx[j], nr.v[j]);
         }
-        const float v = (pushed ? 0.0f : p.x) + s;
-        r[i] = v;
-        mx = fmaxf(mx, v);
+        qv_store(pi + i, np_);
+        qv_store(r + i, nr);
     }
 };
 
-// Sum over entries [e0, e0 + ne) of w * thr(x[col]) for this lane's query,
+// Sum over entries [e0, e0 + ne) of w * thr(x[col]) for this lane's queries,
 // flushing each completed row of [r0, r0 + n_rows) through the epilogue.
 // Row ends are relative to e0; rows may be empty.
 template <bool kUnit, int kMode, class RowEnd, class RowScale>
 __device__ __forceinline__ void run_entries(const BArgs &a, const float *__restrict__ xt, int64_t r0, int n_rows,
-                                            int64_t e0, int ne, float theta, BEpi<kMode> &epi, RowEnd row_end,
-                                            RowScale row_scale, float *acc_out) {
+                                            int64_t e0, int ne, BEpi<kMode> &epi, RowEnd row_end,
+                                            RowScale row_scale, QV *acc_out) {
+    using Pre = typename BEpi<kMode>::Pre;
     const int lane = threadIdx.x & (kWave - 1);
+    const int64_t lc = lane_col();
     int j = 0, rstart = 0;
     int rend = n_rows > 0 ? row_end(0) : INT_MAX;
-    float2 pre = n_rows > 0 ? epi.pre(r0, row_scale(0)) : make_float2(0.0f, 0.0f);
-    float acc = 0.0f;
+    Pre pre = epi.pre(r0, n_rows > 0 ? row_scale(0) : 0.0f);
+    QV acc = qv_zero();
     while (j < n_rows && rend == 0) {
-        epi.full(r0 + j, 0.0f, pre, 0);
+        epi.full(r0 + j, acc, pre, 0);
         ++j;
         if (j < n_rows) {
             rend = row_end(j);
@@ -125,24 +190,28 @@ __device__ __forceinline__ void run_entries(const BArgs &a, const float *__restr
         float my_w = 1.0f;
         if constexpr (!kUnit) my_w = lane < cnt ? a.w[e0 + base + lane] : 0.0f;
         for (int k0 = 0; k0 < cnt; k0 += kInFlight) {
-            float v[kInFlight];
+            QV v[kInFlight];
 #pragma unroll
             for (int u = 0; u < kInFlight; ++u) {
                 const int k = k0 + u < kWave ? k0 + u : kWave - 1;
                 const int32_t c = __builtin_amdgcn_readlane(my_c, k);
-                v[u] = k0 + u < cnt ? xt[(int64_t)c * kTileQ + lane] : 0.0f;
+                v[u] = k0 + u < cnt ? qv_load(xt + (int64_t)c * kTileQ + lc) : qv_zero();
             }
 #pragma unroll
             for (int u = 0; u < kInFlight; ++u) {
                 const int k = k0 + u;
                 if (k < cnt) {
-                    float xv = v[u];
-                    if constexpr (kMode == kBBack) xv = xv > theta ? xv : 0.0f;
-                    acc += kUnit ? xv : readlane_f(my_w, k) * xv;
+                    const float wk = kUnit ? 1.0f : readlane_f(my_w, k);
+#pragma unroll
+                    for (int q = 0; q < kVec; ++q) {
+                        float xv = v[u].v[q];
+                        if constexpr (kMode == kBBack) xv = xv > epi.theta.v[q] ? xv : 0.0f;
+                        acc.v[q] += kUnit ? xv : wk * xv;
+                    }
                     const int e = base + k + 1;
                     while (e == rend) {
                         epi.full(r0 + j, acc, pre, rend - rstart);
-                        acc = 0.0f;
+                        acc = qv_zero();
                         rstart = rend;
                         ++j;
                         if (j < n_rows) {
@@ -160,28 +229,54 @@ __device__ __forceinline__ void run_entries(const BArgs &a, const float *__restr
 }
 
 template <int kMode>
-__device__ __forceinline__ BEpi<kMode> make_bepi(const BArgs &a, int t, float theta) {
-    if constexpr (kMode == kBBack) return BEpi<kBBack>{a.y + t * a.y_stride, theta};
-    else return BEpi<kBFwd>{a.y + t * a.y_stride, a.pi + t * a.pi_stride, theta, a.alpha};
+__device__ __forceinline__ BEpi<kMode> make_bepi(const BArgs &a, int t, const QV &theta) {
+    BEpi<kMode> e;
+    if constexpr (kMode == kBBack) {
+        e.z = a.y + t * a.y_stride;
+    } else {
+        e.r = a.y + t * a.y_stride;
+        e.pi = a.pi + t * a.pi_stride;
+        e.alpha = a.alpha;
+    }
+    e.theta = theta;
+#pragma unroll
+    for (int j = 0; j < kVec; ++j) {
+        e.np[j] = 0;
+        e.mx[j] = 0.0f;
+    }
+    return e;
 }
 
+__device__ __forceinline__ QV lane_theta(const TileCtl &tc) {
+    QV th;
+    const int q0 = (threadIdx.x & 63) * kVec;
+#pragma unroll
+    for (int j = 0; j < kVec; ++j) th.v[j] = tc.q[q0 + j].theta;
+    return th;
+}
+
+// Per-workgroup max and n_p of every query of the tile, one slot per query.
 template <int kMode>
 __device__ __forceinline__ void bflush(const BArgs &a, int t, BEpi<kMode> &epi) {
-    __shared__ float smx[kWavesPerBlock][kWave];
-    __shared__ unsigned long long snp[kWavesPerBlock][kWave];
+    __shared__ float smx[kWavesPerBlock][kTileQ];
+    __shared__ unsigned long long snp[kWavesPerBlock][kTileQ];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    smx[wid][lane] = epi.mx;
-    snp[wid][lane] = epi.np;
+#pragma unroll
+    for (int j = 0; j < kVec; ++j) {
+        smx[wid][lane * kVec + j] = epi.mx[j];
+        snp[wid][lane * kVec + j] = epi.np[j];
+    }
     __syncthreads();
-    if (wid == 0) {
-        float m = smx[0][lane];
-        unsigned long long n = snp[0][lane];
+    const int q = threadIdx.x;
+    if (q < kTileQ) {
+        float m = smx[0][q];
+        unsigned long long n = snp[0][q];
 #pragma unroll
         for (int i = 1; i < kWavesPerBlock; ++i) {
-            m = fmaxf(m, smx[i][lane]);
-            n += snp[i][lane];
+            m = fmaxf(m, smx[i][q]);
+            n += snp[i][q];
         }
-        const int64_t o = (int64_t)blockIdx.x * kTileQ + lane;
+        const int64_t o = (int64_t)blockIdx.x * kTileQ + q;
         if (a.blk_max) a.blk_max[t * a.blk_stride_f + o] = m;
         if (a.blk_np) a.blk_np[t * a.blk_stride_u + o] = n;
     }
@@ -193,10 +288,9 @@ __global__ void __launch_bounds__(kBlock) kb_gather(BArgs a) {
     const TileCtl &tc = a.ctl[t];
     if (tc.all_done) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const float theta = tc.q[lane].theta;
     const float *xt = a.x + t * a.x_stride;
     float *part = a.part + t * a.part_stride;
-    BEpi<kMode> epi = make_bepi<kMode>(a, t, theta);
+    BEpi<kMode> epi = make_bepi<kMode>(a, t, lane_theta(tc));
     const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t it = wave0; it < a.n_items; it += stride) {
@@ -219,7 +313,7 @@ __global__ void __launch_bounds__(kBlock) kb_gather(BArgs a) {
                 return jj < kWave ? __builtin_amdgcn_readlane(end0, jj) : __builtin_amdgcn_readlane(end1, jj - kWave);
             };
             auto row_scale = [&](int jj) { return jj < kWave ? readlane_f(sc0, jj) : readlane_f(sc1, jj - kWave); };
-            run_entries<kUnit, kMode>(a, xt, r0, n, e0, ne, theta, epi, row_end, row_scale, nullptr);
+            run_entries<kUnit, kMode>(a, xt, r0, n, e0, ne, epi, row_end, row_scale, nullptr);
         } else {
             const int64_t row = item.row;
             const int64_t rb = a.off[row], re = a.off[row + 1];
@@ -230,9 +324,9 @@ __global__ void __launch_bounds__(kBlock) kb_gather(BArgs a) {
             if constexpr (kMode == kBBack) scale = a.inv_b[row];
             auto row_end = [&](int) { return whole ? ne : INT_MAX; };
             auto row_scale = [&](int) { return scale; };
-            float acc = 0.0f;
-            run_entries<kUnit, kMode>(a, xt, row, whole ? 1 : 0, e0, ne, theta, epi, row_end, row_scale, &acc);
-            if (!whole) part[it * kTileQ + lane] = acc;
+            QV acc;
+            run_entries<kUnit, kMode>(a, xt, row, whole ? 1 : 0, e0, ne, epi, row_end, row_scale, &acc);
+            if (!whole) qv_store(part + it * kTileQ + lane_col(), acc);
         }
     }
     bflush<kMode>(a, t, epi);
@@ -244,27 +338,30 @@ __global__ void __launch_bounds__(kBlock) kb_fix(BArgs a) {
     const int t = blockIdx.y;
     const TileCtl &tc = a.ctl[t];
     if (tc.all_done) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const float theta = tc.q[lane].theta;
     const float *part = a.part + t * a.part_stride;
-    BEpi<kMode> epi = make_bepi<kMode>(a, t, theta);
+    BEpi<kMode> epi = make_bepi<kMode>(a, t, lane_theta(tc));
     const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t i = wave0; i < a.n_split; i += stride) {
         const SplitRow sr = a.split[i];
-        float s = 0.0f;
-        for (int ch = 0; ch < sr.nch; ++ch) s += part[(int64_t)(sr.first_item + ch) * kTileQ + lane];
+        QV s = qv_zero();
+        for (int ch = 0; ch < sr.nch; ++ch) {
+            const QV p = qv_load(part + (int64_t)(sr.first_item + ch) * kTileQ + lane_col());
+#pragma unroll
+            for (int j = 0; j < kVec; ++j) s.v[j] += p.v[j];
+        }
         const float scale = kMode == kBBack ? a.inv_b[sr.row] : 0.0f;
         epi.full(sr.row, s, epi.pre(sr.row, scale), a.off[sr.row + 1] - a.off[sr.row]);
     }
     bflush<kMode>(a, t, epi);
 }
 
-// One wave per tile, lane = query: max r and n_p from the partials, then the
-// stop / switch rule of Algorithm 4 for every running query.
-__global__ void __launch_bounds__(kWave) kb_control(TileCtl *ctl, const float *blk_max, const unsigned long long *blk_np,
-                                                    int64_t stride_f, int64_t stride_u, int grid_cap, int n_back,
-                                                    int n_back_fix, int n_fwd, int n_fwd_fix, Rule rule) {
+// One workgroup per tile, one thread per query: max r and n_p from the
+// partials, then the stop / switch rule of Algorithm 4 for every running query.
+__global__ void __launch_bounds__(kTileQ) kb_control(TileCtl *ctl, const float *blk_max, const unsigned long long *blk_np,
+                                                     int64_t stride_f, int64_t stride_u, int grid_cap, int n_back,
+                                                     int n_back_fix, int n_fwd, int n_fwd_fix, Rule rule) {
+    __shared__ int running_any[kTileQ / kWave];
     const int t = blockIdx.x;
     TileCtl &tc = ctl[t];
     if (tc.all_done) return;
@@ -306,7 +403,13 @@ __global__ void __launch_bounds__(kWave) kb_control(TileCtl *ctl, const float *b
         }
     }
     const unsigned long long running = __ballot(!done);
-    if (q == 0) tc.all_done = running == 0ull ? 1 : 0;
+    if ((q & 63) == 0) running_any[q >> 6] = running != 0ull;
+    __syncthreads();
+    if (q == 0) {
+        int any = 0;
+        for (int i = 0; i < kTileQ / kWave; ++i) any |= running_any[i];
+        tc.all_done = any ? 0 : 1;
+    }
 }
 
 __global__ void kb_fill(float *p, int64_t n) {
@@ -319,9 +422,11 @@ struct InitQuery {
     float eps_f;
 };
 
-// One wave per tile: lane q starts query q of the tile (or stays empty).
-__global__ void __launch_bounds__(kWave) kb_init(TileCtl *ctl, float *r, int64_t r_stride, const InitQuery *qs,
-                                                 int64_t n_valid, int32_t max_iters) {
+// One workgroup per tile, one thread per query: start query q of the tile
+// (or leave the slot empty).
+__global__ void __launch_bounds__(kTileQ) kb_init(TileCtl *ctl, float *r, int64_t r_stride, const InitQuery *qs,
+                                                  int64_t n_valid, int32_t max_iters) {
+    __shared__ int running_any[kTileQ / kWave];
     const int t = blockIdx.x, q = threadIdx.x;
     const int64_t gq = (int64_t)t * kTileQ + q;
     QueryCtl &c = ctl[t].q[q];
@@ -342,21 +447,44 @@ __global__ void __launch_bounds__(kWave) kb_init(TileCtl *ctl, float *r, int64_t
     c.last_max = live ? 1.0f : 0.0f;
     c.source = src;
     const unsigned long long running = __ballot(run);
-    if (q == 0) ctl[t].all_done = running == 0ull ? 1 : 0;
+    if ((q & 63) == 0) running_any[q >> 6] = running != 0ull;
+    __syncthreads();
+    if (q == 0) {
+        int any = 0;
+        for (int i = 0; i < kTileQ / kWave; ++i) any |= running_any[i];
+        ctl[t].all_done = any ? 0 : 1;
+    }
 }
 
-// Zeroes the residue and reserve of the lanes set in masks[t] (every row).
+// Zeroes the residue and reserve of the queries set in the tile's mask words
+// (masks[t * kMaskWords + q / 64] bit q % 64), in every row.
 __global__ void __launch_bounds__(kBlock) kb_clear_lanes(float *r, float *pi, int64_t tile_u, int64_t n_u,
                                                          const unsigned long long *masks) {
     const int t = blockIdx.y;
-    const unsigned long long m = masks[t];
-    if (m == 0ull) return;
+    const unsigned long long *m = masks + (int64_t)t * kMaskWords;
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < kMaskWords; ++i) any = any || m[i] != 0ull;
+    if (!any) return;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (!((m >> lane) & 1ull)) return;
+    bool mine[kVec];
+    bool some = false;
+#pragma unroll
+    for (int j = 0; j < kVec; ++j) {
+        const int q = lane * kVec + j;
+        mine[j] = (m[q >> 6] >> (q & 63)) & 1ull;
+        some = some || mine[j];
+    }
+    if (!some) return;
     float *rt = r + t * tile_u, *pt = pi + t * tile_u;
     for (int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + wid; u < n_u; u += (int64_t)gridDim.x * kWavesPerBlock) {
-        rt[u * kTileQ + lane] = 0.0f;
-        pt[u * kTileQ + lane] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < kVec; ++j) {
+            if (mine[j]) {
+                rt[u * kTileQ + lane * kVec + j] = 0.0f;
+                pt[u * kTileQ + lane * kVec + j] = 0.0f;
+            }
+        }
     }
 }
 
@@ -383,17 +511,25 @@ __global__ void kb_admit(TileCtl *ctl, float *r, int64_t tile_u, const AdmitReq 
     if (run) tc.all_done = 0;
 }
 
-// out[j * n_u + u] = pi[u][lanes[j]] for the j < n_sel selected lanes of one tile.
-__global__ void __launch_bounds__(kBlock) kb_gather_lanes(const float *pi, int64_t n_u, const int32_t *lanes, int n_sel,
-                                                          float *out) {
-    __shared__ float tile[kWave][kWave + 1];
-    const int64_t u0 = (int64_t)blockIdx.x * kWave;
+// Reads a 64-row block of one tile into LDS: tile[i][q] = pi[u0 + i][q].
+__device__ __forceinline__ void load_row_block(const float *pi, int64_t u0, int64_t n_u, float (*tile)[kTileQ + 1]) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int i = wid; i < kWave; i += kWavesPerBlock) {
         const int64_t u = u0 + i;
-        tile[i][lane] = u < n_u ? pi[u * kTileQ + lane] : 0.0f;
+        const QV v = u < n_u ? qv_load(pi + u * kTileQ + lane * kVec) : qv_zero();
+#pragma unroll
+        for (int j = 0; j < kVec; ++j) tile[i][lane * kVec + j] = v.v[j];
     }
     __syncthreads();
+}
+
+// out[j * n_u + u] = pi[u][lanes[j]] for the j < n_sel selected queries of one tile.
+__global__ void __launch_bounds__(kBlock) kb_gather_lanes(const float *pi, int64_t n_u, const int32_t *lanes, int n_sel,
+                                                          float *out) {
+    __shared__ float tile[kWave][kTileQ + 1];
+    const int64_t u0 = (int64_t)blockIdx.x * kWave;
+    load_row_block(pi, u0, n_u, tile);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int j = wid; j < n_sel; j += kWavesPerBlock) {
         const int q = lanes[j];
         const int64_t u = u0 + lane;
@@ -401,41 +537,43 @@ __global__ void __launch_bounds__(kBlock) kb_gather_lanes(const float *pi, int64
     }
 }
 
-// out[(t * kTileQ + q) * n_u + u] = pi[t][u][q], through 64 x 64 LDS tiles.
+// out[(t * kTileQ + q) * n_u + u] = pi[t][u][q] for rows t * kTileQ + q < n_rows_valid.
 __global__ void __launch_bounds__(kBlock) kb_transpose(const float *pi, int64_t pi_stride, int64_t n_u, float *out,
                                                        int64_t n_rows_valid) {
-    __shared__ float tile[kWave][kWave + 1];
+    __shared__ float tile[kWave][kTileQ + 1];
     const int t = blockIdx.y;
     const int64_t u0 = (int64_t)blockIdx.x * kWave;
-    const float *src = pi + t * pi_stride;
+    load_row_block(pi + t * pi_stride, u0, n_u, tile);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int i = wid; i < kWave; i += kWavesPerBlock) {
-        const int64_t u = u0 + i;
-        tile[i][lane] = u < n_u ? src[u * kTileQ + lane] : 0.0f;
-    }
-    __syncthreads();
-    for (int q = wid; q < kWave; q += kWavesPerBlock) {
+    for (int q = wid; q < kTileQ; q += kWavesPerBlock) {
         const int64_t row = (int64_t)t * kTileQ + q;
         const int64_t u = u0 + lane;
         if (row < n_rows_valid && u < n_u) out[row * n_u + u] = tile[lane][q];
     }
 }
 
-// Per-lane sums of a tile vector: blk[t][block][q].
+// Per-query sums of a tile vector: blk[t][block][q].
 __global__ void __launch_bounds__(kBlock) kb_sums(const float *x, int64_t x_stride, int64_t n_u, double *blk) {
-    __shared__ double s[kWavesPerBlock][kWave];
+    __shared__ double s[kWavesPerBlock][kTileQ];
     const int t = blockIdx.y;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const float *xt = x + t * x_stride;
-    double acc = 0.0;
-    for (int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + wid; u < n_u; u += (int64_t)gridDim.x * kWavesPerBlock)
-        acc += (double)xt[u * kTileQ + lane];
-    s[wid][lane] = acc;
+    double acc[kVec];
+#pragma unroll
+    for (int j = 0; j < kVec; ++j) acc[j] = 0.0;
+    for (int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + wid; u < n_u; u += (int64_t)gridDim.x * kWavesPerBlock) {
+        const QV v = qv_load(xt + u * kTileQ + lane * kVec);
+#pragma unroll
+        for (int j = 0; j < kVec; ++j) acc[j] += (double)v.v[j];
+    }
+#pragma unroll
+    for (int j = 0; j < kVec; ++j) s[wid][lane * kVec + j] = acc[j];
     __syncthreads();
-    if (wid == 0) {
+    const int q = threadIdx.x;
+    if (q < kTileQ) {
         double v = 0.0;
-        for (int i = 0; i < kWavesPerBlock; ++i) v += s[i][lane];
-        blk[((int64_t)t * gridDim.x + blockIdx.x) * kTileQ + lane] = v;
+        for (int i = 0; i < kWavesPerBlock; ++i) v += s[i][q];
+        blk[((int64_t)t * gridDim.x + blockIdx.x) * kTileQ + q] = v;
     }
 }
 
@@ -515,7 +653,7 @@ void batch_init(Graph &g, BatchState &b, int nt, const int32_t *sources, const f
     InitQuery *dq = nullptr;
     check_hip(hipMallocAsync((void **)&dq, hq.size() * sizeof(InitQuery), s), "batch init");
     check_hip(hipMemcpyAsync(dq, hq.data(), hq.size() * sizeof(InitQuery), hipMemcpyHostToDevice, s), "batch init");
-    hipLaunchKernelGGL(kb_init, dim3(nt), dim3(kWave), 0, s, b.ctl, b.r, tile_u, dq, n_valid, max_iters);
+    hipLaunchKernelGGL(kb_init, dim3(nt), dim3(kTileQ), 0, s, b.ctl, b.r, tile_u, dq, n_valid, max_iters);
     check_hip(hipFreeAsync(dq, s), "batch init");
     check_hip(hipGetLastError(), "batch init launch");
 }
@@ -559,7 +697,7 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
         a.blk_np += slot;
         hipLaunchKernelGGL((kb_fix<kBFwd>), dim3(p.fwd_fix, nt), dim3(kBlock), 0, s, a);
     }
-    hipLaunchKernelGGL(kb_control, dim3(nt), dim3(kWave), 0, s, b.ctl, b.blk_max, b.blk_np, sf, su, g.grid_cap,
+    hipLaunchKernelGGL(kb_control, dim3(nt), dim3(kTileQ), 0, s, b.ctl, b.blk_max, b.blk_np, sf, su, g.grid_cap,
                        (int)p.back, (int)p.back_fix, (int)p.fwd, (int)p.fwd_fix, make_rule(g));
     check_hip(hipGetLastError(), "batch round launch");
 }
@@ -590,7 +728,7 @@ void batch_empty(Graph &g, BatchState &b, int nt, hipStream_t s) {
     const int64_t tile_u = g.n_u * kTileQ;
     hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.r, (int64_t)nt * tile_u);
     hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.pi, (int64_t)nt * tile_u);
-    hipLaunchKernelGGL(kb_init, dim3(nt), dim3(kWave), 0, s, b.ctl, b.r, tile_u, (const InitQuery *)nullptr,
+    hipLaunchKernelGGL(kb_init, dim3(nt), dim3(kTileQ), 0, s, b.ctl, b.r, tile_u, (const InitQuery *)nullptr,
                        (int64_t)0, (int32_t)1);
     check_hip(hipGetLastError(), "batch empty launch");
 }
@@ -598,8 +736,8 @@ void batch_empty(Graph &g, BatchState &b, int nt, hipStream_t s) {
 void batch_admit(Graph &g, BatchState &b, const std::vector<AdmitReq> &reqs, int32_t max_iters, hipStream_t s) {
     if (reqs.empty()) return;
     const int64_t tile_u = g.n_u * kTileQ;
-    std::vector<unsigned long long> masks((size_t)b.tiles, 0ull);
-    for (const AdmitReq &a : reqs) masks[a.tile] |= 1ull << a.lane;
+    std::vector<unsigned long long> masks((size_t)b.tiles * kMaskWords, 0ull);
+    for (const AdmitReq &a : reqs) masks[(size_t)a.tile * kMaskWords + a.lane / 64] |= 1ull << (a.lane % 64);
     unsigned long long *dm = nullptr;
     AdmitReq *dr = nullptr;
     check_hip(hipMallocAsync((void **)&dm, masks.size() * 8, s), "admit");

@@ -44,7 +44,7 @@ Server::Server(Graph &g, int64_t max_device_bytes, int32_t k, int32_t max_iters,
     const int64_t per_tile = batch_tile_bytes(g, false);
     const int64_t tiles = (budget - scratch) / per_tile;
     if (tiles < 1)
-        throw Failure{AHPP_ERR_OUT_OF_MEMORY, "ahpp_server_create: budget holds no 64-query tile (" +
+        throw Failure{AHPP_ERR_OUT_OF_MEMORY, "ahpp_server_create: budget holds no query tile (" +
                                                   std::to_string(per_tile + scratch) + " bytes needed)"};
     const int nt = (int)std::min<int64_t>(tiles, 1 << 14);
     try {
