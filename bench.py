@@ -10,9 +10,12 @@ the timed region; the timed region covers the whole batch (rounds of
 Algorithm 4 and the top-k) for `--steps` batches.
 
 Also reported: the plain single-query push on the same GPU (sources drawn
-proportional to degree) with p50 / p99 latency, the roofline of the dominant
-gather kernel (algorithmic bytes / HIP-event time, against 8 TB/s HBM), and
-the CPU oracle's FP64 ASRP on one query of the same graph.
+proportional to degree) with p50 / p99 latency; a serving run of the
+continuous-batching server on the same graph (Poisson arrivals, sources
+proportional to degree, eps uniform on {1e-5, 1e-6, 1e-7, 1e-8}, latency from
+arrival to top-k on the host); the roofline of the dominant gather kernel
+(algorithmic bytes / HIP-event time, against 8 TB/s HBM); and the CPU
+oracle's FP64 ASRP on one query of the same graph.
 
 Prints one JSON line.
 """
@@ -64,16 +67,47 @@ def _traffic(kernel_kind_name):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(g, source, eps):
+def cpu_baseline(g, sources, eps):
+    """The oracle's FP64 ASRP (lambda from Theorem 3) on the host cores: one
+    query on one thread (latency), then one query per thread on every thread
+    the oracle's OpenMP runtime offers (throughput, the reported value)."""
     import oracle
     og = oracle.OracleGraph.from_graph(g)
     lam = og.lambda_thm3()
     t0 = time.perf_counter()
-    _, _, st, ok = og.asrp(int(source), eps, lam)
-    dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 full FP64 ASRP query (source {int(source)}, eps {eps:g}, {st.iterations} rounds, "
-                      f"lambda from Theorem 3) on the same graph, 1 thread, {dt:.1f} s"}
+    _, _, st, ok = og.asrp(int(sources[0]), eps, lam)
+    dt1 = time.perf_counter() - t0
+    nth = max(1, min(oracle.max_threads(), len(sources)))
+    t0 = time.perf_counter()
+    _, _, bad = og.asrp_many(sources[:nth], eps, lam, nthreads=nth)
+    dtn = time.perf_counter() - t0
+    return {"value": nth / dtn, "unit": "queries/s", "cores": nth, "kind": "oracle",
+            "single_thread_ms": round(dt1 * 1e3, 1),
+            "sample": f"{nth} full FP64 ASRP queries (sources proportional to degree, eps {eps:g}, lambda from "
+                      f"Theorem 3) on the same graph, one per thread on {nth} threads, {dtn:.1f} s; one of them "
+                      f"alone on 1 thread: {dt1:.1f} s, {st.iterations} rounds"}
+
+
+SERVE_EPS = (1e-5, 1e-6, 1e-7, 1e-8)
+
+
+def serve_leg(ahpp, synth, g, dg, args):
+    """Continuous batching under Poisson arrivals on the loaded graph."""
+    from paper_2512_11606_amd import serve
+    n = args.serve_queries
+    sources = synth.degree_queries(g, n, 2003)
+    pick = (synth.CounterRNG(2003, "serve_eps").uniform(n) * len(SERVE_EPS)).astype(int)
+    eps = [SERVE_EPS[min(i, len(SERVE_EPS) - 1)] for i in pick]
+    srv = ahpp.Server(dg, k=50, max_slots=args.serve_slots)
+    try:
+        summary, res = serve.run(srv, sources, eps, rate_qps=args.serve_rate, rounds_per_step=args.serve_rounds,
+                                 max_wall_s=180.0)
+    finally:
+        srv.close()
+    summary["converged"] = sum(1 for r in res.values() if r["stats"]["converged"] == 1)
+    summary["eps_set"] = list(SERVE_EPS)
+    summary["k"] = 50
+    return {kk: (round(v, 2) if isinstance(v, float) else v) for kk, v in summary.items()}
 
 
 def main():
@@ -84,6 +118,11 @@ def main():
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--plain", type=int, default=32, help="plain single queries timed for latency")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-queries", type=int, default=800)
+    ap.add_argument("--serve-rate", type=float, default=150.0, help="offered load, queries/s")
+    ap.add_argument("--serve-slots", type=int, default=256)
+    ap.add_argument("--serve-rounds", type=int, default=4, help="rounds per server step")
     ap.add_argument("--graph", default="m1")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (counter calibration) and exit")
@@ -142,6 +181,8 @@ def main():
         lat.append((time.perf_counter() - a) * 1e3)
     plain_qps = len(lat) / (sum(lat) / 1e3)
 
+    serving = None if args.no_serve else serve_leg(ahpp, synth, g, dg, args)
+
     dom_kind = max(prof, key=lambda kk: prof[kk]["ms"])
     dom = prof[dom_kind]
     name = {ahpp.PROF_BATCH_BACK: "kb_gather<back>", ahpp.PROF_BATCH_FWD: "kb_gather<fwd>"}[dom_kind]
@@ -170,10 +211,11 @@ def main():
         "plain_latency_ms_p99": round(_percentile(lat, 99), 2),
         "batched_over_plain": round(value / plain_qps, 2),
         "topk_complete": topk_ok,
+        "serving": serving,
         "roofline": roofline,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(g, plain_src[0], eps)
+        out["cpu_baseline"] = cpu_baseline(g, plain_src, eps)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

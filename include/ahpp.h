@@ -162,7 +162,7 @@ ahpp_status_t ahpp_topk(const ahpp_graph_t *g, const float *pi, int32_t k, int32
 
 /* Serving engine: queries that arrive over time share the device with
  * continuous batching.  The engine holds `slots` concurrent queries (lanes of
- * 64-query tiles, each with its own residues, reserves, threshold, phase and
+ * 256-query tiles, each with its own residues, reserves, threshold, phase and
  * stop rule, exactly as ahpp_query_batch); a query waits in a host queue
  * until a slot is free, then runs in the same rounds as every other running
  * query, and leaves its slot as soon as its stop rule holds.  Results are the
@@ -171,14 +171,17 @@ ahpp_status_t ahpp_topk(const ahpp_graph_t *g, const float *pi, int32_t k, int32
 typedef struct ahpp_server ahpp_server_t;
 
 /* Creates a server on graph g (which must outlive it).
- *   max_device_bytes: budget for per-query device state; slots = 64 * the
- *     number of tiles that fit (<= 0: a quarter of the free memory), >= 64.
+ *   max_device_bytes: budget for per-query device state; slots = 256 * the
+ *     number of 256-query tiles that fit (<= 0: a quarter of the free
+ *     memory), at least 256.
+ *   max_slots: cap on the slots (<= 0: none), rounded up to whole tiles;
+ *     fewer slots mean fewer tiles per round, so each round is shorter.
  *   k: top-k size of every result, 1..2048.  max_iters: round cap per query
  *     (<= 0: 100000).  keep_pi: nonzero keeps each finished query's full
  *     vector until its result is read (ahpp_server_results pi_out).
  * Errors: INVALID_ARG, OUT_OF_MEMORY (budget below one tile), DEVICE. */
-ahpp_status_t ahpp_server_create(ahpp_graph_t *g, int64_t max_device_bytes, int32_t k, int32_t max_iters,
-                                 int32_t keep_pi, ahpp_server_t **out);
+ahpp_status_t ahpp_server_create(ahpp_graph_t *g, int64_t max_device_bytes, int32_t max_slots, int32_t k,
+                                 int32_t max_iters, int32_t keep_pi, ahpp_server_t **out);
 void ahpp_server_free(ahpp_server_t *s);
 
 /* Queues one query (host only, no device work): source in U, eps > 0 (Eq. 4);

@@ -86,7 +86,7 @@ def load_library(path: str = LIB_PATH):
     lib.ahpp_topk.restype = ctypes.c_int
     lib.ahpp_topk.argtypes = [P, P, i32, i32, P, P, P, P]
     lib.ahpp_server_create.restype = ctypes.c_int
-    lib.ahpp_server_create.argtypes = [P, i64, i32, i32, i32, ctypes.POINTER(ctypes.c_void_p)]
+    lib.ahpp_server_create.argtypes = [P, i64, i32, i32, i32, i32, ctypes.POINTER(ctypes.c_void_p)]
     lib.ahpp_server_free.restype = None
     lib.ahpp_server_free.argtypes = [P]
     lib.ahpp_server_submit.restype = ctypes.c_int
@@ -271,13 +271,14 @@ def ahpp_profile_read(g: Graph, kind: int) -> dict:
 class Server:
     """Continuous-batching server over a loaded graph (ahpp_server_* in ahpp.h)."""
 
-    def __init__(self, g: Graph, k: int, max_device_bytes: int = 0, max_iters: int = 0, keep_pi: bool = False):
+    def __init__(self, g: Graph, k: int, max_device_bytes: int = 0, max_iters: int = 0, keep_pi: bool = False,
+                 max_slots: int = 0):
         self.g = g
         self.k = int(k)
         self.keep_pi = bool(keep_pi)
         h = ctypes.c_void_p()
-        _check(load_library().ahpp_server_create(g._h, int(max_device_bytes), self.k, int(max_iters),
-                                                 1 if keep_pi else 0, ctypes.byref(h)))
+        _check(load_library().ahpp_server_create(g._h, int(max_device_bytes), int(max_slots), self.k,
+                                                 int(max_iters), 1 if keep_pi else 0, ctypes.byref(h)))
         self._h = h
 
     def close(self):

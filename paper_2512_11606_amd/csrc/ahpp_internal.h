@@ -233,7 +233,7 @@ void batch_lanes_out(Graph &g, BatchState &b, int tile, const int32_t *d_lanes, 
 // serve.hip: continuous batching over the lanes of a private batch state.
 class Server {
   public:
-    Server(Graph &g, int64_t max_device_bytes, int32_t k, int32_t max_iters, bool keep_pi);
+    Server(Graph &g, int64_t max_device_bytes, int32_t max_slots, int32_t k, int32_t max_iters, bool keep_pi);
     ~Server();
     void submit(int64_t tag, int32_t source, double eps);
     int step(int rounds, hipStream_t s);

@@ -161,8 +161,8 @@ extern "C" {
 
 const char *ahpp_last_error(void) { return g_last_error.c_str(); }
 
-ahpp_status_t ahpp_server_create(ahpp_graph_t *h, int64_t max_device_bytes, int32_t k, int32_t max_iters,
-                                 int32_t keep_pi, ahpp_server_t **out) {
+ahpp_status_t ahpp_server_create(ahpp_graph_t *h, int64_t max_device_bytes, int32_t max_slots, int32_t k,
+                                 int32_t max_iters, int32_t keep_pi, ahpp_server_t **out) {
     g_last_error.clear();
     if (!h || !out) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_create: NULL argument");
     *out = nullptr;
@@ -171,7 +171,7 @@ ahpp_status_t ahpp_server_create(ahpp_graph_t *h, int64_t max_device_bytes, int3
     if (!srv) return fail(AHPP_ERR_OUT_OF_MEMORY, "ahpp_server_create: host allocation failed");
     try {
         DeviceScope scope(h->g.device);
-        srv->impl = new Server(h->g, max_device_bytes, k, max_iters, keep_pi != 0);
+        srv->impl = new Server(h->g, max_device_bytes, max_slots, k, max_iters, keep_pi != 0);
     } catch (const Failure &f) {
         delete srv;
         return fail(f.status, f.msg);

@@ -5,9 +5,9 @@
 // and stop rule (the per-query control of the batched rounds).  A step
 //   1. admits queued queries into free lanes (their columns are cleared and
 //      the source gets unit residue, Algorithm 4's initial state),
-//   2. runs a fixed number of rounds for every tile (stopped lanes keep
-//      threshold +inf and do not change; tiles with no running lane return
-//      at once),
+//   2. runs a fixed number of rounds over the tiles up to the last one with
+//      a running lane (stopped lanes keep threshold +inf and do not change;
+//      tiles with no running lane return at once),
 //   3. collects the lanes whose stop rule held: their reserves are copied out
 //      query-major, reduced to the top-k on the device, copied to the host,
 //      and the lane is free for the next admission.
@@ -30,7 +30,7 @@ double now_ms() {
 }
 }  // namespace
 
-Server::Server(Graph &g, int64_t max_device_bytes, int32_t k, int32_t max_iters, bool keep_pi)
+Server::Server(Graph &g, int64_t max_device_bytes, int32_t max_slots, int32_t k, int32_t max_iters, bool keep_pi)
     : g_(g), k_(k), max_iters_(max_iters > 0 ? max_iters : 100000), keep_pi_(keep_pi) {
     const int64_t before = g.device_bytes;
     const int64_t scratch = (int64_t)kTileQ * g.n_u * 4 + (int64_t)kTileQ * k * 8 + 4096 +
@@ -46,7 +46,9 @@ Server::Server(Graph &g, int64_t max_device_bytes, int32_t k, int32_t max_iters,
     if (tiles < 1)
         throw Failure{AHPP_ERR_OUT_OF_MEMORY, "ahpp_server_create: budget holds no query tile (" +
                                                   std::to_string(per_tile + scratch) + " bytes needed)"};
-    const int nt = (int)std::min<int64_t>(tiles, 1 << 14);
+    int64_t cap = 1 << 14;
+    if (max_slots > 0) cap = std::min<int64_t>(cap, ((int64_t)max_slots + kTileQ - 1) / kTileQ);
+    const int nt = (int)std::min<int64_t>(tiles, cap);
     try {
         ensure_batch_state(g, b_, nt, false);
         d_scores_ = (float *)dev_alloc(g, (size_t)kTileQ * g.n_u * 4, "server scores");
@@ -90,12 +92,20 @@ int Server::step(int rounds, hipStream_t s) {
         reqs.push_back(AdmitReq{(int32_t)(i / kTileQ), (int32_t)(i % kTileQ), p.source, (float)(p.eps / g_.lambda)});
     }
     batch_admit(g_, b_, reqs, max_iters_, s);
+    // Admission fills the lowest free lanes, so running queries gather in the
+    // low tiles: rounds cover tiles [0, active) only, and each active tile
+    // gets a larger share of the workgroups.
     int64_t running = 0;
-    for (const Lane &l : lanes_) running += l.busy;
+    int active = 0;
+    for (size_t i = 0; i < lanes_.size(); ++i)
+        if (lanes_[i].busy) {
+            ++running;
+            active = (int)(i / kTileQ) + 1;
+        }
     // 2. Rounds for every running query.
     if (running > 0) {
         b_.live_q = running;
-        for (int i = 0; i < rounds; ++i) batch_round(g_, b_, b_.tiles, s);
+        for (int i = 0; i < rounds; ++i) batch_round(g_, b_, active, s);
     }
     // 3. Collection of stopped queries.
     std::vector<TileCtl> ctl((size_t)b_.tiles);

@@ -108,6 +108,11 @@ def test_budget_and_argument_errors(env):
     assert e.value.status == ahpp.ERR_OUT_OF_MEMORY
     with pytest.raises(ahpp.AhppError):
         ahpp.Server(dg, k=0)
+    # A slot cap rounds up to whole 256-query tiles.
+    for cap, want in ((1, 256), (256, 256), (257, 512)):
+        s2 = ahpp.Server(dg, k=10, max_device_bytes=1 << 30, max_slots=cap)
+        assert s2.info()["slots"] == want
+        s2.close()
     srv = ahpp.Server(dg, k=10, max_device_bytes=1 << 30)
     with pytest.raises(ahpp.AhppError):
         srv.submit(0, g.n_u, 1e-6)
