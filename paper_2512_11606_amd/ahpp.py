@@ -318,7 +318,10 @@ class Server:
         if want_pi:
             if not self.keep_pi:
                 raise ValueError("server was created without keep_pi")
-            pi = torch.empty((max_n, self.g.n_u), dtype=torch.float32, device=torch.device("cuda", self.g.device))
+            # Only as many vectors as are waiting (each is n_u floats).
+            max_n = min(max_n, self.info()["ready"])
+            pi = torch.empty((max(max_n, 1), self.g.n_u), dtype=torch.float32,
+                             device=torch.device("cuda", self.g.device))
         n = ctypes.c_int32(0)
         _check(load_library().ahpp_server_results(self._h, max_n, _np_ptr(tags), _np_ptr(idx), _np_ptr(val),
                                                   _np_ptr(tn), ctypes.cast(st, ctypes.c_void_p), _dev_ptr(pi),

@@ -35,6 +35,21 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
+SYNTH_SRC = os.path.join(HERE, "synth_native.cpp")
+SYNTH_LIB = os.path.join(HERE, "libsynth.so")
+
+
+def build_synth(verbose: bool = False) -> str:
+    """Host-only input generator (g++, OpenMP): same arrays as synth.py."""
+    tmp = SYNTH_LIB + ".tmp"
+    cmd = ["g++", "-O3", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-Wall", SYNTH_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, SYNTH_LIB)
+    return SYNTH_LIB
+
+
 def build(verbose: bool = False, jobs: int = 5) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
@@ -51,4 +66,6 @@ def build(verbose: bool = False, jobs: int = 5) -> str:
 
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)
+    build_synth(verbose="-v" in sys.argv)
     print(LIB)
+    print(SYNTH_LIB)

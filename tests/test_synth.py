@@ -43,3 +43,46 @@ def test_query_sets():
     assert deg[d].mean() > deg.mean()                            # degree-biased
     u = synth.uniform_queries(g, 10, 1)
     assert np.array_equal(u, synth.uniform_queries(g, 10, 1))
+
+
+def _native_lib():
+    import os
+    from paper_2512_11606_amd import build
+    if not os.path.exists(build.SYNTH_LIB):
+        build.build_synth()
+    lib = synth.native_lib()
+    assert lib is not None
+    return lib
+
+
+FIELDS = ("edge_u", "edge_v", "edge_w", "assoc_u", "assoc_a", "assoc_w")
+
+
+def test_native_generator_matches_numpy_definition():
+    """libsynth.so repeats synth.py's steps: identical arrays, including
+    heavy edge rejection (few V nodes), the over-full last round, lonely U
+    nodes, and attribute lists that need several rejection rounds."""
+    _native_lib()
+    cases = [("tiny", None), ((5000, 2000, 40000, 200, 6, 717), {}),
+             ((3000, 50, 20000, 30, 25, 9), {}), ((4000, 3000, 4500, 40, 3, 11), {"gamma": 2.6}),
+             ((20000, 10000, 300000, 500, 12, 5), {"attr_exponent": 1.3})]
+    for args, kw in cases:
+        if isinstance(args, str):
+            a, b = synth.make_graph(args, native=False), synth.make_graph(args, native=True)
+        else:
+            a = synth.make_custom(*args, native=False, **kw)
+            b = synth.make_custom(*args, native=True, **kw)
+        for f in FIELDS:
+            x, y = getattr(a, f), getattr(b, f)
+            assert x.dtype == y.dtype and np.array_equal(x, y), (args, f)
+    # The sparse case really had lonely U nodes to fix and many rejections.
+    g = synth.make_custom(4000, 3000, 4500, 40, 3, 11, gamma=2.6, native=True)
+    assert np.bincount(g.edge_u, minlength=g.n_u).min() >= 1 and g.m_e > 4500
+
+
+def test_native_generator_needs_the_library_when_forced(monkeypatch):
+    monkeypatch.setattr(synth, "_NATIVE_LIB", None)
+    monkeypatch.setattr(synth.os.path, "exists", lambda p: False)
+    import pytest
+    with pytest.raises(RuntimeError):
+        synth.make_graph("tiny", native=True)
