@@ -165,7 +165,8 @@ def main():
         res = ahpp.ahpp_query_batch(dg, sources, eps, k=k, want_pi=False, want_stats=False)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = {kind: ahpp.ahpp_profile_read(dg, kind) for kind in (ahpp.PROF_BATCH_BACK, ahpp.PROF_BATCH_FWD)}
+    prof = {kind: ahpp.ahpp_profile_read(dg, kind)
+            for kind in (ahpp.PROF_BATCH_BACK, ahpp.PROF_BATCH_FWD, ahpp.PROF_BATCH_HOT)}
     ahpp.ahpp_profile_enable(dg, False)
     elapsed = t1 - t0
     value = args.batch * args.steps / elapsed
@@ -185,7 +186,8 @@ def main():
 
     dom_kind = max(prof, key=lambda kk: prof[kk]["ms"])
     dom = prof[dom_kind]
-    name = {ahpp.PROF_BATCH_BACK: "kb_gather<back>", ahpp.PROF_BATCH_FWD: "kb_gather<fwd>"}[dom_kind]
+    name = {ahpp.PROF_BATCH_BACK: "kb_gather<back>", ahpp.PROF_BATCH_FWD: "kb_gather<fwd>",
+            ahpp.PROF_BATCH_HOT: "kb_hot"}[dom_kind]
     avg_ms = dom["ms"] / max(dom["launches"], 1)
     bytes_per_launch = dom["bytes"] / max(dom["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
@@ -213,6 +215,11 @@ def main():
         "topk_complete": topk_ok,
         "serving": serving,
         "roofline": roofline,
+        "kernels": {kname: {"launches": prof[kk]["launches"],
+                            "avg_ms": round(prof[kk]["ms"] / max(prof[kk]["launches"], 1), 4),
+                            "algo_GBps": round(prof[kk]["bytes"] / max(prof[kk]["ms"], 1e-9) / 1e6, 1)}
+                    for kk, kname in ((ahpp.PROF_BATCH_BACK, "kb_gather<back>"), (ahpp.PROF_BATCH_FWD, "kb_gather<fwd>"),
+                                      (ahpp.PROF_BATCH_HOT, "kb_hot"))},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, plain_src, eps)

@@ -215,7 +215,9 @@ ahpp_status_t ahpp_server_info(const ahpp_server_t *s, int32_t *slots, int32_t *
  * (CSR entries and offsets once per launch, one 4-byte residue per entry and
  * query, and the per-row, per-query state the epilogue reads and writes).
  * Kinds: 0 single-query V/attribute gather, 1 single-query U gather,
- *        2 batched V/attribute gather, 3 batched U gather.
+ *        2 batched V/attribute gather (rows other than the hot rows),
+ *        3 batched U gather, 4 batched hot-row pass (the longest V/attribute
+ *        rows summed by streaming the U residues once, plus its reduction).
  * ahpp_profile_enable(g, 1) clears the totals and starts; (g, 0) stops.
  * ahpp_profile_read waits for the recorded events and returns the totals
  * (host pointers, each nullable).  Errors: INVALID_ARG (NULL graph or bad

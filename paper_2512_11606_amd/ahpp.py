@@ -25,7 +25,7 @@ EXPORTED = ("ahpp_graph_load", "ahpp_graph_info", "ahpp_graph_free", "ahpp_query
             "ahpp_server_results", "ahpp_server_info", "ahpp_profile_enable", "ahpp_profile_read", "ahpp_last_error")
 
 # Kernel kinds of ahpp_profile_read.
-PROF_SINGLE_BACK, PROF_SINGLE_FWD, PROF_BATCH_BACK, PROF_BATCH_FWD = 0, 1, 2, 3
+PROF_SINGLE_BACK, PROF_SINGLE_FWD, PROF_BATCH_BACK, PROF_BATCH_FWD, PROF_BATCH_HOT = 0, 1, 2, 3, 4
 
 
 class AhppError(RuntimeError):

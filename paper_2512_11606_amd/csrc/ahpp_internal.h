@@ -109,14 +109,40 @@ struct BatchState {
     float *part = nullptr;          // [tiles][max(n_items)][kTileQ]
     TileCtl *ctl = nullptr;         // [tiles]
     float *blk_max = nullptr;       // [tiles][2][grid_x][kTileQ]
-    unsigned long long *blk_np = nullptr;  // [tiles][4][grid_x][kTileQ]
+    unsigned long long *blk_np = nullptr;  // [tiles][5][grid_x][kTileQ]
+    float *hot_part = nullptr;      // [tiles][hot chunks][hot rows][kTileQ]
     float *out = nullptr;           // [tiles * kTileQ][n_u] query-major scores for top-k
     double *sums = nullptr;         // [tiles][grid_x][kTileQ] residue sums
     int64_t live_q = 0;             // queries still running at the last poll
 };
 
+// Hot rows: the longest rows of the back CSR (the most popular attributes
+// and V nodes).  The batched engine does not gather them entry by entry: it
+// streams each tile's U rows once, in fixed chunks, and accumulates every hot
+// row's sum in LDS (one thread per query column, so each accumulator has one
+// writer and the sum order is fixed), then adds the chunk partials in chunk
+// order.
+constexpr int kHotMax = 128;             // at most this many (LDS: kHotMax x kTileQ floats)
+constexpr int kHotWaves = 16;            // waves of the streaming pass; wave g owns h % 16 == g
+constexpr int kHotPerWave = kHotMax / kHotWaves;  // hot rows (register accumulators) per wave
+constexpr int64_t kHotMinLen = 1024;     // a hot row has at least one full item of entries
+struct HotSet {
+    int32_t n = 0;                       // hot rows (0: none, the batch gathers every row)
+    int32_t *rows = nullptr;             // [n] back row of hot index h
+    int32_t *len = nullptr;              // [n] entries of that row
+    DevCsr list;                         // rows g * n_u + u: (hot index, back weight) of u's hot
+                                         // rows h with h % kHotWaves == g, by h
+    int32_t n_chunks = 0;                // fixed U chunks of the streaming pass
+    int64_t chunk_rows = 0;
+    WorkItem *cold_items = nullptr;      // back schedule without the hot rows
+    int64_t n_cold_items = 0;
+    SplitRow *cold_split = nullptr;
+    int64_t n_cold_split = 0;
+    int64_t cold_nnz = 0, cold_rows = 0;
+};
+
 // Launch timing of the gather kernels (see ahpp_profile_enable).
-constexpr int kProfKinds = 4;
+constexpr int kProfKinds = 5;
 struct ProfLaunch {
     int kind;
     hipEvent_t start, stop;
@@ -125,9 +151,9 @@ struct ProfLaunch {
 struct Profiler {
     bool on = false;
     std::vector<ProfLaunch> pending;
-    int64_t launches[kProfKinds] = {0, 0, 0, 0};
-    double ms[kProfKinds] = {0, 0, 0, 0};
-    double bytes[kProfKinds] = {0, 0, 0, 0};
+    int64_t launches[kProfKinds] = {};
+    double ms[kProfKinds] = {};
+    double bytes[kProfKinds] = {};
 };
 // Records `kind` around the launches issued by f() when profiling is on.
 template <class F>
@@ -162,6 +188,7 @@ struct Graph {
     DevCsr back;                    // rows V then attributes (n_v + a); cols U; weights
                                     // w(u,x) c_d(u) (V rows) or w(u,x) c_s(u) (attribute rows)
     float *inv_b = nullptr;         // 1/d(v) for V rows, 1/t(a) for attribute rows
+    HotSet hot;                     // batched engine: hot back rows and the cold schedule
     int64_t dangling_u = 0;
     int64_t device_bytes = 0;
     double load_ms = 0, lambda_ms = 0;

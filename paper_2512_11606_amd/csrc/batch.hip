@@ -93,13 +93,19 @@ struct BArgs {
     TileCtl *ctl;          // tile 0
     int64_t x_stride, y_stride, pi_stride, part_stride;  // floats per tile
     float *blk_max;        // [tile][2][grid_cap][kTileQ] slot base of this launch
-    unsigned long long *blk_np;  // [tile][4][grid_cap][kTileQ] slot base
+    unsigned long long *blk_np;  // [tile][5][grid_cap][kTileQ] slot base
     int64_t blk_stride_f, blk_stride_u;   // elements per tile
     float alpha;
 };
 
 __device__ __forceinline__ float readlane_f(float v, int k) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int k) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, k);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), k);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 __device__ __forceinline__ int64_t lane_col() { return (int64_t)(threadIdx.x & 63) * kVec; }
@@ -360,7 +366,7 @@ __global__ void __launch_bounds__(kBlock) kb_fix(BArgs a) {
 // partials, then the stop / switch rule of Algorithm 4 for every running query.
 __global__ void __launch_bounds__(kTileQ) kb_control(TileCtl *ctl, const float *blk_max, const unsigned long long *blk_np,
                                                      int64_t stride_f, int64_t stride_u, int grid_cap, int n_back,
-                                                     int n_back_fix, int n_fwd, int n_fwd_fix, Rule rule) {
+                                                     int n_back_fix, int n_fwd, int n_fwd_fix, int n_hot, Rule rule) {
     __shared__ int running_any[kTileQ / kWave];
     const int t = blockIdx.x;
     TileCtl &tc = ctl[t];
@@ -372,8 +378,8 @@ __global__ void __launch_bounds__(kTileQ) kb_control(TileCtl *ctl, const float *
     for (int i = 0; i < n_fwd; ++i) m = fmaxf(m, bm[(int64_t)i * kTileQ + q]);
     for (int i = 0; i < n_fwd_fix; ++i) m = fmaxf(m, bm[((int64_t)grid_cap + i) * kTileQ + q]);
     unsigned long long np = 0;
-    const int cnt[4] = {n_back, n_back_fix, n_fwd, n_fwd_fix};
-    for (int k = 0; k < 4; ++k)
+    const int cnt[5] = {n_back, n_back_fix, n_fwd, n_fwd_fix, n_hot};
+    for (int k = 0; k < 5; ++k)
         for (int i = 0; i < cnt[k]; ++i) np += bn[((int64_t)k * grid_cap + i) * kTileQ + q];
     QueryCtl &c = tc.q[q];
     int done = c.done;
@@ -410,6 +416,192 @@ __global__ void __launch_bounds__(kTileQ) kb_control(TileCtl *ctl, const float *
         for (int i = 0; i < kTileQ / kWave; ++i) any |= running_any[i];
         tc.all_done = any ? 0 : 1;
     }
+}
+
+// ---------------------------------------------------------------- hot rows
+
+struct HotArgs {
+    const float *r;         // residues (tile 0)
+    int64_t r_stride;
+    float *part;            // chunk partials (tile 0), [n_chunks][n_hot][kTileQ]
+    int64_t part_stride;
+    const TileCtl *ctl;
+    int64_t n_u, chunk_rows;
+    int n_hot, n_chunks;
+};
+
+constexpr int kHotThreads = kHotWaves * kWave;  // one workgroup per (chunk, tile)
+constexpr int kHotBlockRows = 32;                // U rows per staged block
+constexpr int kHotStage = kHotBlockRows * kTileQ / 4 / kHotThreads;  // float4 per thread per block
+constexpr int kHotWindow = 2 * kWave;            // hot-list entries per wave held in registers
+constexpr int kHotCols = kTileQ / kWave;         // columns per lane: lane, lane + 64, ...
+static_assert(kHotPerWave == 8, "the accumulator chain below is written for 8 rows per wave");
+static_assert(kHotBlockRows < kWave, "a block's offsets sit one per lane");
+
+// What a wave needs for one block of U rows, loaded one block ahead with
+// vector loads (coalesced, many in flight) and read back with readlane.
+struct HotBlock {
+    float4 x[kHotStage];   // the thread's share of the block's residues (raw)
+    int64_t off;           // lane j <= kHotBlockRows: offset of row ub + j in this wave's list
+    int32_t h0, h1;        // entries e_b + lane and e_b + 64 + lane: hot index
+    float w0, w1;          //   and back weight
+};
+
+// One workgroup of kHotWaves waves per (chunk, tile).  The chunk's U rows are
+// streamed from HBM once: each block of kHotBlockRows rows is loaded one block
+// ahead into registers, thresholded into LDS, and read from there by every
+// wave (one barrier per block).  Wave g owns the hot rows h = g, g + 16, ...,
+// g + 112 and keeps their sums for its lane's columns (l, l + 64, l + 128,
+// l + 192) in registers; its list offsets and a window of its list entries
+// for the block are loaded with the block, so the per-entry work is register
+// arithmetic: for each entry (u, h, w') it adds w' thr(r(u)) to the register
+// row of h.  Each accumulator has one owner and the adds are ordered by u, so
+// the result is deterministic.
+__global__ void __launch_bounds__(kHotThreads) kb_hot(HotArgs a, const int64_t *__restrict__ hot_off,
+                                                      const int32_t *__restrict__ hot_col,
+                                                      const float *__restrict__ hot_w) {
+    __shared__ float4 xs[2][kHotBlockRows * kTileQ / 4];
+    const int t = blockIdx.y;
+    const TileCtl &tc = a.ctl[t];
+    if (tc.all_done) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int grp = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
+    // Staging role: float4 i of the block is row i / 64, columns 4 (i % 64) .. + 3.
+    const int scol = (tid % (kTileQ / 4)) * 4;
+    float sth[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sth[k] = tc.q[scol + k].theta;
+    const float *rt = a.r + t * a.r_stride;
+    float *pt = a.part + t * a.part_stride;
+    const int64_t *off = hot_off + grp * a.n_u;
+    const int c = blockIdx.x;
+    const int64_t u0 = (int64_t)c * a.chunk_rows;
+    const int64_t u1 = u0 + a.chunk_rows < a.n_u ? u0 + a.chunk_rows : a.n_u;
+    float acc[kHotPerWave][kHotCols];
+#pragma unroll
+    for (int k = 0; k < kHotPerWave; ++k)
+#pragma unroll
+        for (int cc = 0; cc < kHotCols; ++cc) acc[k][cc] = 0.0f;
+    const int64_t e_end = off[u1];  // end of this wave's entries in the chunk
+    // Loads of block ub; e_b is the offset of its first row (known from the
+    // previous block, or read directly for the first block).
+    auto load_block = [&](HotBlock &blk, int64_t ub, int64_t e_b) {
+#pragma unroll
+        for (int i = 0; i < kHotStage; ++i) {
+            const int64_t u = ub + (tid + i * kHotThreads) / (kTileQ / 4);
+            blk.x[i] = u < u1 ? *reinterpret_cast<const float4 *>(rt + u * kTileQ + scol)
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        const int64_t ur = ub + lane < u1 ? ub + lane : u1;
+        blk.off = lane <= kHotBlockRows ? off[ur] : 0;
+        blk.h0 = e_b + lane < e_end ? hot_col[e_b + lane] : 0;
+        blk.w0 = e_b + lane < e_end ? hot_w[e_b + lane] : 0.0f;
+        blk.h1 = e_b + kWave + lane < e_end ? hot_col[e_b + kWave + lane] : 0;
+        blk.w1 = e_b + kWave + lane < e_end ? hot_w[e_b + kWave + lane] : 0.0f;
+    };
+    auto stage = [&](int buf, const HotBlock &blk) {
+#pragma unroll
+        for (int i = 0; i < kHotStage; ++i) {
+            float4 v = blk.x[i];
+            v.x = v.x > sth[0] ? v.x : 0.0f;
+            v.y = v.y > sth[1] ? v.y : 0.0f;
+            v.z = v.z > sth[2] ? v.z : 0.0f;
+            v.w = v.w > sth[3] ? v.w : 0.0f;
+            xs[buf][tid + i * kHotThreads] = v;
+        }
+    };
+    if (u0 < u1) {
+        HotBlock cur;
+        load_block(cur, u0, off[u0]);
+        stage(0, cur);
+        __syncthreads();
+        int buf = 0;
+        for (int64_t ub = u0; ub < u1; ub += kHotBlockRows) {
+            const int64_t e_b = readlane_i64(cur.off, 0);
+            HotBlock nxt;
+            load_block(nxt, ub + kHotBlockRows, readlane_i64(cur.off, kHotBlockRows));
+            const float *xb = reinterpret_cast<const float *>(xs[buf]);
+            const int nrows = u1 - ub < kHotBlockRows ? (int)(u1 - ub) : kHotBlockRows;
+            for (int j = 0; j < nrows; ++j) {
+                const int k0 = (int)(readlane_i64(cur.off, j) - e_b);
+                const int k1 = (int)(readlane_i64(cur.off, j + 1) - e_b);
+                if (k0 == k1) continue;
+                float x[kHotCols];
+#pragma unroll
+                for (int cc = 0; cc < kHotCols; ++cc) x[cc] = xb[j * kTileQ + cc * kWave + lane];
+                for (int k = k0; k < k1; ++k) {
+                    int h;
+                    float w;
+                    if (k < kWave) {
+                        h = __builtin_amdgcn_readlane(cur.h0, k);
+                        w = readlane_f(cur.w0, k);
+                    } else if (k < kHotWindow) {
+                        h = __builtin_amdgcn_readlane(cur.h1, k - kWave);
+                        w = readlane_f(cur.w1, k - kWave);
+                    } else {  // a block with more entries than the window: read them directly
+                        h = hot_col[e_b + k];
+                        w = hot_w[e_b + k];
+                    }
+                    const int kr = h / kHotWaves;  // register row of this entry
+#pragma unroll
+                    for (int kk = 0; kk < kHotPerWave; ++kk)
+                        if (kr == kk)
+#pragma unroll
+                            for (int cc = 0; cc < kHotCols; ++cc) acc[kk][cc] += w * x[cc];
+                }
+            }
+            stage(buf ^ 1, nxt);
+            buf ^= 1;
+            cur = nxt;
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kHotPerWave; ++k) {
+        const int h = grp + k * kHotWaves;
+        if (h < a.n_hot)
+#pragma unroll
+            for (int cc = 0; cc < kHotCols; ++cc)
+                pt[((int64_t)c * a.n_hot + h) * kTileQ + cc * kWave + lane] = acc[k][cc];
+    }
+}
+
+struct HotReduceArgs {
+    const float *part;      // tile 0 partials
+    int64_t part_stride;
+    const int32_t *rows, *len;
+    const float *inv_b;
+    float *z;               // tile 0
+    int64_t z_stride;
+    unsigned long long *blk_np;  // n_p slot of this launch (tile 0)
+    int64_t blk_stride_u;
+    const TileCtl *ctl;
+    int n_hot, n_chunks;
+};
+
+// One workgroup per (hot row, tile): z(x) = inv_b(x) * (chunk partials added
+// in chunk order), and the row's entry count for the queries it pushes.
+__global__ void __launch_bounds__(kBlock) kb_hot_reduce(HotReduceArgs a) {
+    const int h = blockIdx.x, t = blockIdx.y;
+    if (a.ctl[t].all_done) return;
+    const int q = threadIdx.x;
+    const float *pt = a.part + t * a.part_stride + (int64_t)h * kTileQ + q;
+    const int64_t cs = (int64_t)a.n_hot * kTileQ;
+    float s = 0.0f;
+    int c = 0;
+    for (; c + 8 <= a.n_chunks; c += 8) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = pt[(c + j) * cs];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += v[j];
+    }
+    for (; c < a.n_chunks; ++c) s += pt[c * cs];
+    const int32_t x = a.rows[h];
+    const float v = a.inv_b[x] * s;
+    a.z[t * a.z_stride + (int64_t)x * kTileQ + q] = v;
+    a.blk_np[t * a.blk_stride_u + (int64_t)h * kTileQ + q] = v > 0.0f ? (unsigned long long)a.len[h] : 0ull;
 }
 
 __global__ void kb_fill(float *p, int64_t n) {
@@ -598,11 +790,28 @@ struct BPlan {
 
 // Workgroups per tile: enough waves to cover the items, at most the
 // per-launch budget spread over the tiles in flight.
+// The back schedule of the batched engine: every row, or only the cold rows
+// when the graph has hot rows.
+struct BackSched {
+    const WorkItem *items;
+    int64_t n_items;
+    const SplitRow *split;
+    int64_t n_split;
+    int64_t nnz, rows;
+};
+
+BackSched back_sched(const Graph &g) {
+    const HotSet &h = g.hot;
+    if (h.n > 0) return BackSched{h.cold_items, h.n_cold_items, h.cold_split, h.n_cold_split, h.cold_nnz, h.cold_rows};
+    return BackSched{g.back.items, g.back.n_items, g.back.split, g.back.n_split, g.back.nnz, g.back.n_rows};
+}
+
 BPlan bplan(const Graph &g, int nt) {
     const int cap = std::min(g.grid_cap, std::max(64, g.grid_cap / std::max(nt, 1)));
+    const BackSched bs = back_sched(g);
     BPlan p;
-    p.back = g.back.n_items ? capped(g.back.n_items, kWavesPerBlock, cap) : 0;
-    p.back_fix = g.back.n_split ? capped(g.back.n_split, kWavesPerBlock, cap) : 0;
+    p.back = bs.n_items ? capped(bs.n_items, kWavesPerBlock, cap) : 0;
+    p.back_fix = bs.n_split ? capped(bs.n_split, kWavesPerBlock, cap) : 0;
     p.fwd = capped(g.fwd.n_items, kWavesPerBlock, cap);
     p.fwd_fix = g.fwd.n_split ? capped(g.fwd.n_split, kWavesPerBlock, cap) : 0;
     return p;
@@ -612,7 +821,7 @@ BPlan bplan(const Graph &g, int nt) {
 
 void free_batch_state(BatchState &b) {
     for (void *p : {(void *)b.r, (void *)b.pi, (void *)b.z, (void *)b.part, (void *)b.ctl, (void *)b.blk_max,
-                    (void *)b.blk_np, (void *)b.out, (void *)b.sums})
+                    (void *)b.blk_np, (void *)b.hot_part, (void *)b.out, (void *)b.sums})
         dfree(p);
     b = BatchState{};
 }
@@ -620,8 +829,9 @@ void free_batch_state(BatchState &b) {
 int64_t batch_tile_bytes(const Graph &g, bool with_out) {
     const int64_t items = std::max<int64_t>(std::max(g.fwd.n_items, g.back.n_items), 1);
     const int64_t Q = kTileQ;
-    return Q * 4 * (2 * g.n_u + std::max<int64_t>(g.n_v + g.n_a, 1) + items + (with_out ? g.n_u : 0)) +
-           (int64_t)sizeof(TileCtl) + (int64_t)g.grid_cap * Q * (2 * 4 + 4 * 8 + 8);
+    const int64_t hot = (int64_t)g.hot.n_chunks * g.hot.n;
+    return Q * 4 * (2 * g.n_u + std::max<int64_t>(g.n_v + g.n_a, 1) + items + hot + (with_out ? g.n_u : 0)) +
+           (int64_t)sizeof(TileCtl) + (int64_t)g.grid_cap * Q * (2 * 4 + 5 * 8 + 8);
 }
 
 void ensure_batch_state(Graph &g, BatchState &b, int tiles, bool with_out) {
@@ -635,7 +845,9 @@ void ensure_batch_state(Graph &g, BatchState &b, int tiles, bool with_out) {
     b.part = (float *)dev_alloc(g, T * items * Q * 4, "batch chunk partials");
     b.ctl = (TileCtl *)dev_alloc(g, T * sizeof(TileCtl), "batch control");
     b.blk_max = (float *)dev_alloc(g, T * 2 * g.grid_cap * Q * 4, "batch workgroup maxima");
-    b.blk_np = (unsigned long long *)dev_alloc(g, T * 4 * g.grid_cap * Q * 8, "batch workgroup counts");
+    b.blk_np = (unsigned long long *)dev_alloc(g, T * 5 * g.grid_cap * Q * 8, "batch workgroup counts");
+    if (g.hot.n > 0)
+        b.hot_part = (float *)dev_alloc(g, T * (size_t)g.hot.n_chunks * g.hot.n * Q * 4, "batch hot-row partials");
     if (with_out) b.out = (float *)dev_alloc(g, T * Q * g.n_u * 4, "batch scores");
     b.sums = (double *)dev_alloc(g, T * g.grid_cap * Q * 8, "batch sums");
     b.tiles = tiles;
@@ -660,21 +872,29 @@ void batch_init(Graph &g, BatchState &b, int nt, const int32_t *sources, const f
 
 void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
     const BPlan p = bplan(g, nt);
+    const BackSched bs = back_sched(g);
+    const HotSet &hs = g.hot;
     const int64_t tile_u = g.n_u * kTileQ, tile_z = std::max<int64_t>(g.n_v + g.n_a, 1) * kTileQ;
     const int64_t tile_part = std::max<int64_t>(std::max(g.fwd.n_items, g.back.n_items), 1) * kTileQ;
-    const int64_t sf = 2 * (int64_t)g.grid_cap * kTileQ, su = 4 * (int64_t)g.grid_cap * kTileQ;
-    BArgs back{g.back.off, g.back.col, g.back.w, g.back.items, g.back.n_items, g.back.split, g.back.n_split,
+    const int64_t sf = 2 * (int64_t)g.grid_cap * kTileQ, su = 5 * (int64_t)g.grid_cap * kTileQ;
+    BArgs back{g.back.off, g.back.col, g.back.w, bs.items, bs.n_items, bs.split, bs.n_split,
                b.r, b.z, nullptr, g.inv_b, b.part, b.ctl, tile_u, tile_z, 0, tile_part, nullptr, b.blk_np, sf, su,
                (float)g.alpha};
-    // Slots of the n_p partials: 0 back, 1 back fix, 2 fwd, 3 fwd fix; of the
-    // max partials: 0 fwd, 1 fwd fix; slots are grid_cap workgroups apart.
+    // Slots of the n_p partials: 0 back, 1 back fix, 2 fwd, 3 fwd fix, 4 hot
+    // rows; of the max partials: 0 fwd, 1 fwd fix; slots are grid_cap
+    // workgroups apart.
     const int64_t slot = (int64_t)g.grid_cap * kTileQ;
     // Algorithmic bytes of a launch: CSR entries and offsets once, 4 bytes
-    // per (entry, running query), and the per-(row, query) epilogue state.
+    // per (entry, running query), and the per-(row, query) state the
+    // epilogue reads and writes.  The hot-row pass reads the hot list and
+    // the U offsets once and each query's residue of every U row once, and
+    // writes and re-reads its chunk partials.
     const double q = (double)b.live_q;
     const double wb = g.fwd.w ? 8.0 : 4.0;
-    const double back_bytes = 8.0 * g.back.nnz + 12.0 * g.back.n_rows + q * (4.0 * g.back.nnz + 4.0 * g.back.n_rows);
+    const double back_bytes = 8.0 * bs.nnz + 12.0 * bs.rows + q * (4.0 * bs.nnz + 4.0 * bs.rows);
     const double fwd_bytes = wb * g.fwd.nnz + 8.0 * g.fwd.n_rows + q * (4.0 * g.fwd.nnz + 16.0 * g.fwd.n_rows);
+    const double hot_bytes = 8.0 * hs.list.nnz + 8.0 * g.n_u + 12.0 * hs.n +
+                             q * (4.0 * g.n_u + 8.0 * hs.n_chunks * hs.n + 4.0 * hs.n);
     if (p.back)
         profiled(g.prof, 2, back_bytes, s, [&] {
             hipLaunchKernelGGL((kb_gather<false, kBBack>), dim3(p.back, nt), dim3(kBlock), 0, s, back);
@@ -683,6 +903,17 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
         BArgs a = back;
         a.blk_np += slot;
         hipLaunchKernelGGL((kb_fix<kBBack>), dim3(p.back_fix, nt), dim3(kBlock), 0, s, a);
+    }
+    if (hs.n > 0) {
+        const int64_t tile_hot = (int64_t)hs.n_chunks * hs.n * kTileQ;
+        HotArgs ha{b.r, tile_u, b.hot_part, tile_hot, b.ctl, g.n_u, hs.chunk_rows, hs.n, hs.n_chunks};
+        HotReduceArgs ra{b.hot_part, tile_hot, hs.rows, hs.len, g.inv_b, b.z, tile_z, b.blk_np + 4 * slot, su, b.ctl,
+                         hs.n, hs.n_chunks};
+        profiled(g.prof, 4, hot_bytes, s, [&] {
+            hipLaunchKernelGGL(kb_hot, dim3((unsigned)hs.n_chunks, nt), dim3(kHotThreads), 0, s, ha,
+                               (const int64_t *)hs.list.off, (const int32_t *)hs.list.col, (const float *)hs.list.w);
+            hipLaunchKernelGGL(kb_hot_reduce, dim3((unsigned)hs.n, nt), dim3(kBlock), 0, s, ra);
+        });
     }
     BArgs fwd{g.fwd.off, g.fwd.col, g.fwd.w, g.fwd.items, g.fwd.n_items, g.fwd.split, g.fwd.n_split,
               b.z, b.r, b.pi, nullptr, b.part, b.ctl, tile_z, tile_u, tile_u, tile_part, b.blk_max,
@@ -698,7 +929,7 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
         hipLaunchKernelGGL((kb_fix<kBFwd>), dim3(p.fwd_fix, nt), dim3(kBlock), 0, s, a);
     }
     hipLaunchKernelGGL(kb_control, dim3(nt), dim3(kTileQ), 0, s, b.ctl, b.blk_max, b.blk_np, sf, su, g.grid_cap,
-                       (int)p.back, (int)p.back_fix, (int)p.fwd, (int)p.fwd_fix, make_rule(g));
+                       (int)p.back, (int)p.back_fix, (int)p.fwd, (int)p.fwd_fix, hs.n, make_rule(g));
     check_hip(hipGetLastError(), "batch round launch");
 }
 

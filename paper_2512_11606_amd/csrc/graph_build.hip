@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "ahpp_internal.h"
@@ -243,6 +244,25 @@ __global__ void k_back_coeffs(const int64_t *off, const int32_t *col, float *w, 
     }
 }
 
+// Entries of the hot rows, keyed by (group of h, U column): entry i of hot
+// row h (start[h] <= i < start[h + 1]) becomes (key (h % kHotWaves) * n_u + u,
+// col h, w back weight).
+__global__ void k_hot_entries(const int64_t *off, const int32_t *col, const float *w, const int32_t *rows,
+                              const int64_t *start, int n_hot, int64_t m, int64_t n_u, uint32_t *key, int32_t *hcol,
+                              float *hw) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = n_hot - 1;  // last h with start[h] <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (start[mid] <= i) lo = mid; else hi = mid - 1;
+        }
+        const int64_t p = off[rows[lo]] + (i - start[lo]);
+        key[i] = (uint32_t)((int64_t)(lo % kHotWaves) * n_u + col[p]);
+        hcol[i] = lo;
+        hw[i] = w[p];
+    }
+}
+
 unsigned grid_for(int64_t n, int per_block = kBlock, unsigned cap = 65536u) {
     int64_t g = (n + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -255,9 +275,10 @@ int bits_for(int64_t n) {
     return b;
 }
 
-// Builds the wave schedule of a CSR from its host copy of the offsets.
+// Builds the wave schedule of a CSR from its host copy of the offsets; rows
+// with skip[r] set get no item (a pack of short rows ends before them).
 void build_items(const std::vector<int64_t> &off, std::vector<WorkItem> &items, std::vector<SplitRow> &split,
-                 int32_t &max_len) {
+                 int32_t &max_len, const std::vector<uint8_t> *skip = nullptr) {
     const int64_t n_rows = (int64_t)off.size() - 1;
     items.clear();
     split.clear();
@@ -266,6 +287,10 @@ void build_items(const std::vector<int64_t> &off, std::vector<WorkItem> &items, 
     while (r < n_rows) {
         int64_t len = off[r + 1] - off[r];
         max_len = (int32_t)std::max<int64_t>(max_len, len);
+        if (skip && (*skip)[r]) {
+            ++r;
+            continue;
+        }
         if (len > kShortRow) {
             int64_t chunks = (len + kItemEdges - 1) / kItemEdges;
             if (chunks > 1) split.push_back(SplitRow{(int32_t)r, (int32_t)items.size(), (int32_t)chunks, 0});
@@ -275,7 +300,7 @@ void build_items(const std::vector<int64_t> &off, std::vector<WorkItem> &items, 
         }
         // Pack consecutive short rows.
         int64_t r1 = r, e = 0;
-        while (r1 < n_rows && r1 - r < kMaxRowsPerItem) {
+        while (r1 < n_rows && r1 - r < kMaxRowsPerItem && !(skip && (*skip)[r1])) {
             int64_t l = off[r1 + 1] - off[r1];
             if (l > kShortRow || e + l > kItemEdges) break;
             e += l;
@@ -351,6 +376,83 @@ void build_csr(Graph &g, DevCsr &c, int64_t n_rows, uint32_t *key, int32_t *col,
         check_hip(hipMemcpyAsync(c.split, split.data(), split.size() * sizeof(SplitRow), hipMemcpyHostToDevice, s),
                   "split H2D");
     check_hip(hipStreamSynchronize(s), "schedule upload");
+}
+
+// Picks the hot rows of the back CSR (the kHotMax longest rows with at least
+// kHotMinLen entries; AHPP_HOT_ROWS=<n> lowers the cap, 0 turns it off),
+// builds their U-major lists (one per group h % kHotWaves, as one CSR over
+// kHotWaves * n_u rows) and the back schedule without them.
+void build_hot(Graph &g, hipStream_t s) {
+    HotSet &h = g.hot;
+    int cap = kHotMax;
+    if (const char *e = std::getenv("AHPP_HOT_ROWS")) cap = std::max(0, std::min(kHotMax, std::atoi(e)));
+    const int64_t n_rows = g.back.n_rows;
+    if (cap == 0 || n_rows == 0 || g.back.nnz == 0) return;
+    std::vector<int64_t> off((size_t)n_rows + 1);
+    check_hip(hipMemcpyAsync(off.data(), g.back.off, off.size() * 8, hipMemcpyDeviceToHost, s), "hot rows");
+    check_hip(hipStreamSynchronize(s), "hot rows");
+    std::vector<int32_t> order;
+    for (int64_t r = 0; r < n_rows; ++r)
+        if (off[r + 1] - off[r] >= kHotMinLen) order.push_back((int32_t)r);
+    if (order.empty()) return;
+    // Longest first, ties by row id; hot index h follows this order.
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
+    if ((int)order.size() > cap) order.resize(cap);
+    const int n = (int)order.size();
+    std::vector<int32_t> len(n);
+    std::vector<int64_t> start(n + 1, 0);
+    std::vector<uint8_t> skip((size_t)n_rows, 0);
+    for (int i = 0; i < n; ++i) {
+        len[i] = (int32_t)(off[order[i] + 1] - off[order[i]]);
+        start[i + 1] = start[i] + len[i];
+        skip[order[i]] = 1;
+    }
+    const int64_t m = start[n];
+    h.n = n;
+    h.rows = (int32_t *)dev_alloc(g, (size_t)n * 4, "hot rows");
+    h.len = (int32_t *)dev_alloc(g, (size_t)n * 4, "hot rows");
+    check_hip(hipMemcpyAsync(h.rows, order.data(), (size_t)n * 4, hipMemcpyHostToDevice, s), "hot rows");
+    check_hip(hipMemcpyAsync(h.len, len.data(), (size_t)n * 4, hipMemcpyHostToDevice, s), "hot rows");
+    int64_t *d_start = nullptr;
+    uint32_t *key = nullptr;
+    int32_t *col = nullptr;
+    float *w = nullptr;
+    check_hip(hipMalloc(&d_start, (size_t)(n + 1) * 8), "hot entries");
+    check_hip(hipMalloc(&key, (size_t)m * 4), "hot entries");
+    check_hip(hipMalloc(&col, (size_t)m * 4), "hot entries");
+    check_hip(hipMalloc(&w, (size_t)m * 4), "hot entries");
+    check_hip(hipMemcpyAsync(d_start, start.data(), (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s), "hot entries");
+    hipLaunchKernelGGL(k_hot_entries, dim3(grid_for(m)), dim3(kBlock), 0, s, g.back.off, g.back.col, g.back.w, h.rows,
+                       d_start, n, m, g.n_u, key, col, w);
+    check_hip(hipGetLastError(), "hot entries launch");
+    build_csr(g, h.list, kHotWaves * g.n_u, key, col, w, m, true, s);
+    dfree(d_start);
+    dfree(key);
+    dfree(col);
+    dfree(w);
+    // Back schedule without the hot rows.
+    std::vector<WorkItem> items;
+    std::vector<SplitRow> split;
+    int32_t max_len = 0;
+    build_items(off, items, split, max_len, &skip);
+    h.n_cold_items = (int64_t)items.size();
+    h.n_cold_split = (int64_t)split.size();
+    h.cold_items = (WorkItem *)dev_alloc(g, std::max<size_t>(items.size(), 1) * sizeof(WorkItem), "cold schedule");
+    h.cold_split = (SplitRow *)dev_alloc(g, std::max<size_t>(split.size(), 1) * sizeof(SplitRow), "cold schedule");
+    if (!items.empty())
+        check_hip(hipMemcpyAsync(h.cold_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, s),
+                  "cold schedule");
+    if (!split.empty())
+        check_hip(hipMemcpyAsync(h.cold_split, split.data(), split.size() * sizeof(SplitRow), hipMemcpyHostToDevice,
+                                 s), "cold schedule");
+    h.cold_nnz = g.back.nnz - m;
+    h.cold_rows = n_rows - n;
+    // Fixed chunking (a property of the graph and the device, not of the
+    // launch), so the sum order never depends on how many tiles run.
+    h.n_chunks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(g.n_cu, g.n_u));
+    h.chunk_rows = (g.n_u + h.n_chunks - 1) / h.n_chunks;
+    check_hip(hipStreamSynchronize(s), "hot rows");
 }
 
 }  // namespace
@@ -452,6 +554,7 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
     dfree(cd);
     dfree(cs);
     g.dangling_u = (int64_t)dang;
+    build_hot(g, s);
     g.load_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
@@ -463,6 +566,9 @@ static void free_csr(DevCsr &c) {
 void free_graph(Graph &g) {
     free_csr(g.fwd);
     free_csr(g.back);
+    free_csr(g.hot.list);
+    for (void *p : {(void *)g.hot.rows, (void *)g.hot.len, (void *)g.hot.cold_items, (void *)g.hot.cold_split}) dfree(p);
+    g.hot = HotSet{};
     free_batch_state(g.batch);
     for (void *p : {(void *)g.inv_b, (void *)g.q_r, (void *)g.q_pi, (void *)g.q_z, (void *)g.q_ctl,
                     (void *)g.part_item, (void *)g.blk_max, (void *)g.blk_np, g.tk_scratch})
