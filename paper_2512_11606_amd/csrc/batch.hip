@@ -364,54 +364,75 @@ __global__ void __launch_bounds__(kBlock) kb_fix(BArgs a) {
 
 // One workgroup per tile, one thread per query: max r and n_p from the
 // partials, then the stop / switch rule of Algorithm 4 for every running query.
-__global__ void __launch_bounds__(kTileQ) kb_control(TileCtl *ctl, const float *blk_max, const unsigned long long *blk_np,
-                                                     int64_t stride_f, int64_t stride_u, int grid_cap, int n_back,
-                                                     int n_back_fix, int n_fwd, int n_fwd_fix, int n_hot, Rule rule) {
+constexpr int kCtlSplit = 4;  // threads per query reducing the partials
+constexpr int kCtlThreads = kCtlSplit * kTileQ;
+
+__global__ void __launch_bounds__(kCtlThreads) kb_control(TileCtl *ctl, const float *blk_max,
+                                                          const unsigned long long *blk_np, int64_t stride_f,
+                                                          int64_t stride_u, int grid_cap, int n_back, int n_back_fix,
+                                                          int n_fwd, int n_fwd_fix, int n_hot, Rule rule) {
     __shared__ int running_any[kTileQ / kWave];
+    __shared__ float s_max[kCtlSplit][kTileQ];
+    __shared__ unsigned long long s_np[kCtlSplit][kTileQ];
     const int t = blockIdx.x;
     TileCtl &tc = ctl[t];
     if (tc.all_done) return;
-    const int q = threadIdx.x;
+    // Thread (part, q) reduces every kCtlSplit-th workgroup partial of query
+    // q; max and integer sums do not depend on the order.
+    const int q = threadIdx.x % kTileQ, part = threadIdx.x / kTileQ;
     const float *bm = blk_max + t * stride_f;
     const unsigned long long *bn = blk_np + t * stride_u;
     float m = 0.0f;
-    for (int i = 0; i < n_fwd; ++i) m = fmaxf(m, bm[(int64_t)i * kTileQ + q]);
-    for (int i = 0; i < n_fwd_fix; ++i) m = fmaxf(m, bm[((int64_t)grid_cap + i) * kTileQ + q]);
+    for (int i = part; i < n_fwd; i += kCtlSplit) m = fmaxf(m, bm[(int64_t)i * kTileQ + q]);
+    for (int i = part; i < n_fwd_fix; i += kCtlSplit) m = fmaxf(m, bm[((int64_t)grid_cap + i) * kTileQ + q]);
     unsigned long long np = 0;
     const int cnt[5] = {n_back, n_back_fix, n_fwd, n_fwd_fix, n_hot};
+#pragma unroll
     for (int k = 0; k < 5; ++k)
-        for (int i = 0; i < cnt[k]; ++i) np += bn[((int64_t)k * grid_cap + i) * kTileQ + q];
-    QueryCtl &c = tc.q[q];
-    int done = c.done;
-    if (!done) {
-        const unsigned long long n_p = c.n_p + np;
-        const int iter = c.iter + 1;
-        c.n_p = n_p;
-        c.iter = iter;
-        c.last_max = m;
-        if (!(m > c.eps_f)) {
-            done = 1;
-            c.status = 1;
-        } else if (iter >= c.max_iters) {
-            done = 1;
-            c.status = 2;
-        } else if (c.phase == 1) {
-            const double tt = (double)logf(m / c.eps_f) * (double)rule.inv_log;
-            if ((double)n_p >= rule.budget_scale * (tt > 0.0 ? tt : 0.0)) {
-                c.phase = 2;
-                c.theta = 0.0f;
-                c.switch_iter = iter;
+        for (int i = part; i < cnt[k]; i += kCtlSplit) np += bn[((int64_t)k * grid_cap + i) * kTileQ + q];
+    s_max[part][q] = m;
+    s_np[part][q] = np;
+    __syncthreads();
+    // Part 0 (the first kTileQ / kWave waves) applies the rule; every
+    // thread still reaches both barriers.
+    if (part == 0) {
+#pragma unroll
+        for (int i = 1; i < kCtlSplit; ++i) {
+            m = fmaxf(m, s_max[i][q]);
+            np += s_np[i][q];
+        }
+        QueryCtl &c = tc.q[q];
+        int done = c.done;
+        if (!done) {
+            const unsigned long long n_p = c.n_p + np;
+            const int iter = c.iter + 1;
+            c.n_p = n_p;
+            c.iter = iter;
+            c.last_max = m;
+            if (!(m > c.eps_f)) {
+                done = 1;
+                c.status = 1;
+            } else if (iter >= c.max_iters) {
+                done = 1;
+                c.status = 2;
+            } else if (c.phase == 1) {
+                const double tt = (double)logf(m / c.eps_f) * (double)rule.inv_log;
+                if ((double)n_p >= rule.budget_scale * (tt > 0.0 ? tt : 0.0)) {
+                    c.phase = 2;
+                    c.theta = 0.0f;
+                    c.switch_iter = iter;
+                }
+            }
+            if (done) {
+                c.done = 1;
+                c.theta = FLT_MAX;
             }
         }
-        if (done) {
-            c.done = 1;
-            c.theta = FLT_MAX;
-        }
+        const unsigned long long running = __ballot(!done);
+        if ((q & 63) == 0) running_any[q >> 6] = running != 0ull;
     }
-    const unsigned long long running = __ballot(!done);
-    if ((q & 63) == 0) running_any[q >> 6] = running != 0ull;
     __syncthreads();
-    if (q == 0) {
+    if (threadIdx.x == 0) {
         int any = 0;
         for (int i = 0; i < kTileQ / kWave; ++i) any |= running_any[i];
         tc.all_done = any ? 0 : 1;
@@ -928,7 +949,7 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
         a.blk_np += slot;
         hipLaunchKernelGGL((kb_fix<kBFwd>), dim3(p.fwd_fix, nt), dim3(kBlock), 0, s, a);
     }
-    hipLaunchKernelGGL(kb_control, dim3(nt), dim3(kTileQ), 0, s, b.ctl, b.blk_max, b.blk_np, sf, su, g.grid_cap,
+    hipLaunchKernelGGL(kb_control, dim3(nt), dim3(kCtlThreads), 0, s, b.ctl, b.blk_max, b.blk_np, sf, su, g.grid_cap,
                        (int)p.back, (int)p.back_fix, (int)p.fwd, (int)p.fwd_fix, hs.n, make_rule(g));
     check_hip(hipGetLastError(), "batch round launch");
 }

@@ -514,8 +514,7 @@ ahpp_status_t ahpp_query_batch(ahpp_graph_t *h, int32_t n_q, const int32_t *sour
                 chunk = next;
             }
             if (g.prof.on) {
-                profiler_void_tail(g.prof, 2, launched - executed);
-                profiler_void_tail(g.prof, 3, launched - executed);
+                for (int kind = 2; kind <= 4; ++kind) profiler_void_tail(g.prof, kind, launched - executed);
             }
             float *scores = pi_out ? pi_out + q0 * g.n_u : g.batch.out;
             batch_scores(g, g.batch, nt, nq, scores, s);
