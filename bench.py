@@ -92,6 +92,24 @@ def cpu_baseline(g, sources, eps):
 SERVE_EPS = (1e-5, 1e-6, 1e-7, 1e-8)
 
 
+def tiny_leg(ahpp, synth, n=200):
+    """Plain single-query latency on the 2k/1k/20k graph (the small parity
+    workload), where launch overhead rather than HBM decides the time."""
+    g = synth.make_graph("tiny")
+    dg = ahpp.load_graph(g, device=0)
+    srcs = synth.uniform_queries(g, n, 2000)
+    ahpp.ahpp_query(dg, int(srcs[0]), 1e-6, k=20)
+    lat = []
+    for s in srcs.tolist():
+        a = time.perf_counter()
+        ahpp.ahpp_query(dg, s, 1e-6, k=20, want_pi=False, want_stats=False)
+        lat.append((time.perf_counter() - a) * 1e3)
+    dg.free()
+    return {"workload": "plain single-query push, 2k/1k/20k unit-weight graph with 100 attributes x 5, eps 1e-6, k 20",
+            "queries": n, "latency_ms_p50": round(_percentile(lat, 50), 3),
+            "latency_ms_p99": round(_percentile(lat, 99), 3), "queries_per_s": round(n / (sum(lat) / 1e3), 1)}
+
+
 def serve_leg(ahpp, synth, g, dg, args):
     """Continuous batching under Poisson arrivals on the loaded graph."""
     from paper_2512_11606_amd import serve
@@ -120,6 +138,8 @@ def main():
     ap.add_argument("--plain", type=int, default=32, help="plain single queries timed for latency")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-tiny", action="store_true", help="skip the small-graph latency run")
+    ap.add_argument("--no-tune", action="store_true", help="keep the untuned batch schedule")
     ap.add_argument("--serve-queries", type=int, default=800)
     ap.add_argument("--serve-rate", type=float, default=150.0, help="offered load, queries/s")
     ap.add_argument("--serve-slots", type=int, default=256)
@@ -154,6 +174,7 @@ def main():
     dg = ahpp.load_graph(g, device=0)
     torch.cuda.synchronize()
     sources = synth.mixed_batch_queries(g, args.batch, 2002)
+    tuned = None if args.no_tune else ahpp.ahpp_graph_tune(dg, max_tiles=max(1, args.batch // 256))
 
     for _ in range(args.warmup):
         ahpp.ahpp_query_batch(dg, sources, eps, k=k, want_pi=False, want_stats=False)
@@ -184,6 +205,7 @@ def main():
     plain_qps = len(lat) / (sum(lat) / 1e3)
 
     serving = None if args.no_serve else serve_leg(ahpp, synth, g, dg, args)
+    plain_tiny = None if args.no_tiny else tiny_leg(ahpp, synth)
 
     dom_kind = max(prof, key=lambda kk: prof[kk]["ms"])
     dom = prof[dom_kind]
@@ -220,7 +242,9 @@ def main():
         "plain_latency_ms_p99": round(_percentile(lat, 99), 2),
         "batched_over_plain": round(value / plain_qps, 2),
         "topk_complete": topk_ok,
+        "tuned_schedule": tuned,
         "serving": serving,
+        "plain_tiny": plain_tiny,
         "roofline": roofline,
         "kernels": {kname: {"launches": prof[kk]["launches"],
                             "avg_ms": round(prof[kk]["ms"] / max(prof[kk]["launches"], 1), 4),

@@ -208,6 +208,29 @@ ahpp_status_t ahpp_server_results(ahpp_server_t *s, int32_t max_n, int64_t *tags
 ahpp_status_t ahpp_server_info(const ahpp_server_t *s, int32_t *slots, int32_t *running, int32_t *queued,
                                int32_t *ready);
 
+/* Schedule autotuner of the batched engine (ahpp_query_batch and servers
+ * created afterwards).  Times a few rounds for each candidate schedule --
+ * tiles of 256 queries in flight (1, 2, 4, ... up to max_tiles; <= 0: as
+ * many as fit in a quarter of the free device memory, at most 16) and 1, 2
+ * or 4 times the default workgroups per tile of the gathers -- and keeps
+ * the one with the least time per tile-round.  A round reads every CSR
+ * entry whatever the frontier, so a few rounds measure the steady state.
+ * Results do not depend on the schedule (every sum has a fixed order), only
+ * the speed does.  AHPP_BATCH_TILES still overrides the tiles in flight.
+ * Blocks until done; overwrites the graph's batch state.  *out (nullable):
+ * the choice, the candidates timed, and the time per tile-round of the
+ * choice and of the untuned schedule with the most tiles.
+ * Errors: INVALID_ARG (NULL graph), OUT_OF_MEMORY, DEVICE. */
+typedef struct {
+    int32_t tiles_in_flight;
+    int32_t workgroup_multiplier;
+    int32_t candidates;
+    int32_t reserved;
+    double ms_per_tile_round;
+    double default_ms_per_tile_round;
+} ahpp_tune_info_t;
+ahpp_status_t ahpp_graph_tune(ahpp_graph_t *g, int32_t max_tiles, ahpp_tune_info_t *out, void *hip_stream);
+
 /* Kernel timing (diagnostics, used by the benchmark's roofline figures).
  * While enabled, the library brackets every launch of its gather kernels with
  * HIP events on the launch stream and adds, per kernel kind, the launch

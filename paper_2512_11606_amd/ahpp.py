@@ -22,7 +22,8 @@ OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CONVERGED = 0, -1, -
 
 EXPORTED = ("ahpp_graph_load", "ahpp_graph_info", "ahpp_graph_free", "ahpp_query", "ahpp_query_batch", "ahpp_topk",
             "ahpp_server_create", "ahpp_server_free", "ahpp_server_submit", "ahpp_server_step",
-            "ahpp_server_results", "ahpp_server_info", "ahpp_profile_enable", "ahpp_profile_read", "ahpp_last_error")
+            "ahpp_server_results", "ahpp_server_info", "ahpp_graph_tune", "ahpp_profile_enable", "ahpp_profile_read",
+            "ahpp_last_error")
 
 # Kernel kinds of ahpp_profile_read.
 PROF_SINGLE_BACK, PROF_SINGLE_FWD, PROF_BATCH_BACK, PROF_BATCH_FWD, PROF_BATCH_HOT = 0, 1, 2, 3, 4
@@ -97,6 +98,8 @@ def load_library(path: str = LIB_PATH):
     lib.ahpp_server_results.argtypes = [P, i32, P, P, P, P, P, P, P, P]
     lib.ahpp_server_info.restype = ctypes.c_int
     lib.ahpp_server_info.argtypes = [P, P, P, P, P]
+    lib.ahpp_graph_tune.restype = ctypes.c_int
+    lib.ahpp_graph_tune.argtypes = [P, i32, P, P]
     lib.ahpp_profile_enable.restype = ctypes.c_int
     lib.ahpp_profile_enable.argtypes = [P, i32]
     lib.ahpp_profile_read.restype = ctypes.c_int
@@ -257,6 +260,19 @@ def ahpp_topk(g: Graph, pi, k: int, exclude: int = -1, stream=None):
 def ahpp_profile_enable(g: Graph, on: bool = True) -> None:
     """Starts (clearing totals) or stops HIP-event timing of the gather kernels."""
     _check(load_library().ahpp_profile_enable(g._h, 1 if on else 0))
+
+
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("tiles_in_flight", ctypes.c_int32), ("workgroup_multiplier", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ms_per_tile_round", ctypes.c_double),
+                ("default_ms_per_tile_round", ctypes.c_double)]
+
+
+def ahpp_graph_tune(g: Graph, max_tiles: int = 0, stream=None) -> dict:
+    """Times candidate batch schedules and keeps the fastest (see ahpp.h)."""
+    info = TuneInfo()
+    _check(load_library().ahpp_graph_tune(g._h, int(max_tiles), ctypes.byref(info), _stream(g.device, stream)))
+    return {f: getattr(info, f) for f, _ in info._fields_ if f != "reserved"}
 
 
 def ahpp_profile_read(g: Graph, kind: int) -> dict:

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <deque>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -114,6 +115,10 @@ struct BatchState {
     float *out = nullptr;           // [tiles * kTileQ][n_u] query-major scores for top-k
     double *sums = nullptr;         // [tiles][grid_x][kTileQ] residue sums
     int64_t live_q = 0;             // queries still running at the last poll
+    // One captured round per number of tiles in flight (replayed on the
+    // caller's stream); they name this state's buffers, so they go with it.
+    std::vector<std::pair<int, hipGraphExec_t>> round_graphs;
+    int graphs_gen = 0;             // Graph::plan_gen the captured rounds were made with
 };
 
 // Hot rows: the longest rows of the back CSR (the most popular attributes
@@ -204,6 +209,15 @@ struct Graph {
     // Top-k scratch.
     void *tk_scratch = nullptr;
     size_t tk_scratch_bytes = 0;
+    // Captured rounds: a library stream to capture on, and the single-query
+    // round (its buffers are fixed at load).
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t single_round_graph = nullptr;
+    // Batched schedule picked by batch_tune (0: not tuned): tiles in flight
+    // and the multiple of the default workgroups per tile of the gathers.
+    int tuned_tiles = 0;
+    int tuned_wg_mult = 1;
+    int plan_gen = 0;               // bumped when the schedule changes (captured rounds go stale)
 };
 
 // Error carrying a status code across internal C++ code (never crosses the ABI).
@@ -228,6 +242,9 @@ void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 void alloc_query_state(Graph &g);
 void single_query_init(Graph &g, int32_t source, float eps_f, int32_t max_iters, hipStream_t s);
 void single_query_round(Graph &g, hipStream_t s);
+void single_query_rounds(Graph &g, int n, hipStream_t s);   // as batch_rounds
+bool graphs_enabled(const Graph &g);
+hipGraphExec_t capture_graph(Graph &g, const char *what, const std::function<void(hipStream_t)> &record);
 void single_query_stats(Graph &g, double *sum_r, hipStream_t s);
 double compute_lambda(Graph &g, int T, hipStream_t s);
 
@@ -245,6 +262,16 @@ void free_batch_state(BatchState &b);
 void batch_init(Graph &g, BatchState &b, int nt, const int32_t *sources, const float *eps_f, int64_t n_q,
                 int32_t max_iters, hipStream_t s);
 void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s);
+// `n` rounds of tiles [0, nt): plain launches, or with AHPP_GRAPHS=1 one
+// captured round replayed n times (HIP graphs; never while profiling).
+void batch_rounds(Graph &g, BatchState &b, int nt, int n, hipStream_t s);
+// Times rounds for each candidate schedule (tiles in flight up to max_tiles,
+// workgroups per tile x1, x2, x4) and keeps the fastest per tile-round in g.
+struct TuneResult {
+    int tiles, wg_mult, candidates;
+    double ms_per_tile_round, default_ms_per_tile_round;
+};
+TuneResult batch_tune(Graph &g, int max_tiles, hipStream_t s);
 // Copies tile scores to query-major rows: out[(t*kTileQ + q) * n_u + u] for
 // the first n_rows rows.
 void batch_scores(Graph &g, BatchState &b, int nt, int64_t n_rows, float *out, hipStream_t s);

@@ -828,7 +828,7 @@ BackSched back_sched(const Graph &g) {
 }
 
 BPlan bplan(const Graph &g, int nt) {
-    const int cap = std::min(g.grid_cap, std::max(64, g.grid_cap / std::max(nt, 1)));
+    const int cap = std::min(g.grid_cap, std::max(64, g.tuned_wg_mult * g.grid_cap / std::max(nt, 1)));
     const BackSched bs = back_sched(g);
     BPlan p;
     p.back = bs.n_items ? capped(bs.n_items, kWavesPerBlock, cap) : 0;
@@ -841,6 +841,7 @@ BPlan bplan(const Graph &g, int nt) {
 }  // namespace
 
 void free_batch_state(BatchState &b) {
+    for (auto &e : b.round_graphs) (void)hipGraphExecDestroy(e.second);
     for (void *p : {(void *)b.r, (void *)b.pi, (void *)b.z, (void *)b.part, (void *)b.ctl, (void *)b.blk_max,
                     (void *)b.blk_np, (void *)b.hot_part, (void *)b.out, (void *)b.sums})
         dfree(p);
@@ -952,6 +953,81 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
     hipLaunchKernelGGL(kb_control, dim3(nt), dim3(kCtlThreads), 0, s, b.ctl, b.blk_max, b.blk_np, sf, su, g.grid_cap,
                        (int)p.back, (int)p.back_fix, (int)p.fwd, (int)p.fwd_fix, hs.n, make_rule(g));
     check_hip(hipGetLastError(), "batch round launch");
+}
+
+TuneResult batch_tune(Graph &g, int max_tiles, hipStream_t s) {
+    // Sources: the first tiles * kTileQ nodes of U, at a tiny eps so no
+    // query stops during the probe.  A pull-form round reads every CSR entry
+    // whatever the frontier, so its cost is the same from the first round.
+    const int kProbe = 3;
+    TuneResult best{0, 1, 0, 0.0, 0.0};
+    g.tuned_tiles = 0;
+    g.tuned_wg_mult = 1;
+    ++g.plan_gen;
+    const bool prof = g.prof.on;
+    g.prof.on = false;
+    std::vector<int> tiles;
+    for (int t = 1; t <= std::max(1, max_tiles); t *= 2) tiles.push_back(t);
+    hipEvent_t e0, e1;
+    check_hip(hipEventCreate(&e0), "tune");
+    check_hip(hipEventCreate(&e1), "tune");
+    double best_ms = 1e300;
+    for (int nt : tiles) {
+        ensure_batch_state(g, g.batch, nt, false);
+        const int64_t n_q = std::min<int64_t>((int64_t)nt * kTileQ, g.n_u);
+        std::vector<int32_t> src((size_t)n_q);
+        std::vector<float> eps_f((size_t)n_q, 1e-30f);
+        for (int64_t i = 0; i < n_q; ++i) src[i] = (int32_t)i;
+        for (int mult : {1, 2, 4}) {
+            if (mult > 1 && std::max(64, (mult / 2) * g.grid_cap / nt) >= g.grid_cap) break;  // same plan as before
+            g.tuned_wg_mult = mult;
+            batch_init(g, g.batch, nt, src.data(), eps_f.data(), n_q, 1 << 20, s);
+            g.batch.live_q = n_q;
+            batch_round(g, g.batch, nt, s);
+            check_hip(hipEventRecord(e0, s), "tune");
+            for (int i = 0; i < kProbe; ++i) batch_round(g, g.batch, nt, s);
+            check_hip(hipEventRecord(e1, s), "tune");
+            check_hip(hipEventSynchronize(e1), "tune");
+            float ms = 0.0f;
+            check_hip(hipEventElapsedTime(&ms, e0, e1), "tune");
+            const double per = (double)ms / (kProbe * nt);
+            ++best.candidates;
+            if (nt == tiles.back() && mult == 1) best.default_ms_per_tile_round = per;
+            if (per < best_ms) {
+                best_ms = per;
+                best.tiles = nt;
+                best.wg_mult = mult;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    best.ms_per_tile_round = best_ms;
+    g.tuned_tiles = best.tiles;
+    g.tuned_wg_mult = best.wg_mult;
+    ++g.plan_gen;
+    g.prof.on = prof;
+    return best;
+}
+
+void batch_rounds(Graph &g, BatchState &b, int nt, int n, hipStream_t s) {
+    if (!graphs_enabled(g)) {
+        for (int i = 0; i < n; ++i) batch_round(g, b, nt, s);
+        return;
+    }
+    if (b.graphs_gen != g.plan_gen) {
+        for (auto &e : b.round_graphs) (void)hipGraphExecDestroy(e.second);
+        b.round_graphs.clear();
+        b.graphs_gen = g.plan_gen;
+    }
+    hipGraphExec_t ex = nullptr;
+    for (auto &e : b.round_graphs)
+        if (e.first == nt) ex = e.second;
+    if (!ex) {
+        ex = capture_graph(g, "batch round capture", [&](hipStream_t cs) { batch_round(g, b, nt, cs); });
+        b.round_graphs.emplace_back(nt, ex);
+    }
+    for (int i = 0; i < n; ++i) check_hip(hipGraphLaunch(ex, s), "round graph launch");
 }
 
 void batch_scores(Graph &g, BatchState &b, int nt, int64_t n_rows, float *out, hipStream_t s) {

@@ -59,18 +59,24 @@ void ensure_topk_scratch(Graph &g, int64_t n_q) {
     g.tk_scratch_bytes = need;
 }
 
-// Tiles of kTileQ queries run side by side in one batch pass: AHPP_BATCH_TILES
-// if set, else as many as fit in a quarter of the free device memory, at most 16.
-int batch_tiles_in_flight(const Graph &g) {
-    if (const char *e = std::getenv("AHPP_BATCH_TILES")) {
-        int v = std::atoi(e);
-        if (v > 0) return v;
-    }
+// Tiles of kTileQ queries that fit in a quarter of the free device memory, at most 16.
+int batch_tiles_fit(const Graph &g) {
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return 4;
     const double per_tile = (double)batch_tile_bytes(g, true);
     int t = (int)std::floor((double)free_b * 0.25 / std::max(per_tile, 1.0));
     return std::max(1, std::min(t, 16));
+}
+
+// Tiles run side by side in one batch pass: AHPP_BATCH_TILES if set, else
+// the tuned count (ahpp_graph_tune), else as many as fit.
+int batch_tiles_in_flight(const Graph &g) {
+    if (const char *e = std::getenv("AHPP_BATCH_TILES")) {
+        int v = std::atoi(e);
+        if (v > 0) return v;
+    }
+    if (g.tuned_tiles > 0) return g.tuned_tiles;
+    return batch_tiles_fit(g);
 }
 
 int default_lambda_iters(int64_t n_u, double alpha) {
@@ -94,7 +100,7 @@ void run_single(Graph &g, hipStream_t s) {
     int chunk = 4, launched = 0;
     Control c;
     for (;;) {
-        for (int i = 0; i < chunk; ++i) single_query_round(g, s);
+        single_query_rounds(g, chunk, s);
         launched += chunk;
         check_hip(hipMemcpyAsync(&c, g.q_ctl, sizeof(Control), hipMemcpyDeviceToHost, s), "poll");
         check_hip(hipStreamSynchronize(s), "poll");
@@ -139,6 +145,40 @@ void profiler_void_tail(Profiler &p, int kind, int64_t n) {
         p.pending.erase(p.pending.begin() + i);
         --n;
     }
+}
+
+// With AHPP_GRAPHS=1 the rounds are replayed from captured HIP graphs.  Off
+// by default: on MI355X replaying a one-round graph costs more than its
+// five launches (2.14 ms against 1.90 ms per query on a 2k-node graph; the
+// same on the 1M graph, where rounds are long).  Profiling needs the plain
+// launches (it records events around them).
+bool graphs_enabled(const Graph &g) {
+    if (g.prof.on) return false;
+    const char *e = std::getenv("AHPP_GRAPHS");
+    return e && std::atoi(e) == 1;
+}
+
+// Records the launches issued by record() on the library's capture stream
+// and returns the instantiated graph.  The recorded work must not allocate
+// or memset (kernels only).
+hipGraphExec_t capture_graph(Graph &g, const char *what, const std::function<void(hipStream_t)> &record) {
+    if (!g.cap_stream) check_hip(hipStreamCreateWithFlags(&g.cap_stream, hipStreamNonBlocking), what);
+    check_hip(hipStreamBeginCapture(g.cap_stream, hipStreamCaptureModeThreadLocal), what);
+    try {
+        record(g.cap_stream);
+    } catch (...) {
+        hipGraph_t partial = nullptr;
+        (void)hipStreamEndCapture(g.cap_stream, &partial);
+        if (partial) (void)hipGraphDestroy(partial);
+        throw;
+    }
+    hipGraph_t graph = nullptr;
+    check_hip(hipStreamEndCapture(g.cap_stream, &graph), what);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    check_hip(e, what);
+    return exec;
 }
 
 void *dev_alloc(Graph &g, size_t bytes, const char *what) {
@@ -244,6 +284,25 @@ ahpp_status_t ahpp_server_info(const ahpp_server_t *srv, int32_t *slots, int32_t
     g_last_error.clear();
     if (!srv || !srv->impl) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_info: NULL server");
     srv->impl->info(slots, running, queued, ready);
+    return AHPP_OK;
+}
+
+ahpp_status_t ahpp_graph_tune(ahpp_graph_t *h, int32_t max_tiles, ahpp_tune_info_t *out, void *hip_stream) {
+    g_last_error.clear();
+    if (!h) return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_tune: NULL graph");
+    Graph &g = h->g;
+    try {
+        DeviceScope scope(g.device);
+        int cap = batch_tiles_fit(g);
+        if (max_tiles > 0) cap = std::min(cap, (int)max_tiles);
+        const TuneResult r = batch_tune(g, cap, (hipStream_t)hip_stream);
+        if (out) *out = ahpp_tune_info_t{r.tiles, r.wg_mult, r.candidates, 0, r.ms_per_tile_round,
+                                         r.default_ms_per_tile_round};
+    } catch (const Failure &f) {
+        return fail(f.status, f.msg);
+    } catch (const std::exception &e) {
+        return fail(AHPP_ERR_OUT_OF_MEMORY, std::string("ahpp_graph_tune: ") + e.what());
+    }
     return AHPP_OK;
 }
 
@@ -489,7 +548,7 @@ ahpp_status_t ahpp_query_batch(ahpp_graph_t *h, int32_t n_q, const int32_t *sour
             g.batch.live_q = nq;
             int chunk = 4, launched = 0, executed = 0;
             for (;;) {
-                for (int i = 0; i < chunk; ++i) batch_round(g, g.batch, nt, s);
+                batch_rounds(g, g.batch, nt, chunk, s);
                 launched += chunk;
                 check_hip(hipMemcpyAsync(ctl.data(), g.batch.ctl, (size_t)nt * sizeof(TileCtl), hipMemcpyDeviceToHost,
                                          s), "poll");

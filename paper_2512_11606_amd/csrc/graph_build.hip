@@ -564,6 +564,10 @@ static void free_csr(DevCsr &c) {
 }
 
 void free_graph(Graph &g) {
+    if (g.single_round_graph) (void)hipGraphExecDestroy(g.single_round_graph);
+    g.single_round_graph = nullptr;
+    if (g.cap_stream) (void)hipStreamDestroy(g.cap_stream);
+    g.cap_stream = nullptr;
     free_csr(g.fwd);
     free_csr(g.back);
     free_csr(g.hot.list);

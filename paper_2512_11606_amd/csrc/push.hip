@@ -458,6 +458,16 @@ void single_query_round(Graph &g, hipStream_t s) {
     check_hip(hipGetLastError(), "round launch");
 }
 
+void single_query_rounds(Graph &g, int n, hipStream_t s) {
+    if (!graphs_enabled(g)) {
+        for (int i = 0; i < n; ++i) single_query_round(g, s);
+        return;
+    }
+    if (!g.single_round_graph)
+        g.single_round_graph = capture_graph(g, "single round capture", [&](hipStream_t cs) { single_query_round(g, cs); });
+    for (int i = 0; i < n; ++i) check_hip(hipGraphLaunch(g.single_round_graph, s), "round graph launch");
+}
+
 void single_query_stats(Graph &g, double *sum_r, hipStream_t s) {
     const unsigned grid = capped(g.n_u, kBlock, 1024);
     double *d = nullptr;

@@ -105,7 +105,7 @@ int Server::step(int rounds, hipStream_t s) {
     // 2. Rounds for every running query.
     if (running > 0) {
         b_.live_q = running;
-        for (int i = 0; i < rounds; ++i) batch_round(g_, b_, active, s);
+        batch_rounds(g_, b_, active, rounds, s);
     }
     // 3. Collection of stopped queries.
     std::vector<TileCtl> ctl((size_t)b_.tiles);

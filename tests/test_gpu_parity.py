@@ -244,3 +244,48 @@ def test_batch_weighted_ragged_tiles(torch_cuda, ahpp, monkeypatch):
     assert np.array_equal(res1.topk_idx.cpu().numpy(), res.topk_idx.cpu().numpy())
     assert [s["iters"] for s in res1.stats] == [s["iters"] for s in res.stats]
     dg.free()
+
+
+def test_captured_rounds_match_plain_launches(torch_cuda, ahpp, tiny, tiny_graph, monkeypatch):
+    """Rounds replayed from HIP graphs give bitwise the results of plain
+    launches: single queries and a two-tile batch, replayed three times with
+    unrelated eager GPU work and synchronisations between the replays."""
+    import torch
+    srcs = synth.mixed_batch_queries(tiny_graph, 300, 77)
+    eps = np.array([(1e-4, 1e-6, 1e-7)[i % 3] for i in range(srcs.size)])
+    monkeypatch.setenv("AHPP_GRAPHS", "0")
+    ref_single = [ahpp.ahpp_query(tiny, int(s), 1e-6, k=20) for s in srcs[:3]]
+    ref_batch = ahpp.ahpp_query_batch(tiny, srcs, eps, k=20)
+    monkeypatch.setenv("AHPP_GRAPHS", "1")
+    for rep in range(3):
+        _say("graph replay", rep)
+        for i, s in enumerate(srcs[:3]):
+            r = ahpp.ahpp_query(tiny, int(s), 1e-6, k=20)
+            assert torch.equal(r.pi, ref_single[i].pi), (rep, i)
+            assert r.stats[0]["iters"] == ref_single[i].stats[0]["iters"]
+        res = ahpp.ahpp_query_batch(tiny, srcs, eps, k=20)
+        assert torch.equal(res.pi, ref_batch.pi), rep
+        assert torch.equal(res.topk_idx, ref_batch.topk_idx), rep
+        x = torch.randn(4096, device="cuda").cumsum(0)
+        torch.cuda.synchronize()
+        assert torch.isfinite(x).all()
+
+
+def test_tuned_schedule_changes_speed_only(torch_cuda, ahpp):
+    """The autotuner picks a schedule among its candidates; batch results are
+    bitwise the same before and after (every sum has a fixed order)."""
+    import torch
+    g = synth.make_custom(6000, 3000, 60000, 300, 6, seed=818, unit_weights=False)
+    dg = ahpp.load_graph(g)
+    srcs = np.concatenate([synth.mixed_batch_queries(g, 500, 51), synth.degree_queries(g, 100, 52)])
+    eps = np.where(np.arange(srcs.size) % 2 == 0, 1e-6, 1e-7)
+    before = ahpp.ahpp_query_batch(dg, srcs, eps, k=25)
+    info = ahpp.ahpp_graph_tune(dg, max_tiles=4)
+    _say("tuned", info)
+    assert info["tiles_in_flight"] in (1, 2, 4) and info["workgroup_multiplier"] in (1, 2, 4)
+    assert info["candidates"] >= 3 and 0 < info["ms_per_tile_round"] <= info["default_ms_per_tile_round"] * 1.0001
+    after = ahpp.ahpp_query_batch(dg, srcs, eps, k=25)
+    assert torch.equal(before.pi, after.pi)
+    assert torch.equal(before.topk_idx, after.topk_idx)
+    assert [s["iters"] for s in before.stats] == [s["iters"] for s in after.stats]
+    dg.free()

@@ -138,3 +138,34 @@ def test_poisson_driver_completes(env):
     for t, r in res.items():
         assert r["stats"]["converged"] == 1 and int(srcs[t]) not in r["topk_idx"].tolist()
     srv.close()
+
+
+def test_server_graph_replay_matches_plain_launches(env, monkeypatch):
+    """The server's rounds replayed from HIP graphs give bitwise the results
+    of plain launches for the same submissions."""
+    g, dg, ahpp, torch = env
+    srcs = synth.degree_queries(g, 300, 44)
+    eps = [EPS_SET[i % 4] for i in range(srcs.size)]
+
+    def serve_all():
+        srv = ahpp.Server(dg, k=25, max_slots=256, keep_pi=True)
+        out = {}
+        for i in range(srcs.size):
+            srv.submit(i, int(srcs[i]), eps[i])
+            if i % 50 == 49:
+                srv.step(3)
+                out.update({r["tag"]: r for r in srv.results(want_pi=True)})
+        while len(out) < srcs.size:
+            srv.step(3)
+            out.update({r["tag"]: r for r in srv.results(want_pi=True)})
+        srv.close()
+        return out
+
+    monkeypatch.setenv("AHPP_GRAPHS", "0")
+    plain = serve_all()
+    monkeypatch.setenv("AHPP_GRAPHS", "1")
+    for rep in range(2):
+        replay = serve_all()
+        for t in range(srcs.size):
+            assert torch.equal(replay[t]["pi"], plain[t]["pi"]), (rep, t)
+            assert replay[t]["topk_idx"].tolist() == plain[t]["topk_idx"].tolist()
