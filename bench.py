@@ -92,6 +92,61 @@ def cpu_baseline(g, sources, eps):
 SERVE_EPS = (1e-5, 1e-6, 1e-7, 1e-8)
 
 
+# The paper's ASRP times on its Amazon graph at eps = 1e-6 (scalability
+# figure, 100% of the graph, one CPU thread of a Xeon Silver 4210): the two
+# sampling modes give 158,896 ms and 188,102 ms per query.
+PAPER_AMAZON_ASRP_MS = (158896.0, 188102.0)
+
+
+def amazon_leg(ahpp, synth, with_cpu, n=16):
+    """Plain single-query latency on the Amazon-shaped graph at eps = 1e-6,
+    beside the oracle's FP64 ASRP on one of the same queries (one thread)."""
+    g = synth.make_graph("amazon")
+    dg = ahpp.load_graph(g, device=0)
+    srcs = synth.degree_queries(g, n, 2005)
+    ahpp.ahpp_query(dg, int(srcs[0]), 1e-6, k=50)
+    lat = []
+    for s in srcs.tolist():
+        a = time.perf_counter()
+        ahpp.ahpp_query(dg, s, 1e-6, k=50, want_pi=False, want_stats=False)
+        lat.append((time.perf_counter() - a) * 1e3)
+    out = {"workload": "plain single-query push, eps 1e-6, k 50, on a synthetic graph of the paper's Amazon sizes "
+                       "(2.3M/8.0M/22.5M, 800 attributes x 10)",
+           "queries": n, "latency_ms_p50": round(_percentile(lat, 50), 2),
+           "latency_ms_p99": round(_percentile(lat, 99), 2), "lambda": round(dg.lam, 2),
+           "paper_asrp_ms_amazon": list(PAPER_AMAZON_ASRP_MS)}
+    dg.free()
+    if with_cpu:
+        import oracle
+        og = oracle.OracleGraph.from_graph(g)
+        lam = og.lambda_thm3()
+        t0 = time.perf_counter()
+        _, _, st, _ = og.asrp(int(srcs[0]), 1e-6, lam)
+        out["cpu_oracle_ms_one_thread"] = round((time.perf_counter() - t0) * 1e3, 1)
+        out["cpu_oracle_rounds"] = st.iterations
+        og.close()
+    return out
+
+
+def mc_leg(ahpp, synth, g, dg, eps=1e-3, p_f=1e-6):
+    """Monte Carlo walks at the sample size that gives an eps-approximate row
+    with probability 1 - p_f (Section 3.1), beside the push at the same eps."""
+    import math
+    walks = int(math.ceil(2.0 * (1.0 + eps / 3.0) * math.log(g.n_u / p_f) / eps ** 2))
+    src = int(synth.degree_queries(g, 1, 2006)[0])
+    ahpp.ahpp_query_mc(dg, src, 1 << 20, seed=1)  # builds the draw tables
+    t0 = time.perf_counter()
+    res = ahpp.ahpp_query_mc(dg, src, walks, seed=2, k=50)
+    mc_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    ahpp.ahpp_query(dg, src, eps, k=50)
+    push_ms = (time.perf_counter() - t0) * 1e3
+    st = res["stats"]
+    return {"workload": f"one source, eps {eps:g} with failure probability {p_f:g}: {walks} walks",
+            "walks": walks, "ms": round(mc_ms, 1), "walks_per_s": round(walks / (mc_ms / 1e3), 1),
+            "steps_per_s": round(st["steps"] / (mc_ms / 1e3), 1), "push_ms_same_eps": round(push_ms, 2)}
+
+
 def tiny_leg(ahpp, synth, n=200):
     """Plain single-query latency on the 2k/1k/20k graph (the small parity
     workload), where launch overhead rather than HBM decides the time."""
@@ -140,6 +195,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-tiny", action="store_true", help="skip the small-graph latency run")
     ap.add_argument("--no-tune", action="store_true", help="keep the untuned batch schedule")
+    ap.add_argument("--no-amazon", action="store_true", help="skip the Amazon-shaped latency run")
+    ap.add_argument("--no-mc", action="store_true", help="skip the Monte Carlo run")
     ap.add_argument("--serve-queries", type=int, default=800)
     ap.add_argument("--serve-rate", type=float, default=150.0, help="offered load, queries/s")
     ap.add_argument("--serve-slots", type=int, default=256)
@@ -206,6 +263,8 @@ def main():
 
     serving = None if args.no_serve else serve_leg(ahpp, synth, g, dg, args)
     plain_tiny = None if args.no_tiny else tiny_leg(ahpp, synth)
+    monte_carlo = None if args.no_mc else mc_leg(ahpp, synth, g, dg)
+    amazon = None if args.no_amazon else amazon_leg(ahpp, synth, not args.no_cpu)
 
     dom_kind = max(prof, key=lambda kk: prof[kk]["ms"])
     dom = prof[dom_kind]
@@ -245,6 +304,8 @@ def main():
         "tuned_schedule": tuned,
         "serving": serving,
         "plain_tiny": plain_tiny,
+        "amazon_shaped": amazon,
+        "monte_carlo": monte_carlo,
         "roofline": roofline,
         "kernels": {kname: {"launches": prof[kk]["launches"],
                             "avg_ms": round(prof[kk]["ms"] / max(prof[kk]["launches"], 1), 4),

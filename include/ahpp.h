@@ -208,6 +208,30 @@ ahpp_status_t ahpp_server_results(ahpp_server_t *s, int32_t max_n, int64_t *tags
 ahpp_status_t ahpp_server_info(const ahpp_server_t *s, int32_t *slots, int32_t *running, int32_t *queued,
                                int32_t *ready);
 
+/* Monte Carlo estimate of one AHPP row (Section 3.1; Lemma 1): n_walks
+ * alpha-hidden walks from `source`; pi(u, x) ~ (walks that stop at x) /
+ * n_walks.  Each walk stops at its node with probability alpha, else moves by
+ * one step of P (Eq. 1 / Eq. 2, drawn by weight); a walk that must step from
+ * a node with no edge (or no attribute) is lost, as the zero row of P loses
+ * that mass.  Randomness: SplitMix64 streams keyed by `seed` and the walk
+ * index; the counts, and so every output, depend only on the seed.
+ *   n_walks: >= 1 (<= 2^40).  pi_out: device float[n_u] (nullable).
+ *   k, topk_idx / topk_val / topk_n: as in ahpp_query (device buffers,
+ *   source excluded).  stats: host, nullable.
+ * Uses the graph's single-query buffers: one call at a time per graph, as
+ * for ahpp_query.  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+typedef struct {
+    int64_t walks;       /* n_walks */
+    int64_t lost;        /* walks ended by an empty row of P */
+    int64_t truncated;   /* walks cut at 4096 steps (probability (1-alpha)^4096) */
+    int64_t steps;       /* steps of P taken by all walks */
+    float ms;            /* device time of the call */
+    float pad;
+} ahpp_mc_stats_t;
+ahpp_status_t ahpp_query_mc(ahpp_graph_t *g, int32_t source, int64_t n_walks, uint64_t seed, float *pi_out,
+                            int32_t k, int32_t *topk_idx, float *topk_val, int32_t *topk_n, ahpp_mc_stats_t *stats,
+                            void *hip_stream);
+
 /* Schedule autotuner of the batched engine (ahpp_query_batch and servers
  * created afterwards).  Times a few rounds for each candidate schedule --
  * tiles of 256 queries in flight (1, 2, 4, ... up to max_tiles; <= 0: as

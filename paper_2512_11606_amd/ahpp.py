@@ -22,8 +22,8 @@ OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CONVERGED = 0, -1, -
 
 EXPORTED = ("ahpp_graph_load", "ahpp_graph_info", "ahpp_graph_free", "ahpp_query", "ahpp_query_batch", "ahpp_topk",
             "ahpp_server_create", "ahpp_server_free", "ahpp_server_submit", "ahpp_server_step",
-            "ahpp_server_results", "ahpp_server_info", "ahpp_graph_tune", "ahpp_profile_enable", "ahpp_profile_read",
-            "ahpp_last_error")
+            "ahpp_server_results", "ahpp_server_info", "ahpp_graph_tune", "ahpp_query_mc", "ahpp_profile_enable",
+            "ahpp_profile_read", "ahpp_last_error")
 
 # Kernel kinds of ahpp_profile_read.
 PROF_SINGLE_BACK, PROF_SINGLE_FWD, PROF_BATCH_BACK, PROF_BATCH_FWD, PROF_BATCH_HOT = 0, 1, 2, 3, 4
@@ -98,6 +98,8 @@ def load_library(path: str = LIB_PATH):
     lib.ahpp_server_results.argtypes = [P, i32, P, P, P, P, P, P, P, P]
     lib.ahpp_server_info.restype = ctypes.c_int
     lib.ahpp_server_info.argtypes = [P, P, P, P, P]
+    lib.ahpp_query_mc.restype = ctypes.c_int
+    lib.ahpp_query_mc.argtypes = [P, i32, i64, ctypes.c_uint64, P, i32, P, P, P, P, P]
     lib.ahpp_graph_tune.restype = ctypes.c_int
     lib.ahpp_graph_tune.argtypes = [P, i32, P, P]
     lib.ahpp_profile_enable.restype = ctypes.c_int
@@ -260,6 +262,30 @@ def ahpp_topk(g: Graph, pi, k: int, exclude: int = -1, stream=None):
 def ahpp_profile_enable(g: Graph, on: bool = True) -> None:
     """Starts (clearing totals) or stops HIP-event timing of the gather kernels."""
     _check(load_library().ahpp_profile_enable(g._h, 1 if on else 0))
+
+
+class McStats(ctypes.Structure):
+    _fields_ = [("walks", ctypes.c_int64), ("lost", ctypes.c_int64), ("truncated", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("ms", ctypes.c_float), ("pad", ctypes.c_float)]
+
+
+def ahpp_query_mc(g: Graph, source: int, n_walks: int, seed: int = 0, k: int = 0, want_pi: bool = True,
+                  stream=None) -> dict:
+    """Monte Carlo estimate of one AHPP row from n_walks walks (see ahpp.h):
+    dict with pi, topk_idx, topk_val, topk_n (torch tensors on the graph's
+    device, or None) and stats."""
+    import torch
+    dev = torch.device("cuda", g.device)
+    pi = torch.empty(g.n_u, dtype=torch.float32, device=dev) if want_pi else None
+    ti = torch.empty(max(k, 1), dtype=torch.int32, device=dev) if k > 0 else None
+    tv = torch.empty(max(k, 1), dtype=torch.float32, device=dev) if k > 0 else None
+    tn = torch.empty(1, dtype=torch.int32, device=dev) if k > 0 else None
+    st = McStats()
+    _check(load_library().ahpp_query_mc(g._h, int(source), int(n_walks), ctypes.c_uint64(int(seed) & (2**64 - 1)),
+                                        _dev_ptr(pi), int(k), _dev_ptr(ti), _dev_ptr(tv), _dev_ptr(tn),
+                                        ctypes.byref(st), _stream(g.device, stream)))
+    return {"pi": pi, "topk_idx": ti, "topk_val": tv, "topk_n": tn,
+            "stats": {f: getattr(st, f) for f, _ in st._fields_ if f != "pad"}}
 
 
 class TuneInfo(ctypes.Structure):

@@ -146,6 +146,16 @@ struct HotSet {
     int64_t cold_nnz = 0, cold_rows = 0;
 };
 
+// Weighted-draw tables of the Monte Carlo walks (built on first use).
+struct McTables {
+    int64_t *f_split = nullptr;  // [n_u] first attribute entry of each fwd row
+    double *f_cum = nullptr;     // [fwd nnz] prefix sums of raw weights, restarting at the split
+    double *b_cum = nullptr;     // [back nnz] prefix sums of raw weights per back row
+};
+struct McResult {
+    int64_t lost, truncated, steps;
+};
+
 // Launch timing of the gather kernels (see ahpp_profile_enable).
 constexpr int kProfKinds = 5;
 struct ProfLaunch {
@@ -194,6 +204,7 @@ struct Graph {
                                     // w(u,x) c_d(u) (V rows) or w(u,x) c_s(u) (attribute rows)
     float *inv_b = nullptr;         // 1/d(v) for V rows, 1/t(a) for attribute rows
     HotSet hot;                     // batched engine: hot back rows and the cold schedule
+    McTables mc;                    // Monte Carlo walks
     int64_t dangling_u = 0;
     int64_t device_bytes = 0;
     double load_ms = 0, lambda_ms = 0;
@@ -231,6 +242,13 @@ inline void dfree(void *p) {
     if (p) (void)hipFree(p);
 }
 void *dev_alloc(Graph &g, size_t bytes, const char *what);
+
+// mc.hip: n_walks walks from source; count[x] = walks stopped at x.
+void ensure_mc_tables(Graph &g, hipStream_t s);
+void free_mc_tables(McTables &t);
+McResult mc_walks(Graph &g, int32_t source, int64_t n_walks, uint64_t seed, int max_steps, unsigned *count,
+                  hipStream_t s);
+void mc_scores(const unsigned *count, int64_t n, int64_t n_walks, float *out, hipStream_t s);
 
 // graph_build.hip
 void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew, const int32_t *au,

@@ -503,6 +503,44 @@ ahpp_status_t ahpp_query(ahpp_graph_t *h, int32_t source, double eps, int32_t ma
     return AHPP_OK;
 }
 
+ahpp_status_t ahpp_query_mc(ahpp_graph_t *h, int32_t source, int64_t n_walks, uint64_t seed, float *pi_out,
+                            int32_t k, int32_t *topk_idx, float *topk_val, int32_t *topk_n, ahpp_mc_stats_t *stats,
+                            void *hip_stream) {
+    g_last_error.clear();
+    if (!h) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_mc: NULL graph");
+    Graph &g = h->g;
+    if (source < 0 || source >= g.n_u) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_mc: source out of range");
+    if (n_walks < 1 || n_walks > (int64_t(1) << 40)) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_mc: n_walks out of range");
+    if (k < 0 || k > kMaxTopK) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_mc: k must be in [0, 2048]");
+    if (k > 0 && (!topk_idx || !topk_val || !topk_n))
+        return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_mc: top-k outputs required when k > 0");
+    hipStream_t s = (hipStream_t)hip_stream;
+    try {
+        DeviceScope scope(g.device);
+        ensure_mc_tables(g, s);
+        hipEvent_t e0, e1;
+        check_hip(hipEventCreate(&e0), "event");
+        check_hip(hipEventCreate(&e1), "event");
+        check_hip(hipEventRecord(e0, s), "event");
+        // Counts in the residue buffer, scores in the reserve buffer.
+        unsigned *count = reinterpret_cast<unsigned *>(g.q_r);
+        const McResult r = mc_walks(g, source, n_walks, seed, 4096, count, s);
+        float *scores = pi_out ? pi_out : g.q_pi;
+        mc_scores(count, g.n_u, n_walks, scores, s);
+        if (k > 0) topk_launch(scores, g.n_u, 0, 1, nullptr, source, k, topk_idx, topk_val, topk_n, g.tk_scratch, s);
+        check_hip(hipEventRecord(e1, s), "event");
+        check_hip(hipStreamSynchronize(s), "walks");
+        float ms = 0.0f;
+        check_hip(hipEventElapsedTime(&ms, e0, e1), "event");
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (stats) *stats = ahpp_mc_stats_t{n_walks, r.lost, r.truncated, r.steps, ms, 0.0f};
+    } catch (const Failure &f) {
+        return fail(f.status, f.msg);
+    }
+    return AHPP_OK;
+}
+
 ahpp_status_t ahpp_query_batch(ahpp_graph_t *h, int32_t n_q, const int32_t *sources, const double *eps,
                                int32_t max_iters, float *pi_out, int32_t k, int32_t *topk_idx, float *topk_val,
                                int32_t *topk_n, ahpp_stats_t *stats, void *hip_stream) {

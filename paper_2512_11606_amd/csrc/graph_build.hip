@@ -571,6 +571,7 @@ void free_graph(Graph &g) {
     free_csr(g.fwd);
     free_csr(g.back);
     free_csr(g.hot.list);
+    free_mc_tables(g.mc);
     for (void *p : {(void *)g.hot.rows, (void *)g.hot.len, (void *)g.hot.cold_items, (void *)g.hot.cold_split}) dfree(p);
     g.hot = HotSet{};
     free_batch_state(g.batch);

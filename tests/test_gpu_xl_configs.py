@@ -152,3 +152,42 @@ def test_hub_batch_on_the_20m_graph(env):
         og.close()
     del pi, res
     dg.free()
+
+
+@pytest.mark.timeout(900)
+def test_amazon_shaped_graph(env):
+    """The graph of the paper's Amazon sizes (2.3M/8.0M/22.5M, 800 attributes
+    x 10) at eps = 1e-6, the setting of its scalability figure: two plain
+    queries in full against the oracle's exact series, and a batch of 256
+    whose results agree with the plain path."""
+    ahpp, torch = env
+    g = synth.make_graph("amazon")
+    dg = ahpp.load_graph(g)
+    _say("loaded amazon-shaped graph; lambda", dg.lam)
+    eps = 1e-6
+    srcs = synth.degree_queries(g, 256, 2005)
+    og = O.OracleGraph.from_graph(g)
+    plain = {}
+    for q in (0, 1):
+        s = int(srcs[q])
+        t0 = time.time()
+        r = ahpp.ahpp_query(dg, s, eps, k=50, want_resid=True)
+        torch.cuda.synchronize()
+        _say(f"plain query {s}: {(time.time() - t0) * 1e3:.1f} ms, {r.stats[0]['iters']} rounds")
+        exact, tail = og.power_series(s)
+        pi = r.pi.cpu().numpy().astype(np.float64)
+        chk = O.check_query(exact, pi, eps, tol=TOL, resid=r.resid.cpu().numpy(), k=50, source=s,
+                            topk_ids=r.topk_idx[: int(r.topk_n.item())].cpu().numpy())
+        _say("check", q, chk.ok, f"max |err| {chk.max_abs_err:.3e}")
+        assert chk.ok, chk.detail
+        plain[q] = pi
+    og.close()
+    res = ahpp.ahpp_query_batch(dg, srcs, eps, k=50)
+    sums = res.pi.sum(dim=1, dtype=torch.float64).cpu().numpy()
+    for q in range(srcs.size):
+        st = res.stats[q]
+        assert st["converged"] == 1 and st["max_residual"] <= eps / dg.lam * (1 + 1e-6), q
+        assert abs(sums[q] + st["sum_residual"] - 1.0) < 1e-5, q
+    for q in (0, 1):
+        assert np.abs(res.pi[q].cpu().numpy().astype(np.float64) - plain[q]).max() <= eps + TOL
+    dg.free()
