@@ -235,8 +235,8 @@ ahpp_status_t ahpp_query_mc(ahpp_graph_t *g, int32_t source, int64_t n_walks, ui
 /* Schedule autotuner of the batched engine (ahpp_query_batch and servers
  * created afterwards).  Times a few rounds for each candidate schedule --
  * tiles of 256 queries in flight (1, 2, 4, ... up to max_tiles; <= 0: as
- * many as fit in a quarter of the free device memory, at most 16) and 1, 2
- * or 4 times the default workgroups per tile of the gathers -- and keeps
+ * many as fit in a quarter of the free device memory, at most 16) and 1,
+ * 2, 4 or 8 times the default workgroups per tile of the gathers -- keeps
  * the one with the least time per tile-round.  A round reads every CSR
  * entry whatever the frontier, so a few rounds measure the steady state.
  * Results do not depend on the schedule (every sum has a fixed order), only

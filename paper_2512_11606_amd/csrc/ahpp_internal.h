@@ -112,8 +112,10 @@ struct BatchState {
     float *blk_max = nullptr;       // [tiles][2][grid_x][kTileQ]
     unsigned long long *blk_np = nullptr;  // [tiles][5][grid_x][kTileQ]
     float *hot_part = nullptr;      // [tiles][hot chunks][hot rows][kTileQ]
+    float *red_max = nullptr;       // [tiles][control slices][kTileQ] partial maxima
+    unsigned long long *red_np = nullptr;  // [tiles][control slices][kTileQ] partial n_p
     float *out = nullptr;           // [tiles * kTileQ][n_u] query-major scores for top-k
-    double *sums = nullptr;         // [tiles][grid_x][kTileQ] residue sums
+    double *sums = nullptr;         // [tiles][grid_cap][kTileQ] residue sums
     int64_t live_q = 0;             // queries still running at the last poll
     // One captured round per number of tiles in flight (replayed on the
     // caller's stream); they name this state's buffers, so they go with it.

@@ -92,8 +92,8 @@ struct BArgs {
     float *part;           // chunk partials (tile 0), [item][kTileQ]
     TileCtl *ctl;          // tile 0
     int64_t x_stride, y_stride, pi_stride, part_stride;  // floats per tile
-    float *blk_max;        // [tile][2][grid_cap][kTileQ] slot base of this launch
-    unsigned long long *blk_np;  // [tile][5][grid_cap][kTileQ] slot base
+    float *blk_max;        // [tile][2][batch_cap][kTileQ] slot base of this launch
+    unsigned long long *blk_np;  // [tile][5][batch_cap][kTileQ] slot base
     int64_t blk_stride_f, blk_stride_u;   // elements per tile
     float alpha;
 };
@@ -364,75 +364,96 @@ __global__ void __launch_bounds__(kBlock) kb_fix(BArgs a) {
 
 // One workgroup per tile, one thread per query: max r and n_p from the
 // partials, then the stop / switch rule of Algorithm 4 for every running query.
-constexpr int kCtlSplit = 4;  // threads per query reducing the partials
+constexpr int kCtlSplit = 4;    // threads per query reducing the partials
 constexpr int kCtlThreads = kCtlSplit * kTileQ;
+constexpr int kCtlSlices = 8;   // workgroups per tile reducing the partials
 
-__global__ void __launch_bounds__(kCtlThreads) kb_control(TileCtl *ctl, const float *blk_max,
-                                                          const unsigned long long *blk_np, int64_t stride_f,
-                                                          int64_t stride_u, int grid_cap, int n_back, int n_back_fix,
-                                                          int n_fwd, int n_fwd_fix, int n_hot, Rule rule) {
-    __shared__ int running_any[kTileQ / kWave];
+// Workgroup (slice, tile), thread (part, q): max r and n_p of query q over
+// the workgroup partials i with i % (kCtlSplit * kCtlSlices) ==
+// slice * kCtlSplit + part; max and integer sums do not depend on the order.
+__global__ void __launch_bounds__(kCtlThreads) kb_control_partials(
+    const TileCtl *ctl, const float *blk_max, const unsigned long long *blk_np, int64_t stride_f, int64_t stride_u,
+    int cap, int n_back, int n_back_fix, int n_fwd, int n_fwd_fix, int n_hot, float *red_max,
+    unsigned long long *red_np) {
     __shared__ float s_max[kCtlSplit][kTileQ];
     __shared__ unsigned long long s_np[kCtlSplit][kTileQ];
-    const int t = blockIdx.x;
-    TileCtl &tc = ctl[t];
-    if (tc.all_done) return;
-    // Thread (part, q) reduces every kCtlSplit-th workgroup partial of query
-    // q; max and integer sums do not depend on the order.
+    const int t = blockIdx.y;
+    if (ctl[t].all_done) return;
     const int q = threadIdx.x % kTileQ, part = threadIdx.x / kTileQ;
+    const int first = blockIdx.x * kCtlSplit + part, step = kCtlSplit * kCtlSlices;
     const float *bm = blk_max + t * stride_f;
     const unsigned long long *bn = blk_np + t * stride_u;
     float m = 0.0f;
-    for (int i = part; i < n_fwd; i += kCtlSplit) m = fmaxf(m, bm[(int64_t)i * kTileQ + q]);
-    for (int i = part; i < n_fwd_fix; i += kCtlSplit) m = fmaxf(m, bm[((int64_t)grid_cap + i) * kTileQ + q]);
+    for (int i = first; i < n_fwd; i += step) m = fmaxf(m, bm[(int64_t)i * kTileQ + q]);
+    for (int i = first; i < n_fwd_fix; i += step) m = fmaxf(m, bm[((int64_t)cap + i) * kTileQ + q]);
     unsigned long long np = 0;
     const int cnt[5] = {n_back, n_back_fix, n_fwd, n_fwd_fix, n_hot};
 #pragma unroll
     for (int k = 0; k < 5; ++k)
-        for (int i = part; i < cnt[k]; i += kCtlSplit) np += bn[((int64_t)k * grid_cap + i) * kTileQ + q];
+        for (int i = first; i < cnt[k]; i += step) np += bn[((int64_t)k * cap + i) * kTileQ + q];
     s_max[part][q] = m;
     s_np[part][q] = np;
     __syncthreads();
-    // Part 0 (the first kTileQ / kWave waves) applies the rule; every
-    // thread still reaches both barriers.
     if (part == 0) {
 #pragma unroll
         for (int i = 1; i < kCtlSplit; ++i) {
             m = fmaxf(m, s_max[i][q]);
             np += s_np[i][q];
         }
-        QueryCtl &c = tc.q[q];
-        int done = c.done;
-        if (!done) {
-            const unsigned long long n_p = c.n_p + np;
-            const int iter = c.iter + 1;
-            c.n_p = n_p;
-            c.iter = iter;
-            c.last_max = m;
-            if (!(m > c.eps_f)) {
-                done = 1;
-                c.status = 1;
-            } else if (iter >= c.max_iters) {
-                done = 1;
-                c.status = 2;
-            } else if (c.phase == 1) {
-                const double tt = (double)logf(m / c.eps_f) * (double)rule.inv_log;
-                if ((double)n_p >= rule.budget_scale * (tt > 0.0 ? tt : 0.0)) {
-                    c.phase = 2;
-                    c.theta = 0.0f;
-                    c.switch_iter = iter;
-                }
-            }
-            if (done) {
-                c.done = 1;
-                c.theta = FLT_MAX;
+        const int64_t o = ((int64_t)t * kCtlSlices + blockIdx.x) * kTileQ + q;
+        red_max[o] = m;
+        red_np[o] = np;
+    }
+}
+
+// One workgroup per tile, one thread per query: combines the slices, then
+// the stop / switch rule of Algorithm 4 for every running query.
+__global__ void __launch_bounds__(kTileQ) kb_control(TileCtl *ctl, const float *red_max,
+                                                     const unsigned long long *red_np, Rule rule) {
+    __shared__ int running_any[kTileQ / kWave];
+    const int t = blockIdx.x;
+    TileCtl &tc = ctl[t];
+    if (tc.all_done) return;
+    const int q = threadIdx.x;
+    float m = 0.0f;
+    unsigned long long np = 0;
+#pragma unroll
+    for (int i = 0; i < kCtlSlices; ++i) {
+        const int64_t o = ((int64_t)t * kCtlSlices + i) * kTileQ + q;
+        m = fmaxf(m, red_max[o]);
+        np += red_np[o];
+    }
+    QueryCtl &c = tc.q[q];
+    int done = c.done;
+    if (!done) {
+        const unsigned long long n_p = c.n_p + np;
+        const int iter = c.iter + 1;
+        c.n_p = n_p;
+        c.iter = iter;
+        c.last_max = m;
+        if (!(m > c.eps_f)) {
+            done = 1;
+            c.status = 1;
+        } else if (iter >= c.max_iters) {
+            done = 1;
+            c.status = 2;
+        } else if (c.phase == 1) {
+            const double tt = (double)logf(m / c.eps_f) * (double)rule.inv_log;
+            if ((double)n_p >= rule.budget_scale * (tt > 0.0 ? tt : 0.0)) {
+                c.phase = 2;
+                c.theta = 0.0f;
+                c.switch_iter = iter;
             }
         }
-        const unsigned long long running = __ballot(!done);
-        if ((q & 63) == 0) running_any[q >> 6] = running != 0ull;
+        if (done) {
+            c.done = 1;
+            c.theta = FLT_MAX;
+        }
     }
+    const unsigned long long running = __ballot(!done);
+    if ((q & 63) == 0) running_any[q >> 6] = running != 0ull;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (q == 0) {
         int any = 0;
         for (int i = 0; i < kTileQ / kWave; ++i) any |= running_any[i];
         tc.all_done = any ? 0 : 1;
@@ -790,6 +811,11 @@ __global__ void __launch_bounds__(kBlock) kb_sums(const float *x, int64_t x_stri
     }
 }
 
+// Workgroups per tile of a batch gather launch are at most this many (the
+// per-workgroup partial slots are sized for it): twice the single-query cap,
+// so the tuner can try up to 8x the default share per tile.
+int batch_cap(const Graph &g) { return 2 * g.grid_cap; }
+
 unsigned capped(int64_t n_units, int64_t per_block, int cap) {
     int64_t g = (n_units + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -828,7 +854,7 @@ BackSched back_sched(const Graph &g) {
 }
 
 BPlan bplan(const Graph &g, int nt) {
-    const int cap = std::min(g.grid_cap, std::max(64, g.tuned_wg_mult * g.grid_cap / std::max(nt, 1)));
+    const int cap = std::min(batch_cap(g), std::max(64, g.tuned_wg_mult * g.grid_cap / std::max(nt, 1)));
     const BackSched bs = back_sched(g);
     BPlan p;
     p.back = bs.n_items ? capped(bs.n_items, kWavesPerBlock, cap) : 0;
@@ -843,7 +869,8 @@ BPlan bplan(const Graph &g, int nt) {
 void free_batch_state(BatchState &b) {
     for (auto &e : b.round_graphs) (void)hipGraphExecDestroy(e.second);
     for (void *p : {(void *)b.r, (void *)b.pi, (void *)b.z, (void *)b.part, (void *)b.ctl, (void *)b.blk_max,
-                    (void *)b.blk_np, (void *)b.hot_part, (void *)b.out, (void *)b.sums})
+                    (void *)b.blk_np, (void *)b.red_max, (void *)b.red_np, (void *)b.hot_part, (void *)b.out,
+                    (void *)b.sums})
         dfree(p);
     b = BatchState{};
 }
@@ -853,7 +880,8 @@ int64_t batch_tile_bytes(const Graph &g, bool with_out) {
     const int64_t Q = kTileQ;
     const int64_t hot = (int64_t)g.hot.n_chunks * g.hot.n;
     return Q * 4 * (2 * g.n_u + std::max<int64_t>(g.n_v + g.n_a, 1) + items + hot + (with_out ? g.n_u : 0)) +
-           (int64_t)sizeof(TileCtl) + (int64_t)g.grid_cap * Q * (2 * 4 + 5 * 8 + 8);
+           (int64_t)sizeof(TileCtl) + (int64_t)batch_cap(g) * Q * (2 * 4 + 5 * 8) + (int64_t)g.grid_cap * Q * 8 +
+           (int64_t)kCtlSlices * Q * 12;
 }
 
 void ensure_batch_state(Graph &g, BatchState &b, int tiles, bool with_out) {
@@ -866,14 +894,16 @@ void ensure_batch_state(Graph &g, BatchState &b, int tiles, bool with_out) {
     b.z = (float *)dev_alloc(g, T * std::max<int64_t>(g.n_v + g.n_a, 1) * Q * 4, "batch V/attribute residues");
     b.part = (float *)dev_alloc(g, T * items * Q * 4, "batch chunk partials");
     b.ctl = (TileCtl *)dev_alloc(g, T * sizeof(TileCtl), "batch control");
-    b.blk_max = (float *)dev_alloc(g, T * 2 * g.grid_cap * Q * 4, "batch workgroup maxima");
-    b.blk_np = (unsigned long long *)dev_alloc(g, T * 5 * g.grid_cap * Q * 8, "batch workgroup counts");
+    b.blk_max = (float *)dev_alloc(g, T * 2 * batch_cap(g) * Q * 4, "batch workgroup maxima");
+    b.blk_np = (unsigned long long *)dev_alloc(g, T * 5 * batch_cap(g) * Q * 8, "batch workgroup counts");
+    b.red_max = (float *)dev_alloc(g, T * kCtlSlices * Q * 4, "batch control slices");
+    b.red_np = (unsigned long long *)dev_alloc(g, T * kCtlSlices * Q * 8, "batch control slices");
     if (g.hot.n > 0)
         b.hot_part = (float *)dev_alloc(g, T * (size_t)g.hot.n_chunks * g.hot.n * Q * 4, "batch hot-row partials");
     if (with_out) b.out = (float *)dev_alloc(g, T * Q * g.n_u * 4, "batch scores");
     b.sums = (double *)dev_alloc(g, T * g.grid_cap * Q * 8, "batch sums");
     b.tiles = tiles;
-    b.grid_x = g.grid_cap;
+    b.grid_x = batch_cap(g);
 }
 
 void batch_init(Graph &g, BatchState &b, int nt, const int32_t *sources, const float *eps_f, int64_t n_q,
@@ -898,14 +928,14 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
     const HotSet &hs = g.hot;
     const int64_t tile_u = g.n_u * kTileQ, tile_z = std::max<int64_t>(g.n_v + g.n_a, 1) * kTileQ;
     const int64_t tile_part = std::max<int64_t>(std::max(g.fwd.n_items, g.back.n_items), 1) * kTileQ;
-    const int64_t sf = 2 * (int64_t)g.grid_cap * kTileQ, su = 5 * (int64_t)g.grid_cap * kTileQ;
+    const int64_t sf = 2 * (int64_t)batch_cap(g) * kTileQ, su = 5 * (int64_t)batch_cap(g) * kTileQ;
     BArgs back{g.back.off, g.back.col, g.back.w, bs.items, bs.n_items, bs.split, bs.n_split,
                b.r, b.z, nullptr, g.inv_b, b.part, b.ctl, tile_u, tile_z, 0, tile_part, nullptr, b.blk_np, sf, su,
                (float)g.alpha};
     // Slots of the n_p partials: 0 back, 1 back fix, 2 fwd, 3 fwd fix, 4 hot
-    // rows; of the max partials: 0 fwd, 1 fwd fix; slots are grid_cap
+    // rows; of the max partials: 0 fwd, 1 fwd fix; slots are batch_cap
     // workgroups apart.
-    const int64_t slot = (int64_t)g.grid_cap * kTileQ;
+    const int64_t slot = (int64_t)batch_cap(g) * kTileQ;
     // Algorithmic bytes of a launch: CSR entries and offsets once, 4 bytes
     // per (entry, running query), and the per-(row, query) state the
     // epilogue reads and writes.  The hot-row pass reads the hot list and
@@ -950,8 +980,10 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
         a.blk_np += slot;
         hipLaunchKernelGGL((kb_fix<kBFwd>), dim3(p.fwd_fix, nt), dim3(kBlock), 0, s, a);
     }
-    hipLaunchKernelGGL(kb_control, dim3(nt), dim3(kCtlThreads), 0, s, b.ctl, b.blk_max, b.blk_np, sf, su, g.grid_cap,
-                       (int)p.back, (int)p.back_fix, (int)p.fwd, (int)p.fwd_fix, hs.n, make_rule(g));
+    hipLaunchKernelGGL(kb_control_partials, dim3(kCtlSlices, nt), dim3(kCtlThreads), 0, s, b.ctl, b.blk_max,
+                       b.blk_np, sf, su, batch_cap(g), (int)p.back, (int)p.back_fix, (int)p.fwd, (int)p.fwd_fix, hs.n,
+                       b.red_max, b.red_np);
+    hipLaunchKernelGGL(kb_control, dim3(nt), dim3(kTileQ), 0, s, b.ctl, b.red_max, b.red_np, make_rule(g));
     check_hip(hipGetLastError(), "batch round launch");
 }
 
@@ -978,8 +1010,8 @@ TuneResult batch_tune(Graph &g, int max_tiles, hipStream_t s) {
         std::vector<int32_t> src((size_t)n_q);
         std::vector<float> eps_f((size_t)n_q, 1e-30f);
         for (int64_t i = 0; i < n_q; ++i) src[i] = (int32_t)i;
-        for (int mult : {1, 2, 4}) {
-            if (mult > 1 && std::max(64, (mult / 2) * g.grid_cap / nt) >= g.grid_cap) break;  // same plan as before
+        for (int mult : {1, 2, 4, 8}) {
+            if (mult > 1 && std::max(64, (mult / 2) * g.grid_cap / nt) >= batch_cap(g)) break;  // same plan as before
             g.tuned_wg_mult = mult;
             batch_init(g, g.batch, nt, src.data(), eps_f.data(), n_q, 1 << 20, s);
             g.batch.live_q = n_q;

@@ -282,7 +282,7 @@ def test_tuned_schedule_changes_speed_only(torch_cuda, ahpp):
     before = ahpp.ahpp_query_batch(dg, srcs, eps, k=25)
     info = ahpp.ahpp_graph_tune(dg, max_tiles=4)
     _say("tuned", info)
-    assert info["tiles_in_flight"] in (1, 2, 4) and info["workgroup_multiplier"] in (1, 2, 4)
+    assert info["tiles_in_flight"] in (1, 2, 4) and info["workgroup_multiplier"] in (1, 2, 4, 8)
     assert info["candidates"] >= 3 and 0 < info["ms_per_tile_round"] <= info["default_ms_per_tile_round"] * 1.0001
     after = ahpp.ahpp_query_batch(dg, srcs, eps, k=25)
     assert torch.equal(before.pi, after.pi)
