@@ -147,6 +147,31 @@ def mc_leg(ahpp, synth, g, dg, eps=1e-3, p_f=1e-6):
             "steps_per_s": round(st["steps"] / (mc_ms / 1e3), 1), "push_ms_same_eps": round(push_ms, 2)}
 
 
+SCHEDULE_NAMES = ("ASRP", "APP", "APP(S)", "APP(E)")
+
+
+def schedule_leg(ahpp, synth, g, dg, n=4, eps_list=(1e-6, 1e-7)):
+    """Exp-2's comparison on the loaded graph: the same sources under ASRP,
+    APP (r_max = eps / (|E| + |E_A|)), APP(S) and APP(E), plain path, k 50."""
+    srcs = synth.degree_queries(g, n, 2007).tolist()
+    out = {"workload": f"{n} degree-weighted sources per eps, plain single-query path, k 50", "eps": {}}
+    for eps in eps_list:
+        row = {}
+        for sch, name in enumerate(SCHEDULE_NAMES):
+            ahpp.ahpp_query_schedule(dg, srcs[0], eps, sch, k=50, want_pi=False)
+            lat, rounds, sw, pushes = [], [], [], []
+            for s in srcs:
+                a = time.perf_counter()
+                r = ahpp.ahpp_query_schedule(dg, s, eps, sch, k=50, want_pi=False)
+                lat.append((time.perf_counter() - a) * 1e3)
+                st = r.stats[0]
+                rounds.append(st["iters"]); sw.append(st["sync_switch_iter"]); pushes.append(st["n_push"])
+            row[name] = {"ms_mean": round(sum(lat) / n, 2), "rounds_mean": round(sum(rounds) / n, 1),
+                         "switch_round": sw, "pushes_mean": round(sum(pushes) / n)}
+        out["eps"][f"{eps:g}"] = row
+    return out
+
+
 def tiny_leg(ahpp, synth, n=200):
     """Plain single-query latency on the 2k/1k/20k graph (the small parity
     workload), where launch overhead rather than HBM decides the time."""
@@ -197,6 +222,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the untuned batch schedule")
     ap.add_argument("--no-amazon", action="store_true", help="skip the Amazon-shaped latency run")
     ap.add_argument("--no-mc", action="store_true", help="skip the Monte Carlo run")
+    ap.add_argument("--no-schedules", action="store_true", help="skip the ASRP / APP / APP(S) / APP(E) comparison")
     ap.add_argument("--serve-queries", type=int, default=800)
     ap.add_argument("--serve-rate", type=float, default=150.0, help="offered load, queries/s")
     ap.add_argument("--serve-slots", type=int, default=256)
@@ -264,6 +290,7 @@ def main():
     serving = None if args.no_serve else serve_leg(ahpp, synth, g, dg, args)
     plain_tiny = None if args.no_tiny else tiny_leg(ahpp, synth)
     monte_carlo = None if args.no_mc else mc_leg(ahpp, synth, g, dg)
+    schedules = None if args.no_schedules else schedule_leg(ahpp, synth, g, dg)
     amazon = None if args.no_amazon else amazon_leg(ahpp, synth, not args.no_cpu)
 
     dom_kind = max(prof, key=lambda kk: prof[kk]["ms"])
@@ -306,6 +333,7 @@ def main():
         "plain_tiny": plain_tiny,
         "amazon_shaped": amazon,
         "monte_carlo": monte_carlo,
+        "push_schedules": schedules,
         "roofline": roofline,
         "kernels": {kname: {"launches": prof[kk]["launches"],
                             "avg_ms": round(prof[kk]["ms"] / max(prof[kk]["launches"], 1), 4),

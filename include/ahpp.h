@@ -138,6 +138,24 @@ ahpp_status_t ahpp_query(ahpp_graph_t *g, int32_t source, double eps, int32_t ma
                          int32_t k, int32_t *topk_idx, float *topk_val, int32_t *topk_n,
                          ahpp_stats_t *stats, void *hip_stream);
 
+/* The same query under the push schedules the paper compares in Exp-2
+ * (the rounds of Algorithm 3 in every case):
+ *   0 ASRP    Algorithm 4 (= ahpp_query).
+ *   1 APP     Algorithm 3 with r_max = eps / (|E| + |E_A|): u is pushed when
+ *             r(u) > r_max (|N(u)| + |A(u)|); stops when no u is.
+ *   2 APP(S)  APP plus Algorithm 4's switch to synchronous rounds, with the
+ *             budget's logarithm taken of max_u r(u) / (r_max (|N(u)| +
+ *             |A(u)|)); stops by APP's rule.
+ *   3 APP(E)  APP with Algorithm 4's threshold eps / lambda and stop rule
+ *             max r <= eps / lambda, no switch.
+ * Arguments, outputs and errors as ahpp_query (INVALID_ARG also for a
+ * schedule outside 0..3); for APP and APP(S), stats->max_residual is the
+ * largest r(u) / (r_max (|N(u)| + |A(u)|)), which the stop rule brings to
+ * <= 1. */
+ahpp_status_t ahpp_query_schedule(ahpp_graph_t *g, int32_t source, double eps, int32_t schedule, int32_t max_iters,
+                                  float *pi_out, float *resid_out, int32_t k, int32_t *topk_idx, float *topk_val,
+                                  int32_t *topk_n, ahpp_stats_t *stats, void *hip_stream);
+
 /* n_q independent queries answered together (Section 5.1 runs queries
  * independently): the rounds of Algorithm 4 for all of them share each pass
  * over the edge lists.  Each query keeps its own eps_f, threshold, phase and

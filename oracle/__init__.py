@@ -17,7 +17,8 @@ Pieces (each names the passage of arXiv 2512.11606 it follows):
 * ``OracleGraph.power_series``: Def. 2 / Algorithm 1 (PI) as a truncated power
   series in C, with its certified tail (Section 3.2).
 * ``OracleGraph.lambda_thm3``: Theorem 3, Eq. 6.
-* ``OracleGraph.asrp`` / ``app``: Algorithms 4 and 3 in double precision.
+* ``OracleGraph.asrp`` / ``app`` / ``forward_push``: Algorithms 4, 3 and 2 in double
+  precision; ``push_schedule``: the four schedules of Exp-2.
 * ``topk``: the k most similar nodes (Exp-4/Exp-6 use of the scores).
 * ``check_query``: Theorem 2's bound and sign, mass conservation, top-k band.
 
@@ -83,6 +84,10 @@ def _load():
     lib.og_asrp_hooked.argtypes = [P, dbl, dbl, i32, dbl, dbl, i64, P, P, P, P, P]
     lib.og_app.restype = ctypes.c_int
     lib.og_app.argtypes = [P, dbl, dbl, i32, dbl, i64, P, P, P]
+    lib.og_forward_push.restype = ctypes.c_int
+    lib.og_forward_push.argtypes = [P, dbl, dbl, i32, dbl, i64, P, P, P, P, P]
+    lib.og_push_schedule.restype = ctypes.c_int
+    lib.og_push_schedule.argtypes = [P, dbl, dbl, i32, dbl, dbl, i32, i64, P, P, P, P, P]
     lib.og_asrp_many.restype = ctypes.c_int
     lib.og_asrp_many.argtypes = [P, dbl, dbl, i32, P, dbl, dbl, i64, ctypes.c_int, P, P]
     lib.og_max_threads.restype = ctypes.c_int
@@ -92,6 +97,34 @@ def _load():
 
 HOOK = ctypes.CFUNCTYPE(None, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                         ctypes.c_void_p)
+
+
+class _Hook:
+    """A Python per-round hook as a C callback.  ctypes only prints an
+    exception raised inside a callback, so the first one is kept (later
+    rounds skip the hook) and raised again once the C call returns."""
+
+    def __init__(self, hook, n: int):
+        self.error = None
+        self.ptr = None
+        if hook is None:
+            return
+
+        def _cb(it, p, rr, user):
+            if self.error is not None:
+                return
+            try:
+                hook(int(it), np.ctypeslib.as_array(p, shape=(n,)).copy(),
+                     np.ctypeslib.as_array(rr, shape=(n,)).copy())
+            except BaseException as e:  # noqa: BLE001 - re-raised by reraise()
+                self.error = e
+
+        self._cb = HOOK(_cb)
+        self.ptr = ctypes.cast(self._cb, ctypes.c_void_p)
+
+    def reraise(self):
+        if self.error is not None:
+            raise self.error
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -174,15 +207,10 @@ class OracleGraph:
             rc = _load().og_asrp(self._h, alpha, beta, int(source), eps, lam, int(max_iters), _ptr(pi), _ptr(r),
                                  ctypes.byref(st))
         else:
-            n = self.n_u
-
-            def _cb(it, p, rr, user):
-                hook(int(it), np.ctypeslib.as_array(p, shape=(n,)).copy(),
-                     np.ctypeslib.as_array(rr, shape=(n,)).copy())
-
-            cb = HOOK(_cb)
+            hk = _Hook(hook, self.n_u)
             rc = _load().og_asrp_hooked(self._h, alpha, beta, int(source), eps, lam, int(max_iters), _ptr(pi),
-                                        _ptr(r), ctypes.byref(st), ctypes.cast(cb, ctypes.c_void_p), None)
+                                        _ptr(r), ctypes.byref(st), hk.ptr, None)
+            hk.reraise()
         if rc < 0:
             raise ValueError("asrp: bad arguments")
         stats = PushStats(st.iterations, st.switch_iteration, st.n_push, st.max_residual, st.sum_residual)
@@ -197,6 +225,35 @@ class OracleGraph:
             raise ValueError("app: bad arguments")
         return pi, r, PushStats(st.iterations, st.switch_iteration, st.n_push, st.max_residual,
                                 st.sum_residual), rc == 0
+
+    def forward_push(self, source: int, r_max: float, alpha: float = ALPHA, beta: float = BETA,
+                     max_pushes: int = 100_000_000, hook=None):
+        """Algorithm 2 (FP) in double precision, one node at a time from a FIFO
+        queue: (reserve, U residues, stats, converged); stats.iterations counts
+        node pushes.  hook(push, reserve, residues) runs after every push."""
+        pi = np.zeros(self.n_u); r = np.zeros(self.n_u); st = _Stats()
+        hk = _Hook(hook, self.n_u)
+        rc = _load().og_forward_push(self._h, alpha, beta, int(source), r_max, int(max_pushes), _ptr(pi), _ptr(r),
+                                     ctypes.byref(st), hk.ptr, None)
+        hk.reraise()
+        if rc < 0:
+            raise ValueError("forward_push: bad arguments")
+        stats = PushStats(st.iterations, st.switch_iteration, st.n_push, st.max_residual, st.sum_residual)
+        return pi, r, stats, rc == 0
+
+    def push_schedule(self, source: int, eps: float, lam: float, schedule: int, alpha: float = ALPHA,
+                      beta: float = BETA, max_iters: int = 1_000_000, hook=None):
+        """Exp-2's schedules (0 ASRP, 1 APP, 2 APP(S), 3 APP(E)) in double
+        precision: (reserve, U residues, stats, converged)."""
+        pi = np.zeros(self.n_u); r = np.zeros(self.n_u); st = _Stats()
+        hk = _Hook(hook, self.n_u)
+        rc = _load().og_push_schedule(self._h, alpha, beta, int(source), eps, lam, int(schedule), int(max_iters),
+                                      _ptr(pi), _ptr(r), ctypes.byref(st), hk.ptr, None)
+        hk.reraise()
+        if rc < 0:
+            raise ValueError("push_schedule: bad arguments")
+        stats = PushStats(st.iterations, st.switch_iteration, st.n_push, st.max_residual, st.sum_residual)
+        return pi, r, stats, rc == 0
 
     def asrp_many(self, sources: Sequence[int], eps: float, lam: float, alpha: float = ALPHA, beta: float = BETA,
                   nthreads: int = 0, keep_pi: bool = False, max_iters: int = 1_000_000):

@@ -17,6 +17,10 @@
  *                           row vector, max entry plus |U|(1-alpha)^T
  *   og_asrp                 Algorithm 4 (ASRP) in double precision
  *   og_app                  Algorithm 3 (APP) in double precision
+ *   og_forward_push         Algorithm 2 (FP): one node at a time, from a
+ *                           FIFO queue, in double precision
+ *   og_push_schedule        the four push schedules the paper compares in
+ *                           Exp-2: ASRP, APP, APP(S), APP(E)
  *   og_asrp_many            og_asrp over a list of sources, one per thread
  *
  * Dangling nodes (no edge, or no attribute) are allowed: the empty sums of
@@ -362,6 +366,157 @@ int og_app(const og_graph *g, double alpha, double beta, int32_t source, double 
     if (st) {
         st->iterations = it;
         st->switch_iteration = -1;
+        st->n_push = n_p;
+        st->max_residual = max_u(g, s.r_u);
+        st->sum_residual = sum_u(g, s.r_u);
+    }
+    free(thr);
+    state_free(&s);
+    return rc;
+}
+
+/* Algorithm 2 (FP).  One U node at a time: a FIFO queue holds the nodes
+ * whose residue is above r_max (|N(u)| + |A(u)|); a node taken from it (and
+ * still above) keeps alpha of its residue as reserve, clears its residue,
+ * and hands rho = (1 - alpha) r to its two-hop neighbours, through V with
+ * weight (1 - beta) w(u_i, v) w(v, u_j) / (d(u_i) d(v)) and through the
+ * attributes with weight beta w(u_i, a) w(u_j, a) / (s(u_i) t(a)).  A node
+ * that a push lifts above its threshold joins the queue unless it is in it.
+ * Stops when the queue is empty (no node above its threshold).
+ * st->iterations counts node pushes, st->n_push the two-hop entries visited
+ * (the per-push cost of Lemma 4).  hook, if given, runs after every push.
+ * Returns 0, 1 if max_pushes pushes did not empty the queue, or -1. */
+int og_forward_push(const og_graph *g, double alpha, double beta, int32_t source, double r_max, int64_t max_pushes,
+                    double *pi_out, double *r_out, og_stats *st, og_round_hook hook, void *user) {
+    if (!g || source < 0 || source >= g->n_u || !(r_max > 0)) return -1;
+    const int64_t n = g->n_u;
+    double *pi = (double *)calloc((size_t)n, sizeof(double));
+    double *r = (double *)calloc((size_t)n, sizeof(double));
+    double *thr = (double *)malloc((size_t)n * sizeof(double));
+    int32_t *queue = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    char *queued = (char *)calloc((size_t)n, 1);
+    if (!pi || !r || !thr || !queue || !queued) {
+        free(pi); free(r); free(thr); free(queue); free(queued);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        thr[i] = r_max * (double)((g->u2v.off[i + 1] - g->u2v.off[i]) + (g->u2a.off[i + 1] - g->u2a.off[i]));
+    r[source] = 1.0;
+    int64_t head = 0, count = 0, pushes = 0, visits = 0;
+    int rc = 0;
+    if (r[source] > thr[source]) { queue[0] = source; queued[source] = 1; count = 1; }
+    while (count > 0) {
+        const int32_t i = queue[head];
+        head = (head + 1) % n;
+        --count;
+        queued[i] = 0;
+        if (!(r[i] > thr[i])) continue;
+        if (pushes >= max_pushes) { rc = 1; break; }
+        pi[i] += alpha * r[i];
+        const double rho = (1.0 - alpha) * r[i];
+        r[i] = 0.0;
+        for (int64_t p = g->u2v.off[i]; p < g->u2v.off[i + 1]; ++p) {
+            const int32_t v = g->u2v.col[p];
+            const double c = (1.0 - beta) * g->u2v.w[p] / (g->d_u[i] * g->d_v[v]) * rho;
+            for (int64_t q = g->v2u.off[v]; q < g->v2u.off[v + 1]; ++q) {
+                const int32_t j = g->v2u.col[q];
+                r[j] += c * g->v2u.w[q];
+                if (r[j] > thr[j] && !queued[j]) { queue[(head + count) % n] = j; queued[j] = 1; ++count; }
+            }
+            visits += g->v2u.off[v + 1] - g->v2u.off[v];
+        }
+        for (int64_t p = g->u2a.off[i]; p < g->u2a.off[i + 1]; ++p) {
+            const int32_t a = g->u2a.col[p];
+            const double c = beta * g->u2a.w[p] / (g->s_u[i] * g->t_a[a]) * rho;
+            for (int64_t q = g->a2u.off[a]; q < g->a2u.off[a + 1]; ++q) {
+                const int32_t j = g->a2u.col[q];
+                r[j] += c * g->a2u.w[q];
+                if (r[j] > thr[j] && !queued[j]) { queue[(head + count) % n] = j; queued[j] = 1; ++count; }
+            }
+            visits += g->a2u.off[a + 1] - g->a2u.off[a];
+        }
+        ++pushes;
+        if (hook) hook(pushes, pi, r, user);
+    }
+    memcpy(pi_out, pi, (size_t)n * sizeof(double));
+    if (r_out) memcpy(r_out, r, (size_t)n * sizeof(double));
+    if (st) {
+        st->iterations = pushes;
+        st->switch_iteration = -1;
+        st->n_push = visits;
+        st->max_residual = max_u(g, r);
+        st->sum_residual = sum_u(g, r);
+    }
+    free(pi); free(r); free(thr); free(queue); free(queued);
+    return rc;
+}
+
+/* The push schedules of Exp-2, in the rounds of Algorithm 3:
+ *   0 ASRP    Algorithm 4 (= og_asrp).
+ *   1 APP     Algorithm 3 with r_max = eps / (|E| + |E_A|) (= og_app): push
+ *             u when r(u) > r_max (|N(u)| + |A(u)|), until no u does.
+ *   2 APP(S)  APP plus Algorithm 4's switch to synchronous rounds: after a
+ *             round of phase 1, once
+ *                 n_p >= 2 (|E| + |E_A|) log_{1/(1-alpha)}(max_u r(u) / thr(u))
+ *             (the number of synchronous rounds that bring every residue
+ *             under its own threshold, as Algorithm 4's budget does for
+ *             eps_f), rounds push every positive residue; the stop rule
+ *             stays APP's.
+ *   3 APP(E)  APP with Algorithm 4's threshold eps_f = eps / lambda for
+ *             every node and its stop rule max_u r(u) <= eps_f, no switch.
+ * Nodes with thr(u) = 0 (no edge and no attribute) count as above their
+ * threshold whenever r(u) > 0.  Returns 0, 1 (round cap), or -1. */
+int og_push_schedule(const og_graph *g, double alpha, double beta, int32_t source, double eps, double lambda,
+                     int32_t schedule, int64_t max_iters, double *pi_out, double *r_out, og_stats *st,
+                     og_round_hook hook, void *user) {
+    if (schedule == 0)
+        return og_asrp_hooked(g, alpha, beta, source, eps, lambda, max_iters, pi_out, r_out, st, hook, user);
+    if (!g || source < 0 || source >= g->n_u || !(eps > 0) || !(lambda > 0) || schedule < 0 || schedule > 3)
+        return -1;
+    push_state s;
+    if (state_alloc(g, &s)) { state_free(&s); return -1; }
+    const double m_total = (double)(g->m_e + g->m_a);
+    const double eps_f = eps / lambda, r_max = eps / m_total;
+    double *thr = (double *)malloc((size_t)g->n_u * sizeof(double));
+    for (int64_t i = 0; i < g->n_u; ++i)
+        thr[i] = r_max * (double)((g->u2v.off[i + 1] - g->u2v.off[i]) + (g->u2a.off[i + 1] - g->u2a.off[i]));
+    s.r_u[source] = 1.0;
+    int64_t n_p = 0, it = 0, switch_it = -1;
+    int phase = 1, rc = 0;
+    for (;;) {
+        /* Stop rule: APP's per-node thresholds, or eps_f for APP(E). */
+        double worst = 0.0;  /* max r(u) / thr(u), or max r(u) / eps_f */
+        int above = 0;
+        for (int64_t i = 0; i < g->n_u; ++i) {
+            const double t = schedule == 3 ? eps_f : thr[i];
+            if (s.r_u[i] > t) {
+                above = 1;
+                const double q = t > 0.0 ? s.r_u[i] / t : INFINITY;
+                worst = q > worst ? q : worst;
+            }
+        }
+        if (!above) break;
+        if (it >= max_iters) { rc = 1; break; }
+        if (schedule == 3) n_p += push_round(g, alpha, beta, &s, NULL, eps_f);
+        else n_p += push_round(g, alpha, beta, &s, phase == 1 ? thr : NULL, 0.0);
+        ++it;
+        if (hook) hook(it, s.pi, s.r_u, user);
+        if (schedule == 2 && phase == 1) {
+            worst = 0.0;
+            for (int64_t i = 0; i < g->n_u; ++i)
+                if (s.r_u[i] > thr[i]) {
+                    const double q = thr[i] > 0.0 ? s.r_u[i] / thr[i] : INFINITY;
+                    worst = q > worst ? q : worst;
+                }
+            const double t = worst > 1.0 ? log(worst) / log(1.0 / (1.0 - alpha)) : 0.0;
+            if ((double)n_p >= 2.0 * m_total * t) { phase = 2; switch_it = it; }
+        }
+    }
+    memcpy(pi_out, s.pi, (size_t)g->n_u * sizeof(double));
+    if (r_out) memcpy(r_out, s.r_u, (size_t)g->n_u * sizeof(double));
+    if (st) {
+        st->iterations = it;
+        st->switch_iteration = switch_it;
         st->n_push = n_p;
         st->max_residual = max_u(g, s.r_u);
         st->sum_residual = sum_u(g, s.r_u);

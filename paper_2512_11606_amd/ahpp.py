@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libahpp.so")
 
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CONVERGED = 0, -1, -2, -3, -4
 
-EXPORTED = ("ahpp_graph_load", "ahpp_graph_info", "ahpp_graph_free", "ahpp_query", "ahpp_query_batch", "ahpp_topk",
+EXPORTED = ("ahpp_graph_load", "ahpp_graph_info", "ahpp_graph_free", "ahpp_query", "ahpp_query_schedule",
+            "ahpp_query_batch", "ahpp_topk",
             "ahpp_server_create", "ahpp_server_free", "ahpp_server_submit", "ahpp_server_step",
             "ahpp_server_results", "ahpp_server_info", "ahpp_graph_tune", "ahpp_query_mc", "ahpp_profile_enable",
             "ahpp_profile_read", "ahpp_last_error")
@@ -98,6 +99,8 @@ def load_library(path: str = LIB_PATH):
     lib.ahpp_server_results.argtypes = [P, i32, P, P, P, P, P, P, P, P]
     lib.ahpp_server_info.restype = ctypes.c_int
     lib.ahpp_server_info.argtypes = [P, P, P, P, P]
+    lib.ahpp_query_schedule.restype = ctypes.c_int
+    lib.ahpp_query_schedule.argtypes = [P, i32, dbl, i32, i32, P, P, i32, P, P, P, P, P]
     lib.ahpp_query_mc.restype = ctypes.c_int
     lib.ahpp_query_mc.argtypes = [P, i32, i64, ctypes.c_uint64, P, i32, P, P, P, P, P]
     lib.ahpp_graph_tune.restype = ctypes.c_int
@@ -224,6 +227,29 @@ def ahpp_query(g: Graph, source: int, eps: float, k: int = 0, max_iters: int = 0
                                               ctypes.byref(st) if want_stats else None, _stream(g.device, stream)),
                     allow_not_converged)
     return QueryResult(pi, resid, ti, tv, tn, [st.as_dict()] if want_stats else [], status)
+
+
+SCHEDULE_ASRP, SCHEDULE_APP, SCHEDULE_APP_S, SCHEDULE_APP_E = 0, 1, 2, 3
+
+
+def ahpp_query_schedule(g: Graph, source: int, eps: float, schedule: int, k: int = 0, max_iters: int = 0,
+                        want_pi: bool = True, want_resid: bool = False, stream=None,
+                        allow_not_converged: bool = False) -> QueryResult:
+    """One query under an Exp-2 push schedule (0 ASRP, 1 APP, 2 APP(S), 3 APP(E))."""
+    import torch
+    dev = torch.device("cuda", g.device)
+    pi = torch.empty(g.n_u, dtype=torch.float32, device=dev) if want_pi else None
+    resid = torch.empty(g.n_u, dtype=torch.float32, device=dev) if want_resid else None
+    ti = torch.empty(max(k, 1), dtype=torch.int32, device=dev) if k > 0 else None
+    tv = torch.empty(max(k, 1), dtype=torch.float32, device=dev) if k > 0 else None
+    tn = torch.empty(1, dtype=torch.int32, device=dev) if k > 0 else None
+    st = Stats()
+    status = _check(load_library().ahpp_query_schedule(g._h, int(source), float(eps), int(schedule), int(max_iters),
+                                                       _dev_ptr(pi), _dev_ptr(resid), int(k), _dev_ptr(ti),
+                                                       _dev_ptr(tv), _dev_ptr(tn), ctypes.byref(st),
+                                                       _stream(g.device, stream)),
+                    allow_not_converged)
+    return QueryResult(pi, resid, ti, tv, tn, [st.as_dict()], status)
 
 
 def ahpp_query_batch(g: Graph, sources: Sequence[int], eps, k: int = 0, max_iters: int = 0, want_pi: bool = True,

@@ -67,8 +67,12 @@ struct Control {
     int32_t status;       // 0 running, 1 converged, 2 round cap reached
     int32_t max_iters;
     unsigned long long n_p;  // edge visits (Algorithm 4's n_p, every phase)
-    float last_max;       // max_i r(u, u_i) after the last completed round
-    float pad0;
+    float last_max;       // max_i r(u, u_i) after the last completed round (ratio form: see stop_ratio)
+    float r_max;          // Algorithm 3's residue threshold factor, eps / (|E| + |E_A|)
+    int32_t node_thr;     // 1: push u when r(u) > r_max deg(u) (APP; APP(S) before its switch)
+    int32_t stop_ratio;   // 1: stop when every r(u) <= r_max deg(u); last_max = max r(u) / (r_max deg(u))
+    int32_t sync_switch;  // 1: Algorithm 4's switch to threshold 0 (ASRP, APP(S))
+    int32_t pad0;
 };
 
 // Constants of the stop/switch rule of one graph.
@@ -205,6 +209,7 @@ struct Graph {
     DevCsr back;                    // rows V then attributes (n_v + a); cols U; weights
                                     // w(u,x) c_d(u) (V rows) or w(u,x) c_s(u) (attribute rows)
     float *inv_b = nullptr;         // 1/d(v) for V rows, 1/t(a) for attribute rows
+    float *deg_u = nullptr;         // |N(u)| + |A(u)| as float (Algorithm 3's thresholds; on first use)
     HotSet hot;                     // batched engine: hot back rows and the cold schedule
     McTables mc;                    // Monte Carlo walks
     int64_t dangling_u = 0;
@@ -260,7 +265,9 @@ void free_graph(Graph &g);
 // push.hip
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 void alloc_query_state(Graph &g);
-void single_query_init(Graph &g, int32_t source, float eps_f, int32_t max_iters, hipStream_t s);
+// schedule: 0 ASRP, 1 APP, 2 APP(S), 3 APP(E) (Exp-2); r_max = eps / (|E| + |E_A|).
+void single_query_init(Graph &g, int32_t source, float eps_f, int32_t max_iters, hipStream_t s, int32_t schedule = 0,
+                       float r_max = 0.0f);
 void single_query_round(Graph &g, hipStream_t s);
 void single_query_rounds(Graph &g, int n, hipStream_t s);   // as batch_rounds
 bool graphs_enabled(const Graph &g);

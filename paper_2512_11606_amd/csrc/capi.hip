@@ -446,17 +446,20 @@ void ahpp_graph_free(ahpp_graph_t *h) {
     delete h;
 }
 
-ahpp_status_t ahpp_query(ahpp_graph_t *h, int32_t source, double eps, int32_t max_iters, float *pi_out,
-                         float *resid_out, int32_t k, int32_t *topk_idx, float *topk_val, int32_t *topk_n,
-                         ahpp_stats_t *stats, void *hip_stream) {
+namespace {
+ahpp_status_t query_impl(const char *name, ahpp_graph_t *h, int32_t source, double eps, int32_t schedule,
+                         int32_t max_iters, float *pi_out, float *resid_out, int32_t k, int32_t *topk_idx,
+                         float *topk_val, int32_t *topk_n, ahpp_stats_t *stats, void *hip_stream) {
     g_last_error.clear();
-    if (!h) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query: NULL graph");
+    const std::string fn(name);
+    if (!h) return fail(AHPP_ERR_INVALID_ARG, fn + ": NULL graph");
     Graph &g = h->g;
-    if (source < 0 || source >= g.n_u) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query: source out of range");
-    if (!(eps > 0.0) || std::isinf(eps)) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query: eps must be > 0 and finite");
-    if (k < 0 || k > kMaxTopK) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query: k must be in [0, 2048]");
+    if (source < 0 || source >= g.n_u) return fail(AHPP_ERR_INVALID_ARG, fn + ": source out of range");
+    if (!(eps > 0.0) || std::isinf(eps)) return fail(AHPP_ERR_INVALID_ARG, fn + ": eps must be > 0 and finite");
+    if (k < 0 || k > kMaxTopK) return fail(AHPP_ERR_INVALID_ARG, fn + ": k must be in [0, 2048]");
     if (k > 0 && (!topk_idx || !topk_val || !topk_n))
-        return fail(AHPP_ERR_INVALID_ARG, "ahpp_query: top-k outputs required when k > 0");
+        return fail(AHPP_ERR_INVALID_ARG, fn + ": top-k outputs required when k > 0");
+    if (schedule < 0 || schedule > 3) return fail(AHPP_ERR_INVALID_ARG, fn + ": schedule must be 0..3");
     if (max_iters <= 0) max_iters = 100000;
     hipStream_t s = (hipStream_t)hip_stream;
     int32_t status = 0;
@@ -467,7 +470,7 @@ ahpp_status_t ahpp_query(ahpp_graph_t *h, int32_t source, double eps, int32_t ma
         check_hip(hipEventCreate(&e1), "event");
         check_hip(hipEventRecord(e0, s), "event");
         const float eps_f = (float)(eps / g.lambda);
-        single_query_init(g, source, eps_f, max_iters, s);
+        single_query_init(g, source, eps_f, max_iters, s, schedule, (float)(eps / (double)(g.m_e + g.m_a)));
         run_single(g, s);
         if (k > 0)
             topk_launch(g.q_pi, g.n_u, 0, 1, nullptr, source, k, topk_idx, topk_val, topk_n, g.tk_scratch, s);
@@ -499,8 +502,23 @@ ahpp_status_t ahpp_query(ahpp_graph_t *h, int32_t source, double eps, int32_t ma
     } catch (const Failure &f) {
         return fail(f.status, f.msg);
     }
-    if (status != 1) return fail(AHPP_ERR_NOT_CONVERGED, "ahpp_query: max_iters reached before max r <= eps/lambda");
+    if (status != 1) return fail(AHPP_ERR_NOT_CONVERGED, fn + ": max_iters reached before the stop rule held");
     return AHPP_OK;
+}
+}  // namespace
+
+ahpp_status_t ahpp_query(ahpp_graph_t *h, int32_t source, double eps, int32_t max_iters, float *pi_out,
+                         float *resid_out, int32_t k, int32_t *topk_idx, float *topk_val, int32_t *topk_n,
+                         ahpp_stats_t *stats, void *hip_stream) {
+    return query_impl("ahpp_query", h, source, eps, 0, max_iters, pi_out, resid_out, k, topk_idx, topk_val, topk_n,
+                      stats, hip_stream);
+}
+
+ahpp_status_t ahpp_query_schedule(ahpp_graph_t *h, int32_t source, double eps, int32_t schedule, int32_t max_iters,
+                                  float *pi_out, float *resid_out, int32_t k, int32_t *topk_idx, float *topk_val,
+                                  int32_t *topk_n, ahpp_stats_t *stats, void *hip_stream) {
+    return query_impl("ahpp_query_schedule", h, source, eps, schedule, max_iters, pi_out, resid_out, k, topk_idx,
+                      topk_val, topk_n, stats, hip_stream);
 }
 
 ahpp_status_t ahpp_query_mc(ahpp_graph_t *h, int32_t source, int64_t n_walks, uint64_t seed, float *pi_out,

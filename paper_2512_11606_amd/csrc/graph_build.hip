@@ -575,6 +575,8 @@ void free_graph(Graph &g) {
     for (void *p : {(void *)g.hot.rows, (void *)g.hot.len, (void *)g.hot.cold_items, (void *)g.hot.cold_split}) dfree(p);
     g.hot = HotSet{};
     free_batch_state(g.batch);
+    dfree(g.deg_u);
+    g.deg_u = nullptr;
     for (void *p : {(void *)g.inv_b, (void *)g.q_r, (void *)g.q_pi, (void *)g.q_z, (void *)g.q_ctl,
                     (void *)g.part_item, (void *)g.blk_max, (void *)g.blk_np, g.tk_scratch})
         dfree(p);

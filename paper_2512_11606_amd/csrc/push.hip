@@ -67,6 +67,7 @@ struct GatherArgs {
     float alpha;
     float *blk_f;               // per-workgroup max, nullable
     unsigned long long *blk_u;  // per-workgroup n_p, nullable
+    const float *deg;           // |N(u)| + |A(u)| of U nodes (Algorithm 3's thresholds), nullable
 };
 
 // Row epilogues: pre(row) is loaded early, with the row's entries;
@@ -93,18 +94,25 @@ struct Epi<kFwdAcc> {
     float *r;
     float *pi;
     float theta, alpha;
+    // Algorithm 3's per-node thresholds r_max deg(u): for pushing (node) and
+    // for the stop rule (ratio: the tracked max is r(u) / (r_max deg(u))).
+    bool node = false, ratio = false;
+    float r_max = 0.0f;
+    const float *deg = nullptr;
     unsigned long long np = 0;
     float mx = 0.0f;
     __device__ float2 pre(int64_t row) const { return make_float2(r[row], pi[row]); }
     __device__ void full(int64_t row, float s, float2 p, int64_t len) {
-        const bool pushed = p.x > theta;
+        const float t_u = (node || ratio) ? r_max * deg[row] : 0.0f;
+        const bool pushed = p.x > (node ? t_u : theta);
         if (pushed) {
             pi[row] = p.y + alpha * p.x;
             np += (unsigned long long)len;
         }
         const float v = (pushed ? 0.0f : p.x) + s;
         r[row] = v;
-        mx = fmaxf(mx, v);
+        if (ratio) mx = fmaxf(mx, t_u > 0.0f ? v / t_u : (v > 0.0f ? FLT_MAX : 0.0f));
+        else mx = fmaxf(mx, v);
     }
 };
 
@@ -125,9 +133,20 @@ struct Epi<kFwdLambda> {
 
 template <int kMode>
 __device__ __forceinline__ Epi<kMode> make_epi(const GatherArgs &a, float theta) {
-    if constexpr (kMode == kBack) return Epi<kBack>{a.y, a.inv_b};
-    else if constexpr (kMode == kFwdAcc) return Epi<kFwdAcc>{a.y, a.aux, theta, a.alpha};
-    else return Epi<kFwdLambda>{a.y, a.aux, a.alpha};
+    if constexpr (kMode == kBack) {
+        return Epi<kBack>{a.y, a.inv_b};
+    } else if constexpr (kMode == kFwdAcc) {
+        Epi<kFwdAcc> e{a.y, a.aux, theta, a.alpha};
+        if (a.ctl) {
+            e.node = a.ctl->node_thr != 0;
+            e.ratio = a.ctl->stop_ratio != 0;
+            e.r_max = a.ctl->r_max;
+            e.deg = a.deg;
+        }
+        return e;
+    } else {
+        return Epi<kFwdLambda>{a.y, a.aux, a.alpha};
+    }
 }
 
 // Writes the workgroup's max and n_p to its slots.
@@ -143,12 +162,15 @@ __device__ __forceinline__ void flush_stat(const GatherArgs &a, Epi<kMode> &e) {
     }
 }
 
+__device__ __forceinline__ float r_max_of(const GatherArgs &a) { return a.ctl ? a.ctl->r_max : 0.0f; }
+
 // Terms of entries e0 + lane + 64 k (k < kPerLane, < ne): w(e) * x(col(e)),
 // where the back gather keeps x only above the threshold.  All loads of a
 // lane are issued before any is used.
-template <bool kUnit, bool kThr>
+template <bool kUnit, bool kThr, bool kNode>
 __device__ __forceinline__ void load_terms(const CsrView &c, const float *__restrict__ x, int64_t e0, int ne,
-                                           float theta, float (&t)[kPerLane]) {
+                                           float theta, const float *__restrict__ deg, float r_max,
+                                           float (&t)[kPerLane]) {
     const int lane = threadIdx.x & (kWave - 1);
     int32_t ci[kPerLane];
     float wv[kPerLane];
@@ -164,10 +186,16 @@ __device__ __forceinline__ void load_terms(const CsrView &c, const float *__rest
             wv[k] = i < ne ? c.w[e0 + i] : 0.0f;
         }
     }
+    float th[kPerLane];
+#pragma unroll
+    for (int k = 0; k < kPerLane; ++k) {
+        th[k] = theta;
+        if constexpr (kNode) th[k] = ci[k] >= 0 ? r_max * deg[ci[k]] : 0.0f;
+    }
 #pragma unroll
     for (int k = 0; k < kPerLane; ++k) {
         float v = ci[k] >= 0 ? x[ci[k]] : 0.0f;
-        if constexpr (kThr) v = v > theta ? v : 0.0f;
+        if constexpr (kThr) v = v > th[k] ? v : 0.0f;
         t[k] = kUnit ? v : v * wv[k];
     }
 }
@@ -175,7 +203,7 @@ __device__ __forceinline__ void load_terms(const CsrView &c, const float *__rest
 // The wave's share of the schedule (grid-stride over items).  Every load of
 // an item that does not depend on another (entries, row bounds, epilogue
 // inputs, the next item's descriptor) is issued before the first wait.
-template <bool kUnit, int kMode>
+template <bool kUnit, int kMode, bool kNode>
 __device__ __forceinline__ void spmv_items(const GatherArgs &a, float theta, float *prod, Epi<kMode> &epi) {
     constexpr int kRowsPerLane = kMaxRowsPerItem / kWave;
     constexpr bool kThr = kMode == kBack;
@@ -205,7 +233,7 @@ __device__ __forceinline__ void spmv_items(const GatherArgs &a, float theta, flo
                     pre[q] = epi.pre(r0 + j);
                 }
             }
-            load_terms<kUnit, kThr>(c, a.x, e0, ne, theta, t);
+            load_terms<kUnit, kThr, kNode>(c, a.x, e0, ne, theta, a.deg, r_max_of(a), t);
 #pragma unroll
             for (int k = 0; k < kPerLane; ++k) {
                 const int i = lane + k * kWave;
@@ -231,7 +259,7 @@ __device__ __forceinline__ void spmv_items(const GatherArgs &a, float theta, flo
             const int ne = (int)(re - e0 < kItemEdges ? re - e0 : kItemEdges);
             const bool whole = re - rb <= kItemEdges;
             const float2 pre = whole ? epi.pre(row) : make_float2(0.0f, 0.0f);
-            load_terms<kUnit, kThr>(c, a.x, e0, ne, theta, t);
+            load_terms<kUnit, kThr, kNode>(c, a.x, e0, ne, theta, a.deg, r_max_of(a), t);
             float s = 0.0f;
 #pragma unroll
             for (int k = 0; k < kPerLane; ++k) s += t[k];
@@ -252,7 +280,12 @@ __global__ void __launch_bounds__(kBlock) k_gather(GatherArgs a) {
     if (a.ctl && a.ctl->done) return;
     const float theta = round_theta(a);
     Epi<kMode> epi = make_epi<kMode>(a, theta);
-    spmv_items<kUnit, kMode>(a, theta, prod[threadIdx.x >> 6], epi);
+    // The V/attribute gather thresholds each gathered U residue: by theta,
+    // or by Algorithm 3's r_max deg(u) while the query's schedule says so.
+    if (kMode == kBack && a.ctl && a.ctl->node_thr)
+        spmv_items<kUnit, kMode, kMode == kBack>(a, theta, prod[threadIdx.x >> 6], epi);
+    else
+        spmv_items<kUnit, kMode, false>(a, theta, prod[threadIdx.x >> 6], epi);
     flush_stat<kMode>(a, epi);
 }
 
@@ -280,19 +313,33 @@ __global__ void k_fill_f32(float *p, float v, int64_t n) {
         p[i] = v;
 }
 
-__global__ void k_query_init(Control *ctl, float *r, int32_t source, float eps_f, int32_t max_iters) {
+// Schedules of Exp-2: 0 ASRP (Algorithm 4), 1 APP (Algorithm 3, r_max =
+// eps / (|E| + |E_A|)), 2 APP(S) (APP with Algorithm 4's switch to
+// synchronous rounds), 3 APP(E) (APP with Algorithm 4's threshold eps_f and
+// stop rule, no switch).
+__global__ void k_query_init(Control *ctl, float *r, int32_t source, float eps_f, int32_t max_iters,
+                             int32_t schedule, float r_max, const float *deg) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const bool app_thr = schedule == 1 || schedule == 2;
+    const float deg_source = deg ? deg[source] : 0.0f;
     r[source] = 1.0f;
     ctl->theta = eps_f;
     ctl->eps_f = eps_f;
-    ctl->done = (1.0f > eps_f) ? 0 : 1;
+    ctl->r_max = r_max;
+    ctl->node_thr = app_thr ? 1 : 0;
+    ctl->stop_ratio = app_thr ? 1 : 0;
+    ctl->sync_switch = (schedule == 0 || schedule == 2) ? 1 : 0;
+    ctl->pad0 = 0;
+    // The unit residue at the source is above its threshold unless eps is that large.
+    const float t0 = app_thr ? r_max * deg_source : eps_f;
+    ctl->done = 1.0f > t0 ? 0 : 1;
     ctl->phase = 1;
     ctl->iter = 0;
     ctl->switch_iter = -1;
     ctl->status = ctl->done ? 1 : 0;
     ctl->max_iters = max_iters;
     ctl->n_p = 0;
-    ctl->last_max = 1.0f;
+    ctl->last_max = app_thr ? (t0 > 0.0f ? 1.0f / t0 : FLT_MAX) : 1.0f;
 }
 
 // Per-workgroup partial arrays read by k_control.
@@ -324,25 +371,33 @@ __global__ void __launch_bounds__(kControlThreads) k_control(Control *ctl, Parti
     if (threadIdx.x != 0) return;
     const unsigned long long n_p = ctl->n_p + np;
     const int iter = ctl->iter + 1;
-    const float eps_f = ctl->eps_f;
+    // Stop level: eps_f for max r (ASRP, APP(E)), or 1 for the largest
+    // r(u) / (r_max deg(u)) (APP, APP(S)).
+    const float level = ctl->stop_ratio ? 1.0f : ctl->eps_f;
     ctl->n_p = n_p;
     ctl->iter = iter;
     ctl->last_max = m;
-    if (!(m > eps_f)) {
+    if (!(m > level)) {
         ctl->done = 1;
         ctl->status = 1;
     } else if (iter >= ctl->max_iters) {
         ctl->done = 1;
         ctl->status = 2;
-    } else if (ctl->phase == 1) {
+    } else if (ctl->phase == 1 && ctl->sync_switch) {
         // Budget of Algorithm 4 with the round count of Theorem 1's proof.
-        const double t = (double)logf(m / eps_f) * (double)rule.inv_log;
+        const double t = (double)logf(m / level) * (double)rule.inv_log;
         if ((double)n_p >= rule.budget_scale * (t > 0.0 ? t : 0.0)) {
             ctl->phase = 2;
             ctl->theta = 0.0f;
+            ctl->node_thr = 0;
             ctl->switch_iter = iter;
         }
     }
+}
+
+__global__ void k_degrees(const int64_t *off, int64_t n, float *deg) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        deg[i] = (float)(off[i + 1] - off[i]);
 }
 
 __global__ void k_max_f32(const float *__restrict__ x, int64_t n, float *blk) {
@@ -432,24 +487,35 @@ void alloc_query_state(Graph &g) {
     g.blk_np = (unsigned long long *)dev_alloc(g, (size_t)4 * g.grid_cap * 8, "workgroup push counts");
 }
 
-void single_query_init(Graph &g, int32_t source, float eps_f, int32_t max_iters, hipStream_t s) {
+void single_query_init(Graph &g, int32_t source, float eps_f, int32_t max_iters, hipStream_t s, int32_t schedule,
+                       float r_max) {
+    if ((schedule == 1 || schedule == 2) && !g.deg_u) {
+        g.deg_u = (float *)dev_alloc(g, (size_t)std::max<int64_t>(g.n_u, 1) * 4, "node degrees");
+        if (g.single_round_graph) {  // captured with no degree array
+            (void)hipGraphExecDestroy(g.single_round_graph);
+            g.single_round_graph = nullptr;
+        }
+        hipLaunchKernelGGL(k_degrees, dim3(capped(g.n_u, kBlock, 4096)), dim3(kBlock), 0, s, g.fwd.off, g.n_u,
+                           g.deg_u);
+    }
     launch_fill_f32(g.q_r, 0.0f, g.n_u, s);
     launch_fill_f32(g.q_pi, 0.0f, g.n_u, s);
-    hipLaunchKernelGGL(k_query_init, dim3(1), dim3(64), 0, s, g.q_ctl, g.q_r, source, eps_f, max_iters);
+    hipLaunchKernelGGL(k_query_init, dim3(1), dim3(64), 0, s, g.q_ctl, g.q_r, source, eps_f, max_iters, schedule,
+                       r_max, (const float *)g.deg_u);
     check_hip(hipGetLastError(), "query init");
 }
 
 void single_query_round(Graph &g, hipStream_t s) {
     const Plan p = make_plan(g);
     GatherArgs back{view(g.back), g.q_r, g.q_z, nullptr, g.inv_b, g.part_item, g.q_ctl, 0.0f, (float)g.alpha,
-                    nullptr, g.blk_np};
+                    nullptr, g.blk_np, g.deg_u};
     // Algorithmic bytes: CSR entries (column, weight) and gathered residue per
     // entry, offsets and per-row state per row.
     const double wb = g.fwd.w ? 8.0 : 4.0;
     launch_gather<kBack>(g, false, back, p.back, p.back_fix, s, 0,
                          12.0 * g.back.nnz + 16.0 * g.back.n_rows);
     GatherArgs fwd{view(g.fwd), g.q_z, g.q_r, g.q_pi, nullptr, g.part_item, g.q_ctl, 0.0f, (float)g.alpha,
-                   g.blk_max, g.blk_np + 2 * g.grid_cap};
+                   g.blk_max, g.blk_np + 2 * g.grid_cap, g.deg_u};
     launch_gather<kFwdAcc>(g, g.unit, fwd, p.fwd, p.fwd_fix, s, 1, (wb + 4.0) * g.fwd.nnz + 24.0 * g.fwd.n_rows);
     Partials part{g.blk_max, (int)p.fwd, g.blk_max + g.grid_cap, (int)p.fwd_fix,
                   {g.blk_np, g.blk_np + g.grid_cap, g.blk_np + 2 * g.grid_cap, g.blk_np + 3 * g.grid_cap},

@@ -55,6 +55,8 @@ def test_argument_errors_need_no_device(lib):
     assert lib.ahpp_query(None, 0, 1e-6, 0, None, None, 0, None, None, None, None, None) == ahpp.ERR_INVALID_ARG
     assert lib.ahpp_topk(None, None, 5, -1, None, None, None, None) == ahpp.ERR_INVALID_ARG
     assert lib.ahpp_graph_tune(None, 0, None, None) == ahpp.ERR_INVALID_ARG
+    assert lib.ahpp_query_schedule(None, 0, 1e-6, 1, 0, None, None, 0, None, None, None, None,
+                                   None) == ahpp.ERR_INVALID_ARG
     assert lib.ahpp_query_mc(None, 0, 10, 1, None, 0, None, None, None, None, None) == ahpp.ERR_INVALID_ARG
     lib.ahpp_graph_free(None)
 

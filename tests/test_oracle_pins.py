@@ -289,6 +289,109 @@ def test_app_guarantee():
     assert (Pi[11] - pi_hat).max() <= eps
 
 
+SCHEDULES = (0, 1, 2, 3)  # ASRP, APP, APP(S), APP(E)
+
+
+def test_schedules_reduce_to_the_two_algorithms():
+    """Exp-2's schedule 0 is Algorithm 4 and schedule 1 is Algorithm 3 with
+    r_max = eps/(|E| + |E_A|): identical reserves, residues and counts."""
+    g, og, Pi = _small_dense_case()
+    lam = og.lambda_thm3()
+    eps = 1e-6
+    a = og.asrp(5, eps, lam)
+    b = og.push_schedule(5, eps, lam, 0)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+    c = og.app(5, eps / (og.m_e + og.m_a))
+    d = og.push_schedule(5, eps, lam, 1)
+    assert np.array_equal(c[0], d[0]) and np.array_equal(c[1], d[1])
+    assert c[2].iterations == d[2].iterations and c[2].n_push == d[2].n_push
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_schedule_invariant_and_bound(schedule):
+    """Every schedule keeps Lemma 2 after every round (it only reorders which
+    residues are pushed) and ends within eps of the exact row: APP(E) by
+    Theorem 2 (its stop rule is max r <= eps/lambda), APP and APP(S) by
+    Algorithm 3's residue threshold (they stop under it)."""
+    g, og, Pi = _small_dense_case()
+    lam = og.lambda_thm3()
+    eps = 1e-5
+    rounds = []
+
+    def hook(it, pi_hat, r):
+        rounds.append(it)
+        assert np.abs(Pi[9] - (pi_hat + r @ Pi)).max() < 1e-13
+
+    pi_hat, r, st, ok = og.push_schedule(9, eps, lam, schedule, hook=hook)
+    assert ok and rounds == list(range(1, st.iterations + 1))
+    diff = Pi[9] - pi_hat
+    assert diff.min() >= -1e-14 and diff.max() <= eps
+    deg = np.array([np.count_nonzero(g.edge_u == i) + np.count_nonzero(g.assoc_u == i) for i in range(g.n_u)])
+    if schedule == 3:
+        assert r.max() <= eps / lam
+    elif schedule in (1, 2):
+        assert (r <= eps / (og.m_e + og.m_a) * deg + 1e-300).all()
+
+
+def test_app_s_switches_and_app_never_does():
+    """APP(S) reaches the synchronous phase at a small eps; APP and APP(E)
+    have no phase switch."""
+    g, og, Pi = _small_dense_case()
+    lam = og.lambda_thm3()
+    assert og.push_schedule(3, 1e-9, lam, 2)[2].switch_iteration > 0
+    assert og.push_schedule(3, 1e-9, lam, 1)[2].switch_iteration == -1
+    assert og.push_schedule(3, 1e-9, lam, 3)[2].switch_iteration == -1
+
+
+def test_forward_push_first_push_is_one_step_of_P():
+    """Algorithm 2's first push from u leaves alpha at u and (1 - alpha) P[u]
+    as residues, with P taken from the dense solve: Pi = alpha (I - (1 -
+    alpha) P)^-1, so P = (I - alpha Pi^-1) / (1 - alpha)."""
+    g, og, Pi = _small_dense_case()
+    P = (np.eye(g.n_u) - O.ALPHA * np.linalg.inv(Pi)) / (1.0 - O.ALPHA)
+    seen = []
+
+    def hook(it, pi_hat, r):
+        if it == 1:
+            seen.append((pi_hat, r))
+
+    og.forward_push(4, 1e-9, max_pushes=1, hook=hook)
+    pi_hat, r = seen[0]
+    want = np.zeros(g.n_u); want[4] = O.ALPHA
+    assert np.abs(pi_hat - want).max() < 1e-15
+    assert np.abs(r - (1.0 - O.ALPHA) * P[4]).max() < 1e-12
+
+
+def test_forward_push_invariant_and_bound():
+    """FP keeps Lemma 2 after every single push and stops with every residue
+    under r_max (|N(u)| + |A(u)|), which with r_max = eps / (|E| + |E_A|)
+    puts it within eps of the exact row; the level-synchronous APP reaches
+    the same bound, so the two agree within eps."""
+    g, og, Pi = _small_dense_case()
+    eps = 1e-6
+    r_max = eps / (og.m_e + og.m_a)
+    pushes = []
+
+    def hook(it, pi_hat, r):
+        pushes.append(it)
+        assert np.abs(Pi[2] - (pi_hat + r @ Pi)).max() < 1e-13
+
+    pi_hat, r, st, ok = og.forward_push(2, r_max, max_pushes=200_000, hook=hook)
+    assert ok and pushes == list(range(1, st.iterations + 1)) and st.switch_iteration == -1
+    deg = np.array([np.count_nonzero(g.edge_u == i) + np.count_nonzero(g.assoc_u == i) for i in range(g.n_u)])
+    assert (r <= r_max * deg).all()
+    diff = Pi[2] - pi_hat
+    assert diff.min() >= -1e-14 and diff.max() <= eps
+    app = og.app(2, r_max)[0]
+    assert np.abs(app - pi_hat).max() <= eps
+
+
+def test_forward_push_push_cap():
+    g, og, Pi = _small_dense_case()
+    _, _, st, ok = og.forward_push(2, 1e-12, max_pushes=3)
+    assert not ok and st.iterations == 3
+
+
 # ---------------------------------------------------------------- lambda
 
 def test_lambda_bounds_column_sums(tiny_oracle, tiny_Pi):
