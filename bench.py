@@ -98,10 +98,9 @@ SERVE_EPS = (1e-5, 1e-6, 1e-7, 1e-8)
 PAPER_AMAZON_ASRP_MS = (158896.0, 188102.0)
 
 
-def amazon_leg(ahpp, synth, with_cpu, n=16):
+def amazon_leg(ahpp, synth, g, with_cpu, n=16):
     """Plain single-query latency on the Amazon-shaped graph at eps = 1e-6,
     beside the oracle's FP64 ASRP on one of the same queries (one thread)."""
-    g = synth.make_graph("amazon")
     dg = ahpp.load_graph(g, device=0)
     srcs = synth.degree_queries(g, n, 2005)
     ahpp.ahpp_query(dg, int(srcs[0]), 1e-6, k=50)
@@ -125,6 +124,41 @@ def amazon_leg(ahpp, synth, with_cpu, n=16):
         out["cpu_oracle_ms_one_thread"] = round((time.perf_counter() - t0) * 1e3, 1)
         out["cpu_oracle_rounds"] = st.iterations
         og.close()
+    return out
+
+
+SCALING_FRACS = (0.5, 0.6, 0.7, 0.8, 0.9, 1.0)
+
+
+def scaling_leg(ahpp, synth, g_full, n=4, eps=1e-6):
+    """Exp-3 on the Amazon-shaped graph: U nodes, or edges, sampled at 50% to
+    100% with their attributes; plain ASRP and APP at eps = 1e-6, k 50, mean
+    per query over n degree-weighted sources of each sampled graph (load and
+    lambda excluded)."""
+    out = {"workload": f"Amazon-shaped graph sampled by U nodes or by edges at 50-100% (with the kept nodes' "
+                       f"attributes); plain ASRP and APP at eps {eps:g}, k 50, {n} degree-weighted sources per graph",
+           "points": []}
+    for mode in ("nodes", "edges"):
+        for f in SCALING_FRACS:
+            if mode == "edges" and f == 1.0:
+                continue  # the whole graph, already measured under "nodes"
+            g = g_full if f == 1.0 else synth.sample_graph(g_full, f, mode, seed=3000)
+            dg = ahpp.load_graph(g, device=0)
+            srcs = synth.degree_queries(g, n, 2008).tolist()
+            pt = {"mode": mode, "frac": f, "n_u": g.n_u, "n_v": g.n_v, "m_e": g.m_e, "m_a": g.m_a,
+                  "lambda": round(dg.lam, 1)}
+            for sch, name in ((0, "ASRP"), (1, "APP")):
+                ahpp.ahpp_query_schedule(dg, srcs[0], eps, sch, k=50, want_pi=False)
+                lat, rounds = [], []
+                for s in srcs:
+                    a = time.perf_counter()
+                    r = ahpp.ahpp_query_schedule(dg, s, eps, sch, k=50, want_pi=False)
+                    lat.append((time.perf_counter() - a) * 1e3)
+                    rounds.append(r.stats[0]["iters"])
+                pt[name] = {"ms_mean": round(sum(lat) / n, 2), "rounds_mean": round(sum(rounds) / n, 1)}
+            dg.free()
+            del g
+            out["points"].append(pt)
     return out
 
 
@@ -220,7 +254,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     ap.add_argument("--no-tiny", action="store_true", help="skip the small-graph latency run")
     ap.add_argument("--no-tune", action="store_true", help="keep the untuned batch schedule")
-    ap.add_argument("--no-amazon", action="store_true", help="skip the Amazon-shaped latency run")
+    ap.add_argument("--no-amazon", action="store_true", help="skip the Amazon-shaped latency and scaling runs")
+    ap.add_argument("--no-scaling", action="store_true", help="skip the 50-100%% sampled-graph scaling run")
     ap.add_argument("--no-mc", action="store_true", help="skip the Monte Carlo run")
     ap.add_argument("--no-schedules", action="store_true", help="skip the ASRP / APP / APP(S) / APP(E) comparison")
     ap.add_argument("--serve-queries", type=int, default=800)
@@ -291,7 +326,12 @@ def main():
     plain_tiny = None if args.no_tiny else tiny_leg(ahpp, synth)
     monte_carlo = None if args.no_mc else mc_leg(ahpp, synth, g, dg)
     schedules = None if args.no_schedules else schedule_leg(ahpp, synth, g, dg)
-    amazon = None if args.no_amazon else amazon_leg(ahpp, synth, not args.no_cpu)
+    amazon = scaling = None
+    if not args.no_amazon:
+        g_am = synth.make_graph("amazon")
+        amazon = amazon_leg(ahpp, synth, g_am, not args.no_cpu)
+        scaling = None if args.no_scaling else scaling_leg(ahpp, synth, g_am)
+        del g_am
 
     dom_kind = max(prof, key=lambda kk: prof[kk]["ms"])
     dom = prof[dom_kind]
@@ -334,6 +374,7 @@ def main():
         "amazon_shaped": amazon,
         "monte_carlo": monte_carlo,
         "push_schedules": schedules,
+        "amazon_scaling": scaling,
         "roofline": roofline,
         "kernels": {kname: {"launches": prof[kk]["launches"],
                             "avg_ms": round(prof[kk]["ms"] / max(prof[kk]["launches"], 1), 4),

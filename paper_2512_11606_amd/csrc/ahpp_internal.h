@@ -201,7 +201,9 @@ struct Graph {
     int device = 0;
     int n_cu = 256;
     int grid_cap = 2048;            // workgroups of the gather kernels
-    int64_t n_u = 0, n_v = 0, n_a = 0, m_e = 0, m_a = 0;
+    // n_v counts the V nodes that have an edge: the device structures number
+    // only those (n_v_input is the caller's count).
+    int64_t n_u = 0, n_v = 0, n_a = 0, m_e = 0, m_a = 0, n_v_input = 0;
     double alpha = 0.15, beta = 0.35, lambda = 1.0;
     int32_t lambda_iters = 0;
     bool unit = false;              // every raw weight is 1 (the fwd CSR stores none)

@@ -418,7 +418,7 @@ ahpp_status_t ahpp_graph_info(const ahpp_graph_t *h, ahpp_graph_info_t *info) {
     if (!h || !info) return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_info: NULL argument");
     const Graph &g = h->g;
     info->n_u = g.n_u;
-    info->n_v = g.n_v;
+    info->n_v = g.n_v_input;
     info->n_attr = g.n_a;
     info->n_edges = g.m_e;
     info->n_assoc = g.m_a;

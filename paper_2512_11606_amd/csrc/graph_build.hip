@@ -61,6 +61,18 @@ __global__ void k_make_entries(const int32_t *row_ids, const int32_t *col_ids, c
     }
 }
 
+// V nodes with at least one edge: flag[v] = 1 (equal values, plain stores).
+__global__ void k_mark_v(const int32_t *ev, int64_t m, unsigned long long *flag) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        flag[ev[i]] = 1ull;
+}
+
+// V ids of the edges, renumbered by the exclusive scan of those flags.
+__global__ void k_remap_v(int32_t *ev, int64_t m, const unsigned long long *map) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        ev[i] = (int32_t)map[ev[i]];
+}
+
 // ---------------------------------------------------------------- scan
 
 __global__ void k_scan_partials(const unsigned long long *in, int64_t n, unsigned long long *part) {
@@ -501,6 +513,30 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
         throw Failure{-1, msg};
     }
     g.unit = !(flags & 16u);
+
+    // A V node without an edge never receives residue and no U row reads
+    // it, so the device numbers only the V nodes that have an edge (in
+    // their input order); a round then spends nothing on the others.
+    g.n_v_input = g.n_v;
+    if (m_e == 0) {
+        g.n_v = 0;
+    } else {
+        unsigned long long *vmap = nullptr, *part = nullptr;
+        const int64_t n = g.n_v + 1;  // one more entry: the scan leaves the count there
+        check_hip(hipMalloc(&vmap, (size_t)n * 8), "V renumbering");
+        check_hip(hipMalloc(&part, (size_t)((n + kScanTile - 1) / kScanTile + 1) * 8), "V renumbering");
+        check_hip(hipMemsetAsync(vmap, 0, (size_t)n * 8, s), "V renumbering");
+        hipLaunchKernelGGL(k_mark_v, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_ev, m_e, vmap);
+        exclusive_scan_u64(vmap, vmap, n, part, s);
+        hipLaunchKernelGGL(k_remap_v, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_ev, m_e, vmap);
+        check_hip(hipGetLastError(), "V renumbering");
+        unsigned long long n_kept = 0;
+        check_hip(hipMemcpyAsync(&n_kept, vmap + g.n_v, 8, hipMemcpyDeviceToHost, s), "V renumbering");
+        check_hip(hipStreamSynchronize(s), "V renumbering");
+        dfree(vmap);
+        dfree(part);
+        g.n_v = (int64_t)n_kept;
+    }
 
     // Entries of both CSRs.
     uint32_t *key = nullptr;

@@ -325,6 +325,56 @@ def make_custom(n_u: int, n_v: int, m_e: int, n_attr: int, attrs_per_node: int, 
     return make_graph(cfg, native=native)
 
 
+def _compact(keep: np.ndarray) -> np.ndarray:
+    """New ids of the kept entries of a mask (-1 for dropped ones)."""
+    ids = np.cumsum(keep, dtype=np.int64) - 1
+    return np.where(keep, ids, -1).astype(np.int64)
+
+
+def _smallest_keys(keys: np.ndarray, k: int) -> np.ndarray:
+    """Mask of the k entries with the smallest keys (64-bit random keys, so
+    ties do not occur in practice)."""
+    keep = np.zeros(keys.size, dtype=bool)
+    if k >= keys.size:
+        keep[:] = True
+    elif k > 0:
+        keep[np.argpartition(keys, k)[:k]] = True
+    return keep
+
+
+def sample_graph(g: AttributedBipartiteGraph, frac: float, mode: str, seed: int) -> AttributedBipartiteGraph:
+    """A sampled subgraph in the manner of Exp-3's scalability graphs.
+
+    mode "nodes": a seeded fraction of U (exactly round(frac |U|) nodes) with
+    all their edges and attribute associations.  mode "edges": a seeded
+    fraction of the edges (exactly round(frac |E|)), and the U nodes they
+    touch with all their attribute associations.  In both, V nodes left
+    without an edge are dropped and U / V ids are renumbered in their old
+    order; the attribute ids and their count stay as they are."""
+    if not (0.0 < frac <= 1.0):
+        raise ValueError("frac must be in (0, 1]")
+    if mode == "nodes":
+        keep_u = _smallest_keys(CounterRNG(seed, "sample_u").bits(g.n_u), int(round(frac * g.n_u)))
+        keep_e = keep_u[g.edge_u]
+    elif mode == "edges":
+        keep_e = _smallest_keys(CounterRNG(seed, "sample_e").bits(g.m_e), int(round(frac * g.m_e)))
+        keep_u = np.zeros(g.n_u, dtype=bool)
+        keep_u[g.edge_u[keep_e]] = True
+    else:
+        raise ValueError("mode must be 'nodes' or 'edges'")
+    keep_v = np.zeros(g.n_v, dtype=bool)
+    keep_v[g.edge_v[keep_e]] = True
+    new_u, new_v = _compact(keep_u), _compact(keep_v)
+    keep_a = keep_u[g.assoc_u]
+    n_u, n_v = int(keep_u.sum()), int(keep_v.sum())
+    cfg = dataclasses.replace(g.config, name=f"{g.config.name}-{mode}{frac:g}", n_u=n_u, n_v=n_v,
+                              m_e=int(keep_e.sum()))
+    return AttributedBipartiteGraph(cfg, n_u, n_v, g.n_attr,
+                                    new_u[g.edge_u[keep_e]].astype(np.int32), new_v[g.edge_v[keep_e]].astype(np.int32),
+                                    g.edge_w[keep_e], new_u[g.assoc_u[keep_a]].astype(np.int32),
+                                    g.assoc_a[keep_a].copy(), g.assoc_w[keep_a])
+
+
 def uniform_queries(g: AttributedBipartiteGraph, n: int, seed: int, distinct: bool = True) -> np.ndarray:
     """n source nodes drawn uniformly over U."""
     rng = CounterRNG(seed, "q_uniform")

@@ -98,6 +98,49 @@ def test_weighted_graph_against_power_series(torch_cuda, ahpp):
     dg.free()
 
 
+@pytest.mark.parametrize("mode", ["nodes", "edges"])
+def test_sampled_graph_against_power_series(torch_cuda, ahpp, mode):
+    """Exp-3's sampled graphs (attributes without members, renumbered ids):
+    plain and batched queries against the exact series."""
+    g = synth.sample_graph(synth.make_custom(6000, 2500, 60000, 300, 8, seed=516, unit_weights=False), 0.6, mode,
+                           seed=7)
+    og = O.OracleGraph.from_graph(g)
+    dg = ahpp.load_graph(g)
+    srcs = synth.degree_queries(g, 3, 98)
+    _say("sampled graph", mode, g.n_u, g.n_v, g.m_e, g.m_a)
+    batch = ahpp.ahpp_query_batch(dg, srcs, 1e-6, k=30)
+    for q, s in enumerate(srcs.tolist()):
+        exact, _ = og.power_series(s)
+        chk = _check(torch_cuda, ahpp.ahpp_query(dg, s, 1e-6, k=30, want_resid=True), exact, 1e-6, k=30, source=s)
+        assert chk.ok, (mode, s, chk.detail)
+        chk = O.check_query(exact, batch.pi[q].cpu().numpy().astype(np.float64), 1e-6, k=30, source=s,
+                            topk_ids=batch.topk_idx[q, : int(batch.topk_n[q].item())].cpu().numpy())
+        assert chk.ok, (mode, s, "batched", chk.detail)
+    og.close()
+    dg.free()
+
+
+def test_edgeless_v_nodes_change_nothing(torch_cuda, ahpp):
+    """V nodes without an edge (before, between and after the others) are
+    dropped at load: the scores equal, bit for bit, those of the same graph
+    numbered without them, and the graph info keeps the caller's V count."""
+    import dataclasses
+    g = synth.make_custom(3000, 1200, 25000, 100, 5, seed=517, unit_weights=False)
+    spread = dataclasses.replace(g, n_v=3 * g.n_v + 2, edge_v=(3 * g.edge_v + 1).astype(np.int32))
+    a, b = ahpp.load_graph(g), ahpp.load_graph(spread)
+    assert b.info["n_v"] == 3 * g.n_v + 2 and a.lam == b.lam
+    srcs = synth.degree_queries(g, 3, 97)
+    for s in srcs.tolist():
+        ra, rb = ahpp.ahpp_query(a, s, 1e-7, k=20), ahpp.ahpp_query(b, s, 1e-7, k=20)
+        assert torch_cuda.equal(ra.pi, rb.pi) and torch_cuda.equal(ra.topk_idx, rb.topk_idx)
+    ba, bb = ahpp.ahpp_query_batch(a, srcs, 1e-7, k=20), ahpp.ahpp_query_batch(b, srcs, 1e-7, k=20)
+    assert torch_cuda.equal(ba.pi, bb.pi)
+    exact, _ = O.OracleGraph.from_graph(spread).power_series(int(srcs[0]))
+    assert _check(torch_cuda, ahpp.ahpp_query(b, int(srcs[0]), 1e-7, want_resid=True), exact, 1e-7).ok
+    a.free()
+    b.free()
+
+
 @pytest.mark.parametrize("beta", [0.0, 1.0])
 def test_pure_structure_and_pure_attribute_walks(torch_cuda, ahpp, tiny_graph, beta):
     og = O.OracleGraph.from_graph(tiny_graph)

@@ -1,6 +1,9 @@
 """Seeded input generators: determinism and the structure the recipe promises."""
 
+import dataclasses
+
 import numpy as np
+import pytest
 
 from paper_2512_11606_amd import synth
 
@@ -86,3 +89,37 @@ def test_native_generator_needs_the_library_when_forced(monkeypatch):
     import pytest
     with pytest.raises(RuntimeError):
         synth.make_graph("tiny", native=True)
+
+
+@pytest.mark.parametrize("mode", ["nodes", "edges"])
+def test_sample_graph_keeps_whole_nodes(mode):
+    """Exp-3's sampled graphs: the kept edges and attribute rows are exactly
+    those of the kept nodes, ids are renumbered in order, sizes are exact.
+    Edge and attribute weights are set to distinct values here, so they
+    identify each entry of the original graph."""
+    g = synth.make_custom(300, 150, 2500, 30, 3, seed=77, unit_weights=False, native=False)
+    g = dataclasses.replace(g, edge_w=(1.0 + np.arange(g.m_e)).astype(np.float32),
+                            assoc_w=(1.0 + np.arange(g.m_a)).astype(np.float32))
+    s = synth.sample_graph(g, 0.6, mode, seed=5)
+    e_of = {float(w): i for i, w in enumerate(g.edge_w)}
+    a_of = {float(w): i for i, w in enumerate(g.assoc_w)}
+    src = np.array([e_of[float(w)] for w in s.edge_w])
+    u_map, v_map = {}, {}
+    for new_u, new_v, i in zip(s.edge_u, s.edge_v, src):
+        assert u_map.setdefault(int(g.edge_u[i]), int(new_u)) == new_u
+        assert v_map.setdefault(int(g.edge_v[i]), int(new_v)) == new_v
+    kept_u = np.array(sorted(u_map))
+    assert [u_map[u] for u in kept_u] == list(range(kept_u.size)) == list(range(s.n_u))
+    assert [v_map[v] for v in sorted(v_map)] == list(range(s.n_v))
+    if mode == "nodes":
+        assert s.n_u == round(0.6 * g.n_u)  # every U node of the generator has an edge
+        want = np.flatnonzero(np.isin(g.edge_u, kept_u))
+        assert np.array_equal(np.sort(src), want)
+    else:
+        assert s.m_e == round(0.6 * g.m_e)
+    # Attribute rows: all of the kept U nodes', no others, attribute ids unchanged.
+    asrc = np.array([a_of[float(w)] for w in s.assoc_w])
+    assert np.array_equal(np.sort(asrc), np.flatnonzero(np.isin(g.assoc_u, kept_u)))
+    for new_u, a, i in zip(s.assoc_u, s.assoc_a, asrc):
+        assert u_map[int(g.assoc_u[i])] == new_u and g.assoc_a[i] == a
+    assert s.n_attr == g.n_attr
