@@ -143,8 +143,8 @@ struct HotSet {
     int32_t *len = nullptr;              // [n] entries of that row
     DevCsr list;                         // rows g * n_u + u: (hot index, back weight) of u's hot
                                          // rows h with h % kHotWaves == g, by h
-    int32_t n_chunks = 0;                // fixed U chunks of the streaming pass
-    int64_t chunk_rows = 0;
+    int32_t n_chunks = 0;                // fixed U chunks of the streaming pass:
+    int64_t *chunk_start = nullptr;      //   chunk c = rows [start[c], start[c+1]) (device)
     WorkItem *cold_items = nullptr;      // back schedule without the hot rows
     int64_t n_cold_items = 0;
     SplitRow *cold_split = nullptr;
@@ -204,6 +204,11 @@ struct Graph {
     // n_v counts the V nodes that have an edge: the device structures number
     // only those (n_v_input is the caller's count).
     int64_t n_u = 0, n_v = 0, n_a = 0, m_e = 0, m_a = 0, n_v_input = 0;
+    // U numbering of the device structures: u_new[input id] = device id
+    // (on the device and in host memory).  Outputs are gathered back to
+    // input order through it.
+    int32_t *u_new = nullptr;
+    std::vector<int32_t> u_new_host;
     double alpha = 0.15, beta = 0.35, lambda = 1.0;
     int32_t lambda_iters = 0;
     bool unit = false;              // every raw weight is 1 (the fwd CSR stores none)
@@ -219,6 +224,7 @@ struct Graph {
     double load_ms = 0, lambda_ms = 0;
     // Single-query state (allocated at load).
     float *q_r = nullptr, *q_pi = nullptr, *q_z = nullptr;
+    float *q_out = nullptr;         // a U vector in input order (top-k input when no output is given)
     Control *q_ctl = nullptr;
     float *part_item = nullptr;            // chunk partial sums, max(n_items) slots
     float *blk_max = nullptr;              // per-workgroup maxima, 2 * grid_cap
@@ -257,7 +263,8 @@ void ensure_mc_tables(Graph &g, hipStream_t s);
 void free_mc_tables(McTables &t);
 McResult mc_walks(Graph &g, int32_t source, int64_t n_walks, uint64_t seed, int max_steps, unsigned *count,
                   hipStream_t s);
-void mc_scores(const unsigned *count, int64_t n, int64_t n_walks, float *out, hipStream_t s);
+// Walk counts (device numbering) to scores in input order.
+void mc_scores(const unsigned *count, const int32_t *u_new, int64_t n, int64_t n_walks, float *out, hipStream_t s);
 
 // graph_build.hip
 void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew, const int32_t *au,
@@ -267,6 +274,8 @@ void free_graph(Graph &g);
 // push.hip
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 void alloc_query_state(Graph &g);
+// out[i] = in[u_new[i]]: a U vector of the device numbering in input order.
+void to_input_order(const Graph &g, const float *in, float *out, hipStream_t s);
 // schedule: 0 ASRP, 1 APP, 2 APP(S), 3 APP(E) (Exp-2); r_max = eps / (|E| + |E_A|).
 void single_query_init(Graph &g, int32_t source, float eps_f, int32_t max_iters, hipStream_t s, int32_t schedule = 0,
                        float r_max = 0.0f);

@@ -468,7 +468,8 @@ struct HotArgs {
     float *part;            // chunk partials (tile 0), [n_chunks][n_hot][kTileQ]
     int64_t part_stride;
     const TileCtl *ctl;
-    int64_t n_u, chunk_rows;
+    const int64_t *chunk_start;  // chunk c = U rows [chunk_start[c], chunk_start[c + 1])
+    int64_t n_u;
     int n_hot, n_chunks;
 };
 
@@ -518,8 +519,8 @@ __global__ void __launch_bounds__(kHotThreads) kb_hot(HotArgs a, const int64_t *
     float *pt = a.part + t * a.part_stride;
     const int64_t *off = hot_off + grp * a.n_u;
     const int c = blockIdx.x;
-    const int64_t u0 = (int64_t)c * a.chunk_rows;
-    const int64_t u1 = u0 + a.chunk_rows < a.n_u ? u0 + a.chunk_rows : a.n_u;
+    const int64_t u0 = a.chunk_start[c];
+    const int64_t u1 = a.chunk_start[c + 1];
     float acc[kHotPerWave][kHotCols];
 #pragma unroll
     for (int k = 0; k < kHotPerWave; ++k)
@@ -745,24 +746,27 @@ __global__ void kb_admit(TileCtl *ctl, float *r, int64_t tile_u, const AdmitReq 
     if (run) tc.all_done = 0;
 }
 
-// Reads a 64-row block of one tile into LDS: tile[i][q] = pi[u0 + i][q].
-__device__ __forceinline__ void load_row_block(const float *pi, int64_t u0, int64_t n_u, float (*tile)[kTileQ + 1]) {
+// Reads a 64-row block of one tile into LDS, rows in input order:
+// tile[i][q] = pi[u_new[u0 + i]][q].
+__device__ __forceinline__ void load_row_block(const float *pi, const int32_t *u_new, int64_t u0, int64_t n_u,
+                                               float (*tile)[kTileQ + 1]) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int i = wid; i < kWave; i += kWavesPerBlock) {
         const int64_t u = u0 + i;
-        const QV v = u < n_u ? qv_load(pi + u * kTileQ + lane * kVec) : qv_zero();
+        const QV v = u < n_u ? qv_load(pi + (int64_t)u_new[u] * kTileQ + lane * kVec) : qv_zero();
 #pragma unroll
         for (int j = 0; j < kVec; ++j) tile[i][lane * kVec + j] = v.v[j];
     }
     __syncthreads();
 }
 
-// out[j * n_u + u] = pi[u][lanes[j]] for the j < n_sel selected queries of one tile.
-__global__ void __launch_bounds__(kBlock) kb_gather_lanes(const float *pi, int64_t n_u, const int32_t *lanes, int n_sel,
-                                                          float *out) {
+// out[j * n_u + u] = pi[u_new[u]][lanes[j]] for the j < n_sel selected
+// queries of one tile (u in input order).
+__global__ void __launch_bounds__(kBlock) kb_gather_lanes(const float *pi, const int32_t *u_new, int64_t n_u,
+                                                          const int32_t *lanes, int n_sel, float *out) {
     __shared__ float tile[kWave][kTileQ + 1];
     const int64_t u0 = (int64_t)blockIdx.x * kWave;
-    load_row_block(pi, u0, n_u, tile);
+    load_row_block(pi, u_new, u0, n_u, tile);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int j = wid; j < n_sel; j += kWavesPerBlock) {
         const int q = lanes[j];
@@ -771,13 +775,14 @@ __global__ void __launch_bounds__(kBlock) kb_gather_lanes(const float *pi, int64
     }
 }
 
-// out[(t * kTileQ + q) * n_u + u] = pi[t][u][q] for rows t * kTileQ + q < n_rows_valid.
-__global__ void __launch_bounds__(kBlock) kb_transpose(const float *pi, int64_t pi_stride, int64_t n_u, float *out,
-                                                       int64_t n_rows_valid) {
+// out[(t * kTileQ + q) * n_u + u] = pi[t][u_new[u]][q] for rows t * kTileQ + q
+// < n_rows_valid (u in input order).
+__global__ void __launch_bounds__(kBlock) kb_transpose(const float *pi, int64_t pi_stride, const int32_t *u_new,
+                                                       int64_t n_u, float *out, int64_t n_rows_valid) {
     __shared__ float tile[kWave][kTileQ + 1];
     const int t = blockIdx.y;
     const int64_t u0 = (int64_t)blockIdx.x * kWave;
-    load_row_block(pi + t * pi_stride, u0, n_u, tile);
+    load_row_block(pi + t * pi_stride, u_new, u0, n_u, tile);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int q = wid; q < kTileQ; q += kWavesPerBlock) {
         const int64_t row = (int64_t)t * kTileQ + q;
@@ -913,7 +918,7 @@ void batch_init(Graph &g, BatchState &b, int nt, const int32_t *sources, const f
     hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.pi, (int64_t)nt * tile_u);
     std::vector<InitQuery> hq((size_t)nt * kTileQ);
     const int64_t n_valid = std::min<int64_t>(n_q, (int64_t)nt * kTileQ);
-    for (int64_t i = 0; i < n_valid; ++i) hq[i] = InitQuery{sources[i], eps_f[i]};
+    for (int64_t i = 0; i < n_valid; ++i) hq[i] = InitQuery{g.u_new_host[(size_t)sources[i]], eps_f[i]};
     InitQuery *dq = nullptr;
     check_hip(hipMallocAsync((void **)&dq, hq.size() * sizeof(InitQuery), s), "batch init");
     check_hip(hipMemcpyAsync(dq, hq.data(), hq.size() * sizeof(InitQuery), hipMemcpyHostToDevice, s), "batch init");
@@ -958,7 +963,7 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
     }
     if (hs.n > 0) {
         const int64_t tile_hot = (int64_t)hs.n_chunks * hs.n * kTileQ;
-        HotArgs ha{b.r, tile_u, b.hot_part, tile_hot, b.ctl, g.n_u, hs.chunk_rows, hs.n, hs.n_chunks};
+        HotArgs ha{b.r, tile_u, b.hot_part, tile_hot, b.ctl, hs.chunk_start, g.n_u, hs.n, hs.n_chunks};
         HotReduceArgs ra{b.hot_part, tile_hot, hs.rows, hs.len, g.inv_b, b.z, tile_z, b.blk_np + 4 * slot, su, b.ctl,
                          hs.n, hs.n_chunks};
         profiled(g.prof, 4, hot_bytes, s, [&] {
@@ -1065,7 +1070,7 @@ void batch_rounds(Graph &g, BatchState &b, int nt, int n, hipStream_t s) {
 void batch_scores(Graph &g, BatchState &b, int nt, int64_t n_rows, float *out, hipStream_t s) {
     const int64_t tile_u = g.n_u * kTileQ;
     hipLaunchKernelGGL(kb_transpose, dim3((unsigned)((g.n_u + kWave - 1) / kWave), nt), dim3(kBlock), 0, s, b.pi,
-                       tile_u, g.n_u, out, std::min<int64_t>(n_rows, (int64_t)nt * kTileQ));
+                       tile_u, (const int32_t *)g.u_new, g.n_u, out, std::min<int64_t>(n_rows, (int64_t)nt * kTileQ));
     check_hip(hipGetLastError(), "batch scores launch");
 }
 
@@ -1103,7 +1108,10 @@ void batch_admit(Graph &g, BatchState &b, const std::vector<AdmitReq> &reqs, int
     check_hip(hipMallocAsync((void **)&dm, masks.size() * 8, s), "admit");
     check_hip(hipMallocAsync((void **)&dr, reqs.size() * sizeof(AdmitReq), s), "admit");
     check_hip(hipMemcpyAsync(dm, masks.data(), masks.size() * 8, hipMemcpyHostToDevice, s), "admit");
-    check_hip(hipMemcpyAsync(dr, reqs.data(), reqs.size() * sizeof(AdmitReq), hipMemcpyHostToDevice, s), "admit");
+    std::vector<AdmitReq> dev_reqs(reqs);  // sources in the device numbering
+    for (AdmitReq &a : dev_reqs) a.source = g.u_new_host[(size_t)a.source];
+    check_hip(hipMemcpyAsync(dr, dev_reqs.data(), dev_reqs.size() * sizeof(AdmitReq), hipMemcpyHostToDevice, s),
+              "admit");
     const unsigned gx = capped(g.n_u, kWavesPerBlock * 16, 1024);
     hipLaunchKernelGGL(kb_clear_lanes, dim3(gx, b.tiles), dim3(kBlock), 0, s, b.r, b.pi, tile_u, g.n_u, dm);
     hipLaunchKernelGGL(kb_admit, dim3(capped((int64_t)reqs.size(), kBlock, 1 << 20)), dim3(kBlock), 0, s, b.ctl, b.r,
@@ -1118,7 +1126,7 @@ void batch_lanes_out(Graph &g, BatchState &b, int tile, const int32_t *d_lanes, 
     if (n_sel <= 0) return;
     const int64_t tile_u = g.n_u * kTileQ;
     hipLaunchKernelGGL(kb_gather_lanes, dim3((unsigned)((g.n_u + kWave - 1) / kWave)), dim3(kBlock), 0, s,
-                       b.pi + tile * tile_u, g.n_u, d_lanes, n_sel, out);
+                       b.pi + tile * tile_u, (const int32_t *)g.u_new, g.n_u, d_lanes, n_sel, out);
     check_hip(hipGetLastError(), "lanes out launch");
 }
 

@@ -470,13 +470,14 @@ ahpp_status_t query_impl(const char *name, ahpp_graph_t *h, int32_t source, doub
         check_hip(hipEventCreate(&e1), "event");
         check_hip(hipEventRecord(e0, s), "event");
         const float eps_f = (float)(eps / g.lambda);
-        single_query_init(g, source, eps_f, max_iters, s, schedule, (float)(eps / (double)(g.m_e + g.m_a)));
+        single_query_init(g, g.u_new_host[(size_t)source], eps_f, max_iters, s, schedule,
+                          (float)(eps / (double)(g.m_e + g.m_a)));
         run_single(g, s);
-        if (k > 0)
-            topk_launch(g.q_pi, g.n_u, 0, 1, nullptr, source, k, topk_idx, topk_val, topk_n, g.tk_scratch, s);
-        if (pi_out) check_hip(hipMemcpyAsync(pi_out, g.q_pi, (size_t)g.n_u * 4, hipMemcpyDeviceToDevice, s), "pi out");
-        if (resid_out)
-            check_hip(hipMemcpyAsync(resid_out, g.q_r, (size_t)g.n_u * 4, hipMemcpyDeviceToDevice, s), "resid out");
+        // Scores in input order (the top-k breaks ties by input id).
+        float *scores = pi_out ? pi_out : (k > 0 ? g.q_out : nullptr);
+        if (scores) to_input_order(g, g.q_pi, scores, s);
+        if (k > 0) topk_launch(scores, g.n_u, 0, 1, nullptr, source, k, topk_idx, topk_val, topk_n, g.tk_scratch, s);
+        if (resid_out) to_input_order(g, g.q_r, resid_out, s);
         check_hip(hipEventRecord(e1, s), "event");
         Control ctl;
         check_hip(hipMemcpyAsync(&ctl, g.q_ctl, sizeof(Control), hipMemcpyDeviceToHost, s), "control D2H");
@@ -542,9 +543,9 @@ ahpp_status_t ahpp_query_mc(ahpp_graph_t *h, int32_t source, int64_t n_walks, ui
         check_hip(hipEventRecord(e0, s), "event");
         // Counts in the residue buffer, scores in the reserve buffer.
         unsigned *count = reinterpret_cast<unsigned *>(g.q_r);
-        const McResult r = mc_walks(g, source, n_walks, seed, 4096, count, s);
+        const McResult r = mc_walks(g, g.u_new_host[(size_t)source], n_walks, seed, 4096, count, s);
         float *scores = pi_out ? pi_out : g.q_pi;
-        mc_scores(count, g.n_u, n_walks, scores, s);
+        mc_scores(count, g.u_new, g.n_u, n_walks, scores, s);
         if (k > 0) topk_launch(scores, g.n_u, 0, 1, nullptr, source, k, topk_idx, topk_val, topk_n, g.tk_scratch, s);
         check_hip(hipEventRecord(e1, s), "event");
         check_hip(hipStreamSynchronize(s), "walks");

@@ -18,6 +18,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
+#include <utility>
 
 #include "ahpp_internal.h"
 #include "dev_util.h"
@@ -61,16 +63,41 @@ __global__ void k_make_entries(const int32_t *row_ids, const int32_t *col_ids, c
     }
 }
 
-// V nodes with at least one edge: flag[v] = 1 (equal values, plain stores).
-__global__ void k_mark_v(const int32_t *ev, int64_t m, unsigned long long *flag) {
+// ---------------------------------------------------------------- numbering
+
+// cnt[ids[i]] += 1 (integer atomics: the counts do not depend on the order).
+__global__ void k_count_ids(const int32_t *ids, int64_t m, unsigned *cnt) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-        flag[ev[i]] = 1ull;
+        atomicAdd(&cnt[ids[i]], 1u);
 }
 
-// V ids of the edges, renumbered by the exclusive scan of those flags.
-__global__ void k_remap_v(int32_t *ev, int64_t m, const unsigned long long *map) {
+// Sort keys of ids 0..n-1: larger counts first; the stable sort keeps id
+// order among equal counts.
+__global__ void k_rank_keys(const unsigned *cnt, int64_t n, uint32_t *key, int32_t *id) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        key[i] = ~cnt[i];
+        id[i] = (int32_t)i;
+    }
+}
+
+// new_of[order[j]] = j.
+__global__ void k_invert(const int32_t *order, int64_t n, int32_t *new_of) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        new_of[order[j]] = (int32_t)j;
+}
+
+// ids[i] = new_of[ids[i]].
+__global__ void k_remap(int32_t *ids, int64_t m, const int32_t *new_of) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-        ev[i] = (int32_t)map[ev[i]];
+        ids[i] = new_of[ids[i]];
+}
+
+// Zero-count entries: how many of the n counts are nonzero.
+__global__ void k_count_nonzero(const unsigned *cnt, int64_t n, unsigned long long *out) {
+    unsigned long long c = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c += cnt[i] != 0u;
+    if (c) atomicAdd(out, c);
 }
 
 // ---------------------------------------------------------------- scan
@@ -193,7 +220,7 @@ __global__ void k_radix_scatter(const uint32_t *key, const int32_t *col, const f
         int64_t pos = (int64_t)dig_off[(int64_t)d * n_tiles + blockIdx.x] + local;
         key_o[pos] = k[j];
         col_o[pos] = col[base + j];
-        w_o[pos] = w[base + j];
+        if (w) w_o[pos] = w[base + j];
     }
 }
 
@@ -324,6 +351,48 @@ void build_items(const std::vector<int64_t> &off, std::vector<WorkItem> &items, 
 }
 
 // Sorts (key, col, w) by key (stable) and builds offsets + schedule.
+// Stable LSD radix sort (4-bit digits) of m (key, col[, w]) triples by key,
+// keys below 2^key_bits; the sorted triples end in the same buffers.
+void sort_by_key(uint32_t *key, int32_t *col, float *w, int64_t m, int key_bits, hipStream_t s) {
+    if (m <= 0) return;
+    uint32_t *key2 = nullptr;
+    int32_t *col2 = nullptr;
+    float *w2 = nullptr;
+    unsigned long long *cnt = nullptr, *part = nullptr;
+    const int64_t n_tiles = (m + kSortTile - 1) / kSortTile;
+    const int64_t n_cnt = 16 * n_tiles;
+    check_hip(hipMalloc(&key2, (size_t)m * 4), "sort buffer");
+    check_hip(hipMalloc(&col2, (size_t)m * 4), "sort buffer");
+    if (w) check_hip(hipMalloc(&w2, (size_t)m * 4), "sort buffer");
+    check_hip(hipMalloc(&cnt, (size_t)n_cnt * 8), "sort counts");
+    check_hip(hipMalloc(&part, (size_t)((n_cnt + kScanTile - 1) / kScanTile + 1) * 8), "scan partials");
+    const int passes = (key_bits + 3) / 4;
+    uint32_t *ki = key, *ko = key2;
+    int32_t *ci = col, *co = col2;
+    float *wi = w, *wo = w2;
+    for (int p = 0; p < passes; ++p) {
+        hipLaunchKernelGGL(k_radix_count, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, ki, m, 4 * p, cnt, n_tiles);
+        exclusive_scan_u64(cnt, cnt, n_cnt, part, s);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, ki, ci, wi, m, 4 * p, cnt,
+                           n_tiles, ko, co, wo);
+        check_hip(hipGetLastError(), "radix sort launch");
+        std::swap(ki, ko);
+        std::swap(ci, co);
+        std::swap(wi, wo);
+    }
+    if (ki != key) {
+        check_hip(hipMemcpyAsync(key, ki, (size_t)m * 4, hipMemcpyDeviceToDevice, s), "sort copy");
+        check_hip(hipMemcpyAsync(col, ci, (size_t)m * 4, hipMemcpyDeviceToDevice, s), "sort copy");
+        if (w) check_hip(hipMemcpyAsync(w, wi, (size_t)m * 4, hipMemcpyDeviceToDevice, s), "sort copy");
+    }
+    check_hip(hipStreamSynchronize(s), "sort");
+    dfree(key2);
+    dfree(col2);
+    dfree(w2);
+    dfree(cnt);
+    dfree(part);
+}
+
 void build_csr(Graph &g, DevCsr &c, int64_t n_rows, uint32_t *key, int32_t *col, float *w, int64_t m, bool keep_w,
                hipStream_t s) {
     c.n_rows = n_rows;
@@ -332,40 +401,11 @@ void build_csr(Graph &g, DevCsr &c, int64_t n_rows, uint32_t *key, int32_t *col,
     c.col = (int32_t *)dev_alloc(g, (size_t)std::max<int64_t>(m, 1) * sizeof(int32_t), "csr columns");
     if (keep_w) c.w = (float *)dev_alloc(g, (size_t)std::max<int64_t>(m, 1) * sizeof(float), "csr weights");
     if (m > 0) {
-        uint32_t *key2 = nullptr;
-        int32_t *col2 = nullptr;
-        float *w2 = nullptr;
-        unsigned long long *cnt = nullptr, *part = nullptr;
-        const int64_t n_tiles = (m + kSortTile - 1) / kSortTile;
-        const int64_t n_cnt = 16 * n_tiles;
-        check_hip(hipMalloc(&key2, (size_t)m * 4), "sort buffer");
-        check_hip(hipMalloc(&col2, (size_t)m * 4), "sort buffer");
-        check_hip(hipMalloc(&w2, (size_t)m * 4), "sort buffer");
-        check_hip(hipMalloc(&cnt, (size_t)n_cnt * 8), "sort counts");
-        check_hip(hipMalloc(&part, (size_t)((n_cnt + kScanTile - 1) / kScanTile + 1) * 8), "scan partials");
-        const int passes = (bits_for(n_rows) + 3) / 4;
-        uint32_t *ki = key, *ko = key2;
-        int32_t *ci = col, *co = col2;
-        float *wi = w, *wo = w2;
-        for (int p = 0; p < passes; ++p) {
-            hipLaunchKernelGGL(k_radix_count, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, ki, m, 4 * p, cnt, n_tiles);
-            exclusive_scan_u64(cnt, cnt, n_cnt, part, s);
-            hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, ki, ci, wi, m, 4 * p, cnt,
-                               n_tiles, ko, co, wo);
-            check_hip(hipGetLastError(), "radix sort launch");
-            std::swap(ki, ko);
-            std::swap(ci, co);
-            std::swap(wi, wo);
-        }
-        hipLaunchKernelGGL(k_offsets, dim3(grid_for(m + 1)), dim3(kBlock), 0, s, ki, m, n_rows, c.off);
-        check_hip(hipMemcpyAsync(c.col, ci, (size_t)m * 4, hipMemcpyDeviceToDevice, s), "csr copy");
-        if (c.w) check_hip(hipMemcpyAsync(c.w, wi, (size_t)m * 4, hipMemcpyDeviceToDevice, s), "csr copy");
+        sort_by_key(key, col, w, m, bits_for(n_rows), s);
+        hipLaunchKernelGGL(k_offsets, dim3(grid_for(m + 1)), dim3(kBlock), 0, s, key, m, n_rows, c.off);
+        check_hip(hipMemcpyAsync(c.col, col, (size_t)m * 4, hipMemcpyDeviceToDevice, s), "csr copy");
+        if (c.w) check_hip(hipMemcpyAsync(c.w, w, (size_t)m * 4, hipMemcpyDeviceToDevice, s), "csr copy");
         check_hip(hipStreamSynchronize(s), "csr build");
-        dfree(key2);
-        dfree(col2);
-        dfree(w2);
-        dfree(cnt);
-        dfree(part);
     } else {
         check_hip(hipMemsetAsync(c.off, 0, (size_t)(n_rows + 1) * sizeof(int64_t), s), "csr offsets");
     }
@@ -388,6 +428,75 @@ void build_csr(Graph &g, DevCsr &c, int64_t n_rows, uint32_t *key, int32_t *col,
         check_hip(hipMemcpyAsync(c.split, split.data(), split.size() * sizeof(SplitRow), hipMemcpyHostToDevice, s),
                   "split H2D");
     check_hip(hipStreamSynchronize(s), "schedule upload");
+}
+
+// Numbers the ids 0..n-1 of one node set by descending reference count
+// (the entries of `lists` that name them), ties by id: new_of[id] = its
+// number.  Returns how many ids have a nonzero count (they come first).
+int64_t number_by_count(Graph &g, int64_t n, std::initializer_list<std::pair<const int32_t *, int64_t>> lists,
+                        int32_t *new_of, hipStream_t s) {
+    if (n <= 0) return 0;
+    unsigned *cnt = nullptr;
+    uint32_t *key = nullptr;
+    int32_t *order = nullptr;
+    unsigned long long *nz = nullptr;
+    check_hip(hipMalloc(&cnt, (size_t)n * 4), "numbering");
+    check_hip(hipMalloc(&key, (size_t)n * 4), "numbering");
+    check_hip(hipMalloc(&order, (size_t)n * 4), "numbering");
+    check_hip(hipMalloc(&nz, 8), "numbering");
+    check_hip(hipMemsetAsync(cnt, 0, (size_t)n * 4, s), "numbering");
+    check_hip(hipMemsetAsync(nz, 0, 8, s), "numbering");
+    for (const auto &l : lists)
+        if (l.second > 0)
+            hipLaunchKernelGGL(k_count_ids, dim3(grid_for(l.second)), dim3(kBlock), 0, s, l.first, l.second, cnt);
+    hipLaunchKernelGGL(k_count_nonzero, dim3(grid_for(n)), dim3(kBlock), 0, s, cnt, n, nz);
+    hipLaunchKernelGGL(k_rank_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, cnt, n, key, order);
+    check_hip(hipGetLastError(), "numbering launch");
+    sort_by_key(key, order, nullptr, n, 32, s);
+    hipLaunchKernelGGL(k_invert, dim3(grid_for(n)), dim3(kBlock), 0, s, order, n, new_of);
+    check_hip(hipGetLastError(), "numbering launch");
+    unsigned long long n_nz = 0;
+    check_hip(hipMemcpyAsync(&n_nz, nz, 8, hipMemcpyDeviceToHost, s), "numbering");
+    check_hip(hipStreamSynchronize(s), "numbering");
+    dfree(cnt);
+    dfree(key);
+    dfree(order);
+    dfree(nz);
+    (void)g;
+    return (int64_t)n_nz;
+}
+
+// Streaming-pass cost of U row u (a row of the device numbering): its
+// entries in the kHotWaves hot lists plus one per wave; cost[n_u] = 0.
+__global__ void k_hot_cost(const int64_t *off, int64_t n_u, unsigned long long *cost) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u <= n_u; u += (int64_t)gridDim.x * blockDim.x) {
+        unsigned long long c = 0;
+        if (u < n_u) {
+            c = kHotWaves;
+            for (int g = 0; g < kHotWaves; ++g) c += (unsigned long long)(off[g * n_u + u + 1] - off[g * n_u + u]);
+        }
+        cost[u] = c;
+    }
+}
+
+// start[c] = the first row whose exclusive cost prefix reaches c / n_chunks
+// of the total (start[0] = 0, start[n_chunks] = n_u; non-decreasing).
+__global__ void k_chunk_bounds(const unsigned long long *prefix, int64_t n_u, int n_chunks, int64_t *start) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > n_chunks) return;
+    if (c == n_chunks) {
+        start[c] = n_u;
+        return;
+    }
+    const unsigned long long target = prefix[n_u] / (unsigned long long)n_chunks * (unsigned long long)c +
+                                      prefix[n_u] % (unsigned long long)n_chunks * (unsigned long long)c /
+                                          (unsigned long long)n_chunks;
+    int64_t lo = 0, hi = n_u;  // smallest u in [0, n_u] with prefix[u] >= target
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (prefix[mid] >= target) hi = mid; else lo = mid + 1;
+    }
+    start[c] = lo;
 }
 
 // Picks the hot rows of the back CSR (the kHotMax longest rows with at least
@@ -461,10 +570,27 @@ void build_hot(Graph &g, hipStream_t s) {
     h.cold_nnz = g.back.nnz - m;
     h.cold_rows = n_rows - n;
     // Fixed chunking (a property of the graph and the device, not of the
-    // launch), so the sum order never depends on how many tiles run.
+    // launch), so the sum order never depends on how many tiles run.  The
+    // chunks are balanced by cost: a row's hot-list entries plus one per
+    // wave (its staging), since the device numbering puts the rows with the
+    // most entries first.
     h.n_chunks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(g.n_cu, g.n_u));
-    h.chunk_rows = (g.n_u + h.n_chunks - 1) / h.n_chunks;
-    check_hip(hipStreamSynchronize(s), "hot rows");
+    h.chunk_start = (int64_t *)dev_alloc(g, (size_t)(h.n_chunks + 1) * 8, "hot chunks");
+    {
+        unsigned long long *cost = nullptr, *part = nullptr;
+        const int64_t n = g.n_u + 1;
+        check_hip(hipMalloc(&cost, (size_t)n * 8), "hot chunks");
+        check_hip(hipMalloc(&part, (size_t)((n + kScanTile - 1) / kScanTile + 1) * 8), "hot chunks");
+        hipLaunchKernelGGL(k_hot_cost, dim3(grid_for(n)), dim3(kBlock), 0, s, (const int64_t *)h.list.off, g.n_u,
+                           cost);
+        exclusive_scan_u64(cost, cost, n, part, s);
+        hipLaunchKernelGGL(k_chunk_bounds, dim3(grid_for(h.n_chunks + 1)), dim3(kBlock), 0, s, cost, g.n_u,
+                           h.n_chunks, h.chunk_start);
+        check_hip(hipGetLastError(), "hot chunks launch");
+        check_hip(hipStreamSynchronize(s), "hot chunks");
+        dfree(cost);
+        dfree(part);
+    }
 }
 
 }  // namespace
@@ -514,29 +640,36 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
     }
     g.unit = !(flags & 16u);
 
-    // A V node without an edge never receives residue and no U row reads
-    // it, so the device numbers only the V nodes that have an edge (in
-    // their input order); a round then spends nothing on the others.
+    // Device numbering of U, V and the attributes: by descending number of
+    // CSR entries that name the node, ties by input id.  The random gathers
+    // of a round then find the most referenced nodes packed together (more
+    // of them per cache line).  A V node without an edge is never read and
+    // never receives residue: it gets no row (it sorts last and is cut).
+    // Only U numbers leave the library, and they are mapped back on the way
+    // out (u_new, u_new_host).
     g.n_v_input = g.n_v;
-    if (m_e == 0) {
-        g.n_v = 0;
-    } else {
-        unsigned long long *vmap = nullptr, *part = nullptr;
-        const int64_t n = g.n_v + 1;  // one more entry: the scan leaves the count there
-        check_hip(hipMalloc(&vmap, (size_t)n * 8), "V renumbering");
-        check_hip(hipMalloc(&part, (size_t)((n + kScanTile - 1) / kScanTile + 1) * 8), "V renumbering");
-        check_hip(hipMemsetAsync(vmap, 0, (size_t)n * 8, s), "V renumbering");
-        hipLaunchKernelGGL(k_mark_v, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_ev, m_e, vmap);
-        exclusive_scan_u64(vmap, vmap, n, part, s);
-        hipLaunchKernelGGL(k_remap_v, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_ev, m_e, vmap);
-        check_hip(hipGetLastError(), "V renumbering");
-        unsigned long long n_kept = 0;
-        check_hip(hipMemcpyAsync(&n_kept, vmap + g.n_v, 8, hipMemcpyDeviceToHost, s), "V renumbering");
-        check_hip(hipStreamSynchronize(s), "V renumbering");
-        dfree(vmap);
-        dfree(part);
-        g.n_v = (int64_t)n_kept;
+    g.u_new = (int32_t *)dev_alloc(g, (size_t)g.n_u * 4, "U numbering");
+    number_by_count(g, g.n_u, {{d_eu, m_e}, {d_au, m_a}}, g.u_new, s);
+    int32_t *v_new = nullptr, *a_new = nullptr;
+    if (g.n_v > 0) check_hip(hipMalloc(&v_new, (size_t)g.n_v * 4), "V numbering");
+    if (g.n_a > 0) check_hip(hipMalloc(&a_new, (size_t)g.n_a * 4), "attribute numbering");
+    const int64_t v_rows = number_by_count(g, g.n_v, {{d_ev, m_e}}, v_new, s);
+    number_by_count(g, g.n_a, {{d_aa, m_a}}, a_new, s);
+    if (m_e > 0) {
+        hipLaunchKernelGGL(k_remap, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_eu, m_e, g.u_new);
+        hipLaunchKernelGGL(k_remap, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_ev, m_e, v_new);
     }
+    if (m_a > 0) {
+        hipLaunchKernelGGL(k_remap, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_au, m_a, g.u_new);
+        hipLaunchKernelGGL(k_remap, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_aa, m_a, a_new);
+    }
+    check_hip(hipGetLastError(), "numbering launch");
+    g.u_new_host.resize((size_t)g.n_u);
+    check_hip(hipMemcpyAsync(g.u_new_host.data(), g.u_new, (size_t)g.n_u * 4, hipMemcpyDeviceToHost, s), "numbering");
+    check_hip(hipStreamSynchronize(s), "numbering");
+    dfree(v_new);
+    dfree(a_new);
+    g.n_v = v_rows;
 
     // Entries of both CSRs.
     uint32_t *key = nullptr;
@@ -608,11 +741,18 @@ void free_graph(Graph &g) {
     free_csr(g.back);
     free_csr(g.hot.list);
     free_mc_tables(g.mc);
-    for (void *p : {(void *)g.hot.rows, (void *)g.hot.len, (void *)g.hot.cold_items, (void *)g.hot.cold_split}) dfree(p);
+    for (void *p : {(void *)g.hot.rows, (void *)g.hot.len, (void *)g.hot.cold_items, (void *)g.hot.cold_split,
+                    (void *)g.hot.chunk_start})
+        dfree(p);
     g.hot = HotSet{};
     free_batch_state(g.batch);
     dfree(g.deg_u);
     g.deg_u = nullptr;
+    dfree(g.u_new);
+    g.u_new = nullptr;
+    g.u_new_host.clear();
+    dfree(g.q_out);
+    g.q_out = nullptr;
     for (void *p : {(void *)g.inv_b, (void *)g.q_r, (void *)g.q_pi, (void *)g.q_z, (void *)g.q_ctl,
                     (void *)g.part_item, (void *)g.blk_max, (void *)g.blk_np, g.tk_scratch})
         dfree(p);

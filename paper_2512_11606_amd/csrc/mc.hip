@@ -176,9 +176,10 @@ __global__ void k_zero_u32(unsigned *p, int64_t n) {
         p[i] = 0u;
 }
 
-__global__ void k_scores(const unsigned *count, int64_t n, double inv_walks, float *out) {
+// Scores in input order: out[i] = count[u_new[i]] / walks.
+__global__ void k_scores(const unsigned *count, const int32_t *u_new, int64_t n, double inv_walks, float *out) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = (float)((double)count[i] * inv_walks);
+        out[i] = (float)((double)count[u_new[i]] * inv_walks);
 }
 
 unsigned grid_waves(int64_t rows) {
@@ -218,8 +219,8 @@ void ensure_mc_tables(Graph &g, hipStream_t s) {
     }
 }
 
-void mc_scores(const unsigned *count, int64_t n, int64_t n_walks, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_scores, dim3(1024), dim3(kBlock), 0, s, count, n, 1.0 / (double)n_walks, out);
+void mc_scores(const unsigned *count, const int32_t *u_new, int64_t n, int64_t n_walks, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_scores, dim3(1024), dim3(kBlock), 0, s, count, u_new, n, 1.0 / (double)n_walks, out);
     check_hip(hipGetLastError(), "walk scores");
 }
 

@@ -468,7 +468,20 @@ void launch_gather(Graph &g, bool unit, const GatherArgs &a, unsigned grid, unsi
     }
 }
 
+__global__ void k_to_input_order(const float *__restrict__ in, const int32_t *__restrict__ u_new, int64_t n,
+                                 float *__restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[u_new[i]];
+}
+
 }  // namespace
+
+void to_input_order(const Graph &g, const float *in, float *out, hipStream_t s) {
+    if (g.n_u <= 0) return;
+    hipLaunchKernelGGL(k_to_input_order, dim3(capped(g.n_u, kBlock, 4096)), dim3(kBlock), 0, s, in,
+                       (const int32_t *)g.u_new, g.n_u, out);
+    check_hip(hipGetLastError(), "input order");
+}
 
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
@@ -480,6 +493,7 @@ void alloc_query_state(Graph &g) {
     auto n1 = [](int64_t n) { return (size_t)(n > 0 ? n : 1); };
     g.q_r = (float *)dev_alloc(g, n1(g.n_u) * 4, "query residues");
     g.q_pi = (float *)dev_alloc(g, n1(g.n_u) * 4, "query reserves");
+    g.q_out = (float *)dev_alloc(g, n1(g.n_u) * 4, "query scores in input order");
     g.q_z = (float *)dev_alloc(g, n1(g.n_v + g.n_a) * 4, "query V/attribute residues");
     g.q_ctl = (Control *)dev_alloc(g, sizeof(Control), "query control");
     g.part_item = (float *)dev_alloc(g, n1(std::max(g.fwd.n_items, g.back.n_items)) * 4, "chunk partials");
