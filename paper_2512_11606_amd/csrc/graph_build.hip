@@ -393,14 +393,21 @@ void sort_by_key(uint32_t *key, int32_t *col, float *w, int64_t m, int key_bits,
     dfree(part);
 }
 
+// CSR of m entries (row key, column, weight).  With n_cols > 0 the entries of
+// every row are put in column order (a stable sort by column first), which
+// under the device numbering puts a row's most referenced columns side by
+// side for the lanes of one load; otherwise rows keep the input order.
 void build_csr(Graph &g, DevCsr &c, int64_t n_rows, uint32_t *key, int32_t *col, float *w, int64_t m, bool keep_w,
-               hipStream_t s) {
+               hipStream_t s, int64_t n_cols = 0) {
     c.n_rows = n_rows;
     c.nnz = m;
     c.off = (int64_t *)dev_alloc(g, (size_t)(n_rows + 1) * sizeof(int64_t), "csr offsets");
     c.col = (int32_t *)dev_alloc(g, (size_t)std::max<int64_t>(m, 1) * sizeof(int32_t), "csr columns");
     if (keep_w) c.w = (float *)dev_alloc(g, (size_t)std::max<int64_t>(m, 1) * sizeof(float), "csr weights");
     if (m > 0) {
+        // Columns are non-negative, so their bits order like unsigned keys.
+        if (n_cols > 0)
+            sort_by_key(reinterpret_cast<uint32_t *>(col), reinterpret_cast<int32_t *>(key), w, m, bits_for(n_cols), s);
         sort_by_key(key, col, w, m, bits_for(n_rows), s);
         hipLaunchKernelGGL(k_offsets, dim3(grid_for(m + 1)), dim3(kBlock), 0, s, key, m, n_rows, c.off);
         check_hip(hipMemcpyAsync(c.col, col, (size_t)m * 4, hipMemcpyDeviceToDevice, s), "csr copy");
@@ -687,7 +694,7 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
     if (m_a > 0)
         hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_au, d_aa, d_aw, m_a,
                            (int32_t)g.n_v, 0u, key + m_e, col + m_e, w + m_e);
-    build_csr(g, g.fwd, g.n_u, key, col, w, m, !g.unit, s);
+    build_csr(g, g.fwd, g.n_u, key, col, w, m, !g.unit, s, g.n_v + g.n_a);
     // back: rows V then attributes (row n_v + a); columns are U ids.
     if (m_e > 0)
         hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_ev, d_eu, d_ew, m_e, 0, 0u, key,
@@ -695,7 +702,7 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
     if (m_a > 0)
         hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_aa, d_au, d_aw, m_a, 0,
                            (uint32_t)g.n_v, key + m_e, col + m_e, w + m_e);
-    build_csr(g, g.back, g.n_v + g.n_a, key, col, w, m, true, s);
+    build_csr(g, g.back, g.n_v + g.n_a, key, col, w, m, true, s, g.n_u);
     dfree(key);
     dfree(col);
     dfree(w);
