@@ -129,22 +129,28 @@ struct BatchState {
 
 // Hot rows: the longest rows of the back CSR (the most popular attributes
 // and V nodes).  The batched engine does not gather them entry by entry: it
-// streams each tile's U rows once, in fixed chunks, and accumulates every hot
-// row's sum in LDS (one thread per query column, so each accumulator has one
-// writer and the sum order is fixed), then adds the chunk partials in chunk
-// order.
-constexpr int kHotMax = 128;             // at most this many (LDS: kHotMax x kTileQ floats)
+// streams each tile's U rows once, in fixed chunks of blocks of
+// kHotBlockRows rows, and adds every hot row's terms in registers (wave g
+// owns the hot rows h with h % kHotWaves == g, one lane per four query
+// columns, so each accumulator has one writer and the sum order is fixed),
+// then adds the chunk partials in chunk order.
+constexpr int kHotMax = 128;             // at most this many hot rows
 constexpr int kHotWaves = 16;            // waves of the streaming pass; wave g owns h % 16 == g
 constexpr int kHotPerWave = kHotMax / kHotWaves;  // hot rows (register accumulators) per wave
 constexpr int64_t kHotMinLen = 1024;     // a hot row has at least one full item of entries
+constexpr int kHotBlockRows = 32;        // U rows per staged block of the streaming pass
 struct HotSet {
     int32_t n = 0;                       // hot rows (0: none, the batch gathers every row)
     int32_t *rows = nullptr;             // [n] back row of hot index h
     int32_t *len = nullptr;              // [n] entries of that row
-    DevCsr list;                         // rows g * n_u + u: (hot index, back weight) of u's hot
-                                         // rows h with h % kHotWaves == g, by h
+    // The hot entries as segments: segment ((g * n_blocks + B) * kHotPerWave
+    // + h / kHotWaves) holds, for block B and the hot row h (h % kHotWaves ==
+    // g), the entries (row of u within the block, back weight), by u.
+    DevCsr list;
     int32_t n_chunks = 0;                // fixed U chunks of the streaming pass:
     int64_t *chunk_start = nullptr;      //   chunk c = rows [start[c], start[c+1]) (device)
+    int64_t *blk_base = nullptr;         //   its blocks B = blk_base[c] ... (device, n_chunks + 1)
+    int64_t n_blocks = 0;
     WorkItem *cold_items = nullptr;      // back schedule without the hot rows
     int64_t n_cold_items = 0;
     SplitRow *cold_split = nullptr;

@@ -469,37 +469,37 @@ struct HotArgs {
     int64_t part_stride;
     const TileCtl *ctl;
     const int64_t *chunk_start;  // chunk c = U rows [chunk_start[c], chunk_start[c + 1])
-    int64_t n_u;
+    const int64_t *blk_base;     // first block of chunk c
+    int64_t n_blocks;
     int n_hot, n_chunks;
 };
 
 constexpr int kHotThreads = kHotWaves * kWave;  // one workgroup per (chunk, tile)
-constexpr int kHotBlockRows = 32;                // U rows per staged block
 constexpr int kHotStage = kHotBlockRows * kTileQ / 4 / kHotThreads;  // float4 per thread per block
 constexpr int kHotWindow = 2 * kWave;            // hot-list entries per wave held in registers
-constexpr int kHotCols = kTileQ / kWave;         // columns per lane: lane, lane + 64, ...
-static_assert(kHotPerWave == 8, "the accumulator chain below is written for 8 rows per wave");
-static_assert(kHotBlockRows < kWave, "a block's offsets sit one per lane");
+static_assert(kHotPerWave == 8, "a wave's block holds one segment per register row, 8 of them");
+static_assert(kHotPerWave < kWave, "a block's segment offsets sit one per lane");
 
 // What a wave needs for one block of U rows, loaded one block ahead with
 // vector loads (coalesced, many in flight) and read back with readlane.
 struct HotBlock {
     float4 x[kHotStage];   // the thread's share of the block's residues (raw)
-    int64_t off;           // lane j <= kHotBlockRows: offset of row ub + j in this wave's list
-    int32_t h0, h1;        // entries e_b + lane and e_b + 64 + lane: hot index
+    int64_t off;           // lane s <= kHotPerWave: start of the wave's segment s (s = kHotPerWave: the end)
+    int32_t p0, p1;        // entries e_b + lane and e_b + 64 + lane: row within the block
     float w0, w1;          //   and back weight
 };
 
 // One workgroup of kHotWaves waves per (chunk, tile).  The chunk's U rows are
-// streamed from HBM once: each block of kHotBlockRows rows is loaded one block
-// ahead into registers, thresholded into LDS, and read from there by every
-// wave (one barrier per block).  Wave g owns the hot rows h = g, g + 16, ...,
-// g + 112 and keeps their sums for its lane's columns (l, l + 64, l + 128,
-// l + 192) in registers; its list offsets and a window of its list entries
-// for the block are loaded with the block, so the per-entry work is register
-// arithmetic: for each entry (u, h, w') it adds w' thr(r(u)) to the register
-// row of h.  Each accumulator has one owner and the adds are ordered by u, so
-// the result is deterministic.
+// streamed from HBM once, in blocks of kHotBlockRows rows: each block is
+// loaded one block ahead into registers, thresholded into LDS, and read from
+// there by every wave (one barrier per block).  Wave g owns the hot rows
+// h = g + 16 s (s = 0..7) and keeps their sums for its lane's query columns
+// 4l .. 4l+3 in registers.  Its entries of a block come as 8 segments, one
+// per register row s, each listing (row within the block, w') by row, so the
+// per-entry work is one 16-byte LDS read and four FMAs into a register row
+// known at compile time; rows with no entry cost nothing.  Each accumulator
+// has one owner and its adds are ordered by block and row, so the result is
+// deterministic.
 __global__ void __launch_bounds__(kHotThreads) kb_hot(HotArgs a, const int64_t *__restrict__ hot_off,
                                                       const int32_t *__restrict__ hot_col,
                                                       const float *__restrict__ hot_w) {
@@ -517,30 +517,29 @@ __global__ void __launch_bounds__(kHotThreads) kb_hot(HotArgs a, const int64_t *
     for (int k = 0; k < 4; ++k) sth[k] = tc.q[scol + k].theta;
     const float *rt = a.r + t * a.r_stride;
     float *pt = a.part + t * a.part_stride;
-    const int64_t *off = hot_off + grp * a.n_u;
     const int c = blockIdx.x;
-    const int64_t u0 = a.chunk_start[c];
-    const int64_t u1 = a.chunk_start[c + 1];
-    float acc[kHotPerWave][kHotCols];
+    const int64_t u0 = a.chunk_start[c], u1 = a.chunk_start[c + 1];
+    const int64_t nb = (u1 - u0 + kHotBlockRows - 1) / kHotBlockRows;
+    // Segment offsets of this wave: block b of the chunk starts at seg(b).
+    const int64_t *seg = hot_off + ((int64_t)grp * a.n_blocks + a.blk_base[c]) * kHotPerWave;
+    float4 acc[kHotPerWave];
 #pragma unroll
-    for (int k = 0; k < kHotPerWave; ++k)
-#pragma unroll
-        for (int cc = 0; cc < kHotCols; ++cc) acc[k][cc] = 0.0f;
-    const int64_t e_end = off[u1];  // end of this wave's entries in the chunk
-    // Loads of block ub; e_b is the offset of its first row (known from the
+    for (int k = 0; k < kHotPerWave; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int64_t e_end = seg[nb * kHotPerWave];  // end of this wave's entries in the chunk
+    // Loads of block b; e_b is the offset of its first entry (known from the
     // previous block, or read directly for the first block).
-    auto load_block = [&](HotBlock &blk, int64_t ub, int64_t e_b) {
+    auto load_block = [&](HotBlock &blk, int64_t b, int64_t e_b) {
+        const int64_t ub = u0 + b * kHotBlockRows;
 #pragma unroll
         for (int i = 0; i < kHotStage; ++i) {
             const int64_t u = ub + (tid + i * kHotThreads) / (kTileQ / 4);
             blk.x[i] = u < u1 ? *reinterpret_cast<const float4 *>(rt + u * kTileQ + scol)
                               : make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        const int64_t ur = ub + lane < u1 ? ub + lane : u1;
-        blk.off = lane <= kHotBlockRows ? off[ur] : 0;
-        blk.h0 = e_b + lane < e_end ? hot_col[e_b + lane] : 0;
+        blk.off = (lane <= kHotPerWave && b < nb) ? seg[b * kHotPerWave + lane] : 0;
+        blk.p0 = e_b + lane < e_end ? hot_col[e_b + lane] : 0;
         blk.w0 = e_b + lane < e_end ? hot_w[e_b + lane] : 0.0f;
-        blk.h1 = e_b + kWave + lane < e_end ? hot_col[e_b + kWave + lane] : 0;
+        blk.p1 = e_b + kWave + lane < e_end ? hot_col[e_b + kWave + lane] : 0;
         blk.w1 = e_b + kWave + lane < e_end ? hot_w[e_b + kWave + lane] : 0.0f;
     };
     auto stage = [&](int buf, const HotBlock &blk) {
@@ -554,44 +553,39 @@ __global__ void __launch_bounds__(kHotThreads) kb_hot(HotArgs a, const int64_t *
             xs[buf][tid + i * kHotThreads] = v;
         }
     };
-    if (u0 < u1) {
+    if (nb > 0) {
         HotBlock cur;
-        load_block(cur, u0, off[u0]);
+        load_block(cur, 0, seg[0]);
         stage(0, cur);
         __syncthreads();
         int buf = 0;
-        for (int64_t ub = u0; ub < u1; ub += kHotBlockRows) {
+        for (int64_t b = 0; b < nb; ++b) {
             const int64_t e_b = readlane_i64(cur.off, 0);
             HotBlock nxt;
-            load_block(nxt, ub + kHotBlockRows, readlane_i64(cur.off, kHotBlockRows));
-            const float *xb = reinterpret_cast<const float *>(xs[buf]);
-            const int nrows = u1 - ub < kHotBlockRows ? (int)(u1 - ub) : kHotBlockRows;
-            for (int j = 0; j < nrows; ++j) {
-                const int k0 = (int)(readlane_i64(cur.off, j) - e_b);
-                const int k1 = (int)(readlane_i64(cur.off, j + 1) - e_b);
-                if (k0 == k1) continue;
-                float x[kHotCols];
+            load_block(nxt, b + 1, readlane_i64(cur.off, kHotPerWave));
+            const float4 *xb = xs[buf];
 #pragma unroll
-                for (int cc = 0; cc < kHotCols; ++cc) x[cc] = xb[j * kTileQ + cc * kWave + lane];
+            for (int sg = 0; sg < kHotPerWave; ++sg) {
+                const int k0 = (int)(readlane_i64(cur.off, sg) - e_b);
+                const int k1 = (int)(readlane_i64(cur.off, sg + 1) - e_b);
                 for (int k = k0; k < k1; ++k) {
-                    int h;
+                    int p;
                     float w;
                     if (k < kWave) {
-                        h = __builtin_amdgcn_readlane(cur.h0, k);
+                        p = __builtin_amdgcn_readlane(cur.p0, k);
                         w = readlane_f(cur.w0, k);
                     } else if (k < kHotWindow) {
-                        h = __builtin_amdgcn_readlane(cur.h1, k - kWave);
+                        p = __builtin_amdgcn_readlane(cur.p1, k - kWave);
                         w = readlane_f(cur.w1, k - kWave);
                     } else {  // a block with more entries than the window: read them directly
-                        h = hot_col[e_b + k];
+                        p = hot_col[e_b + k];
                         w = hot_w[e_b + k];
                     }
-                    const int kr = h / kHotWaves;  // register row of this entry
-#pragma unroll
-                    for (int kk = 0; kk < kHotPerWave; ++kk)
-                        if (kr == kk)
-#pragma unroll
-                            for (int cc = 0; cc < kHotCols; ++cc) acc[kk][cc] += w * x[cc];
+                    const float4 x = xb[p * (kTileQ / 4) + lane];
+                    acc[sg].x += w * x.x;
+                    acc[sg].y += w * x.y;
+                    acc[sg].z += w * x.z;
+                    acc[sg].w += w * x.w;
                 }
             }
             stage(buf ^ 1, nxt);
@@ -604,9 +598,7 @@ __global__ void __launch_bounds__(kHotThreads) kb_hot(HotArgs a, const int64_t *
     for (int k = 0; k < kHotPerWave; ++k) {
         const int h = grp + k * kHotWaves;
         if (h < a.n_hot)
-#pragma unroll
-            for (int cc = 0; cc < kHotCols; ++cc)
-                pt[((int64_t)c * a.n_hot + h) * kTileQ + cc * kWave + lane] = acc[k][cc];
+            *reinterpret_cast<float4 *>(pt + ((int64_t)c * a.n_hot + h) * kTileQ + lane * 4) = acc[k];
     }
 }
 
@@ -944,13 +936,13 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
     // Algorithmic bytes of a launch: CSR entries and offsets once, 4 bytes
     // per (entry, running query), and the per-(row, query) state the
     // epilogue reads and writes.  The hot-row pass reads the hot list and
-    // the U offsets once and each query's residue of every U row once, and
-    // writes and re-reads its chunk partials.
+    // its segment offsets once and each query's residue of every U row once,
+    // and writes and re-reads its chunk partials.
     const double q = (double)b.live_q;
     const double wb = g.fwd.w ? 8.0 : 4.0;
     const double back_bytes = 8.0 * bs.nnz + 12.0 * bs.rows + q * (4.0 * bs.nnz + 4.0 * bs.rows);
     const double fwd_bytes = wb * g.fwd.nnz + 8.0 * g.fwd.n_rows + q * (4.0 * g.fwd.nnz + 16.0 * g.fwd.n_rows);
-    const double hot_bytes = 8.0 * hs.list.nnz + 8.0 * g.n_u + 12.0 * hs.n +
+    const double hot_bytes = 8.0 * hs.list.nnz + 8.0 * (hs.list.n_rows + 1) + 12.0 * hs.n +
                              q * (4.0 * g.n_u + 8.0 * hs.n_chunks * hs.n + 4.0 * hs.n);
     if (p.back)
         profiled(g.prof, 2, back_bytes, s, [&] {
@@ -963,7 +955,8 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
     }
     if (hs.n > 0) {
         const int64_t tile_hot = (int64_t)hs.n_chunks * hs.n * kTileQ;
-        HotArgs ha{b.r, tile_u, b.hot_part, tile_hot, b.ctl, hs.chunk_start, g.n_u, hs.n, hs.n_chunks};
+        HotArgs ha{b.r,           tile_u,      b.hot_part, tile_hot, b.ctl, hs.chunk_start,
+                   hs.blk_base,   hs.n_blocks, hs.n,       hs.n_chunks};
         HotReduceArgs ra{b.hot_part, tile_hot, hs.rows, hs.len, g.inv_b, b.z, tile_z, b.blk_np + 4 * slot, su, b.ctl,
                          hs.n, hs.n_chunks};
         profiled(g.prof, 4, hot_bytes, s, [&] {

@@ -286,18 +286,46 @@ __global__ void k_back_coeffs(const int64_t *off, const int32_t *col, float *w, 
 // Entries of the hot rows, keyed by (group of h, U column): entry i of hot
 // row h (start[h] <= i < start[h + 1]) becomes (key (h % kHotWaves) * n_u + u,
 // col h, w back weight).
+// Hot entry i (the hot rows' entries, concatenated in hot order; start[h]
+// = first entry of hot row h): its hot index and back CSR position.
+__device__ __forceinline__ int hot_of_entry(const int64_t *start, int n_hot, int64_t i) {
+    int lo = 0, hi = n_hot - 1;  // last h with start[h] <= i
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// cnt[u] = hot entries naming U row u (at most kHotMax per row).
+__global__ void k_hot_count(const int64_t *off, const int32_t *col, const int32_t *rows, const int64_t *start,
+                            int n_hot, int64_t m, unsigned *cnt) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int h = hot_of_entry(start, n_hot, i);
+        atomicAdd(&cnt[col[off[rows[h]] + (i - start[h])]], 1u);
+    }
+}
+
+// Segment key, row within the block and weight of every hot entry: U row u
+// lies in chunk c (chunk_start[c] <= u < chunk_start[c + 1]), block B =
+// blk_base[c] + (u - chunk_start[c]) / kHotBlockRows.
 __global__ void k_hot_entries(const int64_t *off, const int32_t *col, const float *w, const int32_t *rows,
-                              const int64_t *start, int n_hot, int64_t m, int64_t n_u, uint32_t *key, int32_t *hcol,
+                              const int64_t *start, int n_hot, int64_t m, const int64_t *chunk_start,
+                              const int64_t *blk_base, int n_chunks, int64_t n_blocks, uint32_t *key, int32_t *hcol,
                               float *hw) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-        int lo = 0, hi = n_hot - 1;  // last h with start[h] <= i
+        const int h = hot_of_entry(start, n_hot, i);
+        const int64_t p = off[rows[h]] + (i - start[h]);
+        const int64_t u = col[p];
+        int lo = 0, hi = n_chunks - 1;  // last c with chunk_start[c] <= u
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (start[mid] <= i) lo = mid; else hi = mid - 1;
+            if (chunk_start[mid] <= u) lo = mid; else hi = mid - 1;
         }
-        const int64_t p = off[rows[lo]] + (i - start[lo]);
-        key[i] = (uint32_t)((int64_t)(lo % kHotWaves) * n_u + col[p]);
-        hcol[i] = lo;
+        const int64_t rel = u - chunk_start[lo];
+        const int64_t blk = blk_base[lo] + rel / kHotBlockRows;
+        key[i] = (uint32_t)(((int64_t)(h % kHotWaves) * n_blocks + blk) * kHotPerWave + h / kHotWaves);
+        hcol[i] = (int32_t)(rel % kHotBlockRows);
         hw[i] = w[p];
     }
 }
@@ -398,7 +426,7 @@ void sort_by_key(uint32_t *key, int32_t *col, float *w, int64_t m, int key_bits,
 // under the device numbering puts a row's most referenced columns side by
 // side for the lanes of one load; otherwise rows keep the input order.
 void build_csr(Graph &g, DevCsr &c, int64_t n_rows, uint32_t *key, int32_t *col, float *w, int64_t m, bool keep_w,
-               hipStream_t s, int64_t n_cols = 0) {
+               hipStream_t s, int64_t n_cols = 0, bool with_items = true) {
     c.n_rows = n_rows;
     c.nnz = m;
     c.off = (int64_t *)dev_alloc(g, (size_t)(n_rows + 1) * sizeof(int64_t), "csr offsets");
@@ -416,6 +444,7 @@ void build_csr(Graph &g, DevCsr &c, int64_t n_rows, uint32_t *key, int32_t *col,
     } else {
         check_hip(hipMemsetAsync(c.off, 0, (size_t)(n_rows + 1) * sizeof(int64_t), s), "csr offsets");
     }
+    if (!with_items) return;
     // Wave schedule (host side: a linear greedy pass over the offsets).
     std::vector<int64_t> off((size_t)n_rows + 1);
     check_hip(hipMemcpyAsync(off.data(), c.off, off.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s), "offsets D2H");
@@ -473,17 +502,11 @@ int64_t number_by_count(Graph &g, int64_t n, std::initializer_list<std::pair<con
     return (int64_t)n_nz;
 }
 
-// Streaming-pass cost of U row u (a row of the device numbering): its
-// entries in the kHotWaves hot lists plus one per wave; cost[n_u] = 0.
-__global__ void k_hot_cost(const int64_t *off, int64_t n_u, unsigned long long *cost) {
-    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u <= n_u; u += (int64_t)gridDim.x * blockDim.x) {
-        unsigned long long c = 0;
-        if (u < n_u) {
-            c = kHotWaves;
-            for (int g = 0; g < kHotWaves; ++g) c += (unsigned long long)(off[g * n_u + u + 1] - off[g * n_u + u]);
-        }
-        cost[u] = c;
-    }
+// Streaming-pass cost of U row u (a row of the device numbering): its hot
+// entries plus kHotWaves for its staging; cost[n_u] = 0.
+__global__ void k_hot_cost(const unsigned *cnt, int64_t n_u, unsigned long long *cost) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u <= n_u; u += (int64_t)gridDim.x * blockDim.x)
+        cost[u] = u < n_u ? (unsigned long long)cnt[u] + kHotWaves : 0ull;
 }
 
 // start[c] = the first row whose exclusive cost prefix reaches c / n_chunks
@@ -508,8 +531,8 @@ __global__ void k_chunk_bounds(const unsigned long long *prefix, int64_t n_u, in
 
 // Picks the hot rows of the back CSR (the kHotMax longest rows with at least
 // kHotMinLen entries; AHPP_HOT_ROWS=<n> lowers the cap, 0 turns it off),
-// builds their U-major lists (one per group h % kHotWaves, as one CSR over
-// kHotWaves * n_u rows) and the back schedule without them.
+// splits U into the pass's chunks and blocks, builds the segmented hot list
+// and the back schedule without the hot rows.
 void build_hot(Graph &g, hipStream_t s) {
     HotSet &h = g.hot;
     int cap = kHotMax;
@@ -551,10 +574,51 @@ void build_hot(Graph &g, hipStream_t s) {
     check_hip(hipMalloc(&col, (size_t)m * 4), "hot entries");
     check_hip(hipMalloc(&w, (size_t)m * 4), "hot entries");
     check_hip(hipMemcpyAsync(d_start, start.data(), (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s), "hot entries");
+
+    // Fixed chunking (a property of the graph and the device, not of the
+    // launch), so the sum order never depends on how many tiles run.  The
+    // chunks are balanced by cost (a row's hot entries plus kHotWaves for its
+    // staging), since the device numbering puts the rows with the most
+    // entries first.
+    h.n_chunks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(g.n_cu, g.n_u));
+    h.chunk_start = (int64_t *)dev_alloc(g, (size_t)(h.n_chunks + 1) * 8, "hot chunks");
+    {
+        unsigned *cnt = nullptr;
+        unsigned long long *cost = nullptr, *part = nullptr;
+        const int64_t nc = g.n_u + 1;
+        check_hip(hipMalloc(&cnt, (size_t)g.n_u * 4), "hot chunks");
+        check_hip(hipMalloc(&cost, (size_t)nc * 8), "hot chunks");
+        check_hip(hipMalloc(&part, (size_t)((nc + kScanTile - 1) / kScanTile + 1) * 8), "hot chunks");
+        check_hip(hipMemsetAsync(cnt, 0, (size_t)g.n_u * 4, s), "hot chunks");
+        hipLaunchKernelGGL(k_hot_count, dim3(grid_for(m)), dim3(kBlock), 0, s, g.back.off, g.back.col, h.rows, d_start,
+                           n, m, cnt);
+        hipLaunchKernelGGL(k_hot_cost, dim3(grid_for(nc)), dim3(kBlock), 0, s, cnt, g.n_u, cost);
+        exclusive_scan_u64(cost, cost, nc, part, s);
+        hipLaunchKernelGGL(k_chunk_bounds, dim3(grid_for(h.n_chunks + 1)), dim3(kBlock), 0, s, cost, g.n_u,
+                           h.n_chunks, h.chunk_start);
+        check_hip(hipGetLastError(), "hot chunks launch");
+        check_hip(hipStreamSynchronize(s), "hot chunks");
+        dfree(cnt);
+        dfree(cost);
+        dfree(part);
+    }
+    // Blocks of kHotBlockRows rows from each chunk's start.
+    std::vector<int64_t> cstart((size_t)h.n_chunks + 1), bbase((size_t)h.n_chunks + 1, 0);
+    check_hip(hipMemcpyAsync(cstart.data(), h.chunk_start, cstart.size() * 8, hipMemcpyDeviceToHost, s), "hot chunks");
+    check_hip(hipStreamSynchronize(s), "hot chunks");
+    for (int c = 0; c < h.n_chunks; ++c)
+        bbase[c + 1] = bbase[c] + (cstart[c + 1] - cstart[c] + kHotBlockRows - 1) / kHotBlockRows;
+    h.n_blocks = bbase[h.n_chunks];
+    const int64_t n_seg = (int64_t)kHotWaves * h.n_blocks * kHotPerWave;
+    if (n_seg >= (int64_t)UINT32_MAX) throw Failure{-1, "ahpp_graph_load: too many hot-pass blocks"};
+    h.blk_base = (int64_t *)dev_alloc(g, bbase.size() * 8, "hot chunks");
+    check_hip(hipMemcpyAsync(h.blk_base, bbase.data(), bbase.size() * 8, hipMemcpyHostToDevice, s), "hot chunks");
     hipLaunchKernelGGL(k_hot_entries, dim3(grid_for(m)), dim3(kBlock), 0, s, g.back.off, g.back.col, g.back.w, h.rows,
-                       d_start, n, m, g.n_u, key, col, w);
+                       d_start, n, m, (const int64_t *)h.chunk_start, (const int64_t *)h.blk_base, h.n_chunks,
+                       h.n_blocks, key, col, w);
     check_hip(hipGetLastError(), "hot entries launch");
-    build_csr(g, h.list, kHotWaves * g.n_u, key, col, w, m, true, s);
+    // Segments keep their entries in row order (a sort by row within the block first).
+    build_csr(g, h.list, n_seg, key, col, w, m, true, s, kHotBlockRows, false);
     dfree(d_start);
     dfree(key);
     dfree(col);
@@ -576,28 +640,7 @@ void build_hot(Graph &g, hipStream_t s) {
                                  s), "cold schedule");
     h.cold_nnz = g.back.nnz - m;
     h.cold_rows = n_rows - n;
-    // Fixed chunking (a property of the graph and the device, not of the
-    // launch), so the sum order never depends on how many tiles run.  The
-    // chunks are balanced by cost: a row's hot-list entries plus one per
-    // wave (its staging), since the device numbering puts the rows with the
-    // most entries first.
-    h.n_chunks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(g.n_cu, g.n_u));
-    h.chunk_start = (int64_t *)dev_alloc(g, (size_t)(h.n_chunks + 1) * 8, "hot chunks");
-    {
-        unsigned long long *cost = nullptr, *part = nullptr;
-        const int64_t n = g.n_u + 1;
-        check_hip(hipMalloc(&cost, (size_t)n * 8), "hot chunks");
-        check_hip(hipMalloc(&part, (size_t)((n + kScanTile - 1) / kScanTile + 1) * 8), "hot chunks");
-        hipLaunchKernelGGL(k_hot_cost, dim3(grid_for(n)), dim3(kBlock), 0, s, (const int64_t *)h.list.off, g.n_u,
-                           cost);
-        exclusive_scan_u64(cost, cost, n, part, s);
-        hipLaunchKernelGGL(k_chunk_bounds, dim3(grid_for(h.n_chunks + 1)), dim3(kBlock), 0, s, cost, g.n_u,
-                           h.n_chunks, h.chunk_start);
-        check_hip(hipGetLastError(), "hot chunks launch");
-        check_hip(hipStreamSynchronize(s), "hot chunks");
-        dfree(cost);
-        dfree(part);
-    }
+    check_hip(hipStreamSynchronize(s), "hot rows");
 }
 
 }  // namespace
@@ -749,7 +792,7 @@ void free_graph(Graph &g) {
     free_csr(g.hot.list);
     free_mc_tables(g.mc);
     for (void *p : {(void *)g.hot.rows, (void *)g.hot.len, (void *)g.hot.cold_items, (void *)g.hot.cold_split,
-                    (void *)g.hot.chunk_start})
+                    (void *)g.hot.chunk_start, (void *)g.hot.blk_base})
         dfree(p);
     g.hot = HotSet{};
     free_batch_state(g.batch);
