@@ -470,8 +470,8 @@ ahpp_status_t query_impl(const char *name, ahpp_graph_t *h, int32_t source, doub
         check_hip(hipEventCreate(&e1), "event");
         check_hip(hipEventRecord(e0, s), "event");
         const float eps_f = (float)(eps / g.lambda);
-        single_query_init(g, g.u_new_host[(size_t)source], eps_f, max_iters, s, schedule,
-                          (float)(eps / (double)(g.m_e + g.m_a)));
+        const int32_t src = g.u_new_host[(size_t)source];
+        single_query_init(g, src, eps_f, max_iters, s, schedule, (float)(eps / (double)(g.m_e + g.m_a)));
         run_single(g, s);
         // Scores in input order (the top-k breaks ties by input id).
         float *scores = pi_out ? pi_out : (k > 0 ? g.q_out : nullptr);
