@@ -564,28 +564,48 @@ __global__ void __launch_bounds__(kHotThreads) kb_hot(HotArgs a, const int64_t *
             HotBlock nxt;
             load_block(nxt, b + 1, readlane_i64(cur.off, kHotPerWave));
             const float4 *xb = xs[buf];
+            // Entry k of the block: (row within the block, w').
+            auto entry = [&](int k, int &p, float &w) {
+                if (k < kWave) {
+                    p = __builtin_amdgcn_readlane(cur.p0, k);
+                    w = readlane_f(cur.w0, k);
+                } else if (k < kHotWindow) {
+                    p = __builtin_amdgcn_readlane(cur.p1, k - kWave);
+                    w = readlane_f(cur.w1, k - kWave);
+                } else {  // a block with more entries than the window: read them directly
+                    p = hot_col[e_b + k];
+                    w = hot_w[e_b + k];
+                }
+            };
+            auto add = [&](float4 &s, float w, const float4 &x) {
+                s.x += w * x.x;
+                s.y += w * x.y;
+                s.z += w * x.z;
+                s.w += w * x.w;
+            };
 #pragma unroll
             for (int sg = 0; sg < kHotPerWave; ++sg) {
                 const int k0 = (int)(readlane_i64(cur.off, sg) - e_b);
                 const int k1 = (int)(readlane_i64(cur.off, sg + 1) - e_b);
-                for (int k = k0; k < k1; ++k) {
+                int k = k0;
+                // Two entries at a time: both LDS reads are in flight before
+                // the adds, which keep the entry order (groups of four
+                // measured slower: most segments are short).
+                for (; k + 1 < k1; k += 2) {
+                    int pa, pb;
+                    float wa, wb;
+                    entry(k, pa, wa);
+                    entry(k + 1, pb, wb);
+                    const float4 xa = xb[pa * (kTileQ / 4) + lane];
+                    const float4 xc = xb[pb * (kTileQ / 4) + lane];
+                    add(acc[sg], wa, xa);
+                    add(acc[sg], wb, xc);
+                }
+                if (k < k1) {
                     int p;
                     float w;
-                    if (k < kWave) {
-                        p = __builtin_amdgcn_readlane(cur.p0, k);
-                        w = readlane_f(cur.w0, k);
-                    } else if (k < kHotWindow) {
-                        p = __builtin_amdgcn_readlane(cur.p1, k - kWave);
-                        w = readlane_f(cur.w1, k - kWave);
-                    } else {  // a block with more entries than the window: read them directly
-                        p = hot_col[e_b + k];
-                        w = hot_w[e_b + k];
-                    }
-                    const float4 x = xb[p * (kTileQ / 4) + lane];
-                    acc[sg].x += w * x.x;
-                    acc[sg].y += w * x.y;
-                    acc[sg].z += w * x.z;
-                    acc[sg].w += w * x.w;
+                    entry(k, p, w);
+                    add(acc[sg], w, xb[p * (kTileQ / 4) + lane]);
                 }
             }
             stage(buf ^ 1, nxt);
