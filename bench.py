@@ -278,8 +278,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: queries are independent and this build measures the single-GPU "
-              "share; multi-GPU sharding is not implemented.", file=sys.stderr)
+        print("bench.py measures one GPU only: queries are independent, the figure is one GPU's share, and "
+              "sharding across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
