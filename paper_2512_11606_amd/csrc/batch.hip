@@ -366,7 +366,7 @@ __global__ void __launch_bounds__(kBlock) kb_fix(BArgs a) {
 // partials, then the stop / switch rule of Algorithm 4 for every running query.
 constexpr int kCtlSplit = 4;    // threads per query reducing the partials
 constexpr int kCtlThreads = kCtlSplit * kTileQ;
-constexpr int kCtlSlices = 8;   // workgroups per tile reducing the partials
+constexpr int kCtlSlices = 32;  // workgroups per tile reducing the partials
 
 // Workgroup (slice, tile), thread (part, q): max r and n_p of query q over
 // the workgroup partials i with i % (kCtlSplit * kCtlSlices) ==

@@ -71,6 +71,21 @@ __global__ void k_count_ids(const int32_t *ids, int64_t m, unsigned *cnt) {
         atomicAdd(&cnt[ids[i]], 1u);
 }
 
+// The same for small id sets (n <= kLdsCountMax): each workgroup counts its
+// share in LDS, then adds its nonzero counts to cnt (few global atomics per
+// id even when a few ids take most entries).
+constexpr int64_t kLdsCountMax = 12288;
+__global__ void k_count_ids_lds(const int32_t *ids, int64_t m, int64_t n, unsigned *cnt) {
+    extern __shared__ unsigned h[];
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) h[i] = 0u;
+    __syncthreads();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&h[ids[i]], 1u);
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+        if (h[i]) atomicAdd(&cnt[i], h[i]);
+}
+
 // Sort keys of ids 0..n-1: larger counts first; the stable sort keeps id
 // order among equal counts.
 __global__ void k_rank_keys(const unsigned *cnt, int64_t n, uint32_t *key, int32_t *id) {
@@ -482,9 +497,14 @@ int64_t number_by_count(Graph &g, int64_t n, std::initializer_list<std::pair<con
     check_hip(hipMalloc(&nz, 8), "numbering");
     check_hip(hipMemsetAsync(cnt, 0, (size_t)n * 4, s), "numbering");
     check_hip(hipMemsetAsync(nz, 0, 8, s), "numbering");
-    for (const auto &l : lists)
-        if (l.second > 0)
+    for (const auto &l : lists) {
+        if (l.second <= 0) continue;
+        if (n <= kLdsCountMax)
+            hipLaunchKernelGGL(k_count_ids_lds, dim3(std::min<unsigned>(grid_for(l.second), 1024u)), dim3(kBlock),
+                               (size_t)n * sizeof(unsigned), s, l.first, l.second, n, cnt);
+        else
             hipLaunchKernelGGL(k_count_ids, dim3(grid_for(l.second)), dim3(kBlock), 0, s, l.first, l.second, cnt);
+    }
     hipLaunchKernelGGL(k_count_nonzero, dim3(grid_for(n)), dim3(kBlock), 0, s, cnt, n, nz);
     hipLaunchKernelGGL(k_rank_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, cnt, n, key, order);
     check_hip(hipGetLastError(), "numbering launch");
