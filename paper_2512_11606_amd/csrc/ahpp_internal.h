@@ -262,6 +262,25 @@ void check_hip(hipError_t e, const char *what);
 inline void dfree(void *p) {
     if (p) (void)hipFree(p);
 }
+
+// Device scratch of n elements (none when n is 0) owned by a scope: freed
+// when the scope ends, also when a step in it throws (hipFree waits for work
+// that may still use it).
+template <typename T>
+class DevTemp {
+  public:
+    DevTemp() = default;
+    DevTemp(size_t n, const char *what) {
+        if (n) check_hip(hipMalloc(reinterpret_cast<void **>(&p_), n * sizeof(T)), what);
+    }
+    ~DevTemp() { dfree(p_); }
+    DevTemp(const DevTemp &) = delete;
+    DevTemp &operator=(const DevTemp &) = delete;
+    T *get() const { return p_; }
+
+  private:
+    T *p_ = nullptr;
+};
 void *dev_alloc(Graph &g, size_t bytes, const char *what);
 
 // mc.hip: n_walks walks from source; count[x] = walks stopped at x.

@@ -398,26 +398,23 @@ void build_items(const std::vector<int64_t> &off, std::vector<WorkItem> &items, 
 // keys below 2^key_bits; the sorted triples end in the same buffers.
 void sort_by_key(uint32_t *key, int32_t *col, float *w, int64_t m, int key_bits, hipStream_t s) {
     if (m <= 0) return;
-    uint32_t *key2 = nullptr;
-    int32_t *col2 = nullptr;
-    float *w2 = nullptr;
-    unsigned long long *cnt = nullptr, *part = nullptr;
     const int64_t n_tiles = (m + kSortTile - 1) / kSortTile;
     const int64_t n_cnt = 16 * n_tiles;
-    check_hip(hipMalloc(&key2, (size_t)m * 4), "sort buffer");
-    check_hip(hipMalloc(&col2, (size_t)m * 4), "sort buffer");
-    if (w) check_hip(hipMalloc(&w2, (size_t)m * 4), "sort buffer");
-    check_hip(hipMalloc(&cnt, (size_t)n_cnt * 8), "sort counts");
-    check_hip(hipMalloc(&part, (size_t)((n_cnt + kScanTile - 1) / kScanTile + 1) * 8), "scan partials");
+    DevTemp<uint32_t> key2((size_t)m, "sort buffer");
+    DevTemp<int32_t> col2((size_t)m, "sort buffer");
+    DevTemp<float> w2(w ? (size_t)m : 0, "sort buffer");
+    DevTemp<unsigned long long> cnt((size_t)n_cnt, "sort counts");
+    DevTemp<unsigned long long> part((size_t)((n_cnt + kScanTile - 1) / kScanTile + 1), "scan partials");
     const int passes = (key_bits + 3) / 4;
-    uint32_t *ki = key, *ko = key2;
-    int32_t *ci = col, *co = col2;
-    float *wi = w, *wo = w2;
+    uint32_t *ki = key, *ko = key2.get();
+    int32_t *ci = col, *co = col2.get();
+    float *wi = w, *wo = w2.get();
     for (int p = 0; p < passes; ++p) {
-        hipLaunchKernelGGL(k_radix_count, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, ki, m, 4 * p, cnt, n_tiles);
-        exclusive_scan_u64(cnt, cnt, n_cnt, part, s);
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, ki, ci, wi, m, 4 * p, cnt,
-                           n_tiles, ko, co, wo);
+        hipLaunchKernelGGL(k_radix_count, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, ki, m, 4 * p, cnt.get(),
+                           n_tiles);
+        exclusive_scan_u64(cnt.get(), cnt.get(), n_cnt, part.get(), s);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)n_tiles), dim3(kBlock), 0, s, ki, ci, wi, m, 4 * p,
+                           cnt.get(), n_tiles, ko, co, wo);
         check_hip(hipGetLastError(), "radix sort launch");
         std::swap(ki, ko);
         std::swap(ci, co);
@@ -429,11 +426,6 @@ void sort_by_key(uint32_t *key, int32_t *col, float *w, int64_t m, int key_bits,
         if (w) check_hip(hipMemcpyAsync(w, wi, (size_t)m * 4, hipMemcpyDeviceToDevice, s), "sort copy");
     }
     check_hip(hipStreamSynchronize(s), "sort");
-    dfree(key2);
-    dfree(col2);
-    dfree(w2);
-    dfree(cnt);
-    dfree(part);
 }
 
 // CSR of m entries (row key, column, weight).  With n_cols > 0 the entries of
@@ -487,14 +479,14 @@ void build_csr(Graph &g, DevCsr &c, int64_t n_rows, uint32_t *key, int32_t *col,
 int64_t number_by_count(Graph &g, int64_t n, std::initializer_list<std::pair<const int32_t *, int64_t>> lists,
                         int32_t *new_of, hipStream_t s) {
     if (n <= 0) return 0;
-    unsigned *cnt = nullptr;
-    uint32_t *key = nullptr;
-    int32_t *order = nullptr;
-    unsigned long long *nz = nullptr;
-    check_hip(hipMalloc(&cnt, (size_t)n * 4), "numbering");
-    check_hip(hipMalloc(&key, (size_t)n * 4), "numbering");
-    check_hip(hipMalloc(&order, (size_t)n * 4), "numbering");
-    check_hip(hipMalloc(&nz, 8), "numbering");
+    DevTemp<unsigned> cnt_((size_t)n, "numbering");
+    DevTemp<uint32_t> key_((size_t)n, "numbering");
+    DevTemp<int32_t> order_((size_t)n, "numbering");
+    DevTemp<unsigned long long> nz_(1, "numbering");
+    unsigned *cnt = cnt_.get();
+    uint32_t *key = key_.get();
+    int32_t *order = order_.get();
+    unsigned long long *nz = nz_.get();
     check_hip(hipMemsetAsync(cnt, 0, (size_t)n * 4, s), "numbering");
     check_hip(hipMemsetAsync(nz, 0, 8, s), "numbering");
     for (const auto &l : lists) {
@@ -514,10 +506,6 @@ int64_t number_by_count(Graph &g, int64_t n, std::initializer_list<std::pair<con
     unsigned long long n_nz = 0;
     check_hip(hipMemcpyAsync(&n_nz, nz, 8, hipMemcpyDeviceToHost, s), "numbering");
     check_hip(hipStreamSynchronize(s), "numbering");
-    dfree(cnt);
-    dfree(key);
-    dfree(order);
-    dfree(nz);
     (void)g;
     return (int64_t)n_nz;
 }
@@ -585,64 +573,60 @@ void build_hot(Graph &g, hipStream_t s) {
     h.len = (int32_t *)dev_alloc(g, (size_t)n * 4, "hot rows");
     check_hip(hipMemcpyAsync(h.rows, order.data(), (size_t)n * 4, hipMemcpyHostToDevice, s), "hot rows");
     check_hip(hipMemcpyAsync(h.len, len.data(), (size_t)n * 4, hipMemcpyHostToDevice, s), "hot rows");
-    int64_t *d_start = nullptr;
-    uint32_t *key = nullptr;
-    int32_t *col = nullptr;
-    float *w = nullptr;
-    check_hip(hipMalloc(&d_start, (size_t)(n + 1) * 8), "hot entries");
-    check_hip(hipMalloc(&key, (size_t)m * 4), "hot entries");
-    check_hip(hipMalloc(&col, (size_t)m * 4), "hot entries");
-    check_hip(hipMalloc(&w, (size_t)m * 4), "hot entries");
-    check_hip(hipMemcpyAsync(d_start, start.data(), (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s), "hot entries");
+    {  // hot entries, chunks and the segmented list; the scratch ends with the block
+        DevTemp<int64_t> start_((size_t)n + 1, "hot entries");
+        DevTemp<uint32_t> key_((size_t)m, "hot entries");
+        DevTemp<int32_t> col_((size_t)m, "hot entries");
+        DevTemp<float> w_((size_t)m, "hot entries");
+        int64_t *d_start = start_.get();
+        uint32_t *key = key_.get();
+        int32_t *col = col_.get();
+        float *w = w_.get();
+        check_hip(hipMemcpyAsync(d_start, start.data(), (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s), "hot entries");
 
-    // Fixed chunking (a property of the graph and the device, not of the
-    // launch), so the sum order never depends on how many tiles run.  The
-    // chunks are balanced by cost (a row's hot entries plus kHotWaves for its
-    // staging), since the device numbering puts the rows with the most
-    // entries first.
-    h.n_chunks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(g.n_cu, g.n_u));
-    h.chunk_start = (int64_t *)dev_alloc(g, (size_t)(h.n_chunks + 1) * 8, "hot chunks");
-    {
-        unsigned *cnt = nullptr;
-        unsigned long long *cost = nullptr, *part = nullptr;
-        const int64_t nc = g.n_u + 1;
-        check_hip(hipMalloc(&cnt, (size_t)g.n_u * 4), "hot chunks");
-        check_hip(hipMalloc(&cost, (size_t)nc * 8), "hot chunks");
-        check_hip(hipMalloc(&part, (size_t)((nc + kScanTile - 1) / kScanTile + 1) * 8), "hot chunks");
-        check_hip(hipMemsetAsync(cnt, 0, (size_t)g.n_u * 4, s), "hot chunks");
-        hipLaunchKernelGGL(k_hot_count, dim3(grid_for(m)), dim3(kBlock), 0, s, g.back.off, g.back.col, h.rows, d_start,
-                           n, m, cnt);
-        hipLaunchKernelGGL(k_hot_cost, dim3(grid_for(nc)), dim3(kBlock), 0, s, cnt, g.n_u, cost);
-        exclusive_scan_u64(cost, cost, nc, part, s);
-        hipLaunchKernelGGL(k_chunk_bounds, dim3(grid_for(h.n_chunks + 1)), dim3(kBlock), 0, s, cost, g.n_u,
-                           h.n_chunks, h.chunk_start);
-        check_hip(hipGetLastError(), "hot chunks launch");
+        // Fixed chunking (a property of the graph and the device, not of the
+        // launch), so the sum order never depends on how many tiles run.  The
+        // chunks are balanced by cost (a row's hot entries plus kHotWaves for its
+        // staging), since the device numbering puts the rows with the most
+        // entries first.
+        h.n_chunks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(g.n_cu, g.n_u));
+        h.chunk_start = (int64_t *)dev_alloc(g, (size_t)(h.n_chunks + 1) * 8, "hot chunks");
+        {
+            const int64_t nc = g.n_u + 1;
+            DevTemp<unsigned> cnt_((size_t)g.n_u, "hot chunks");
+            DevTemp<unsigned long long> cost_((size_t)nc, "hot chunks");
+            DevTemp<unsigned long long> part_((size_t)((nc + kScanTile - 1) / kScanTile + 1), "hot chunks");
+            unsigned *cnt = cnt_.get();
+            unsigned long long *cost = cost_.get(), *part = part_.get();
+            check_hip(hipMemsetAsync(cnt, 0, (size_t)g.n_u * 4, s), "hot chunks");
+            hipLaunchKernelGGL(k_hot_count, dim3(grid_for(m)), dim3(kBlock), 0, s, g.back.off, g.back.col, h.rows,
+                               d_start, n, m, cnt);
+            hipLaunchKernelGGL(k_hot_cost, dim3(grid_for(nc)), dim3(kBlock), 0, s, cnt, g.n_u, cost);
+            exclusive_scan_u64(cost, cost, nc, part, s);
+            hipLaunchKernelGGL(k_chunk_bounds, dim3(grid_for(h.n_chunks + 1)), dim3(kBlock), 0, s, cost, g.n_u,
+                               h.n_chunks, h.chunk_start);
+            check_hip(hipGetLastError(), "hot chunks launch");
+            check_hip(hipStreamSynchronize(s), "hot chunks");
+        }
+        // Blocks of kHotBlockRows rows from each chunk's start.
+        std::vector<int64_t> cstart((size_t)h.n_chunks + 1), bbase((size_t)h.n_chunks + 1, 0);
+        check_hip(hipMemcpyAsync(cstart.data(), h.chunk_start, cstart.size() * 8, hipMemcpyDeviceToHost, s),
+                  "hot chunks");
         check_hip(hipStreamSynchronize(s), "hot chunks");
-        dfree(cnt);
-        dfree(cost);
-        dfree(part);
+        for (int c = 0; c < h.n_chunks; ++c)
+            bbase[c + 1] = bbase[c] + (cstart[c + 1] - cstart[c] + kHotBlockRows - 1) / kHotBlockRows;
+        h.n_blocks = bbase[h.n_chunks];
+        const int64_t n_seg = (int64_t)kHotWaves * h.n_blocks * kHotPerWave;
+        if (n_seg >= (int64_t)UINT32_MAX) throw Failure{-1, "ahpp_graph_load: too many hot-pass blocks"};
+        h.blk_base = (int64_t *)dev_alloc(g, bbase.size() * 8, "hot chunks");
+        check_hip(hipMemcpyAsync(h.blk_base, bbase.data(), bbase.size() * 8, hipMemcpyHostToDevice, s), "hot chunks");
+        hipLaunchKernelGGL(k_hot_entries, dim3(grid_for(m)), dim3(kBlock), 0, s, g.back.off, g.back.col, g.back.w,
+                           h.rows, d_start, n, m, (const int64_t *)h.chunk_start, (const int64_t *)h.blk_base,
+                           h.n_chunks, h.n_blocks, key, col, w);
+        check_hip(hipGetLastError(), "hot entries launch");
+        // Segments keep their entries in row order (a sort by row within the block first).
+        build_csr(g, h.list, n_seg, key, col, w, m, true, s, kHotBlockRows, false);
     }
-    // Blocks of kHotBlockRows rows from each chunk's start.
-    std::vector<int64_t> cstart((size_t)h.n_chunks + 1), bbase((size_t)h.n_chunks + 1, 0);
-    check_hip(hipMemcpyAsync(cstart.data(), h.chunk_start, cstart.size() * 8, hipMemcpyDeviceToHost, s), "hot chunks");
-    check_hip(hipStreamSynchronize(s), "hot chunks");
-    for (int c = 0; c < h.n_chunks; ++c)
-        bbase[c + 1] = bbase[c] + (cstart[c + 1] - cstart[c] + kHotBlockRows - 1) / kHotBlockRows;
-    h.n_blocks = bbase[h.n_chunks];
-    const int64_t n_seg = (int64_t)kHotWaves * h.n_blocks * kHotPerWave;
-    if (n_seg >= (int64_t)UINT32_MAX) throw Failure{-1, "ahpp_graph_load: too many hot-pass blocks"};
-    h.blk_base = (int64_t *)dev_alloc(g, bbase.size() * 8, "hot chunks");
-    check_hip(hipMemcpyAsync(h.blk_base, bbase.data(), bbase.size() * 8, hipMemcpyHostToDevice, s), "hot chunks");
-    hipLaunchKernelGGL(k_hot_entries, dim3(grid_for(m)), dim3(kBlock), 0, s, g.back.off, g.back.col, g.back.w, h.rows,
-                       d_start, n, m, (const int64_t *)h.chunk_start, (const int64_t *)h.blk_base, h.n_chunks,
-                       h.n_blocks, key, col, w);
-    check_hip(hipGetLastError(), "hot entries launch");
-    // Segments keep their entries in row order (a sort by row within the block first).
-    build_csr(g, h.list, n_seg, key, col, w, m, true, s, kHotBlockRows, false);
-    dfree(d_start);
-    dfree(key);
-    dfree(col);
-    dfree(w);
     // Back schedule without the hot rows.
     std::vector<WorkItem> items;
     std::vector<SplitRow> split;
@@ -669,116 +653,109 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
                  const int32_t *aa, const float *aw, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
     const int64_t m_e = g.m_e, m_a = g.m_a, m = m_e + m_a;
-    // Upload COO.
-    int32_t *d_eu = nullptr, *d_ev = nullptr, *d_au = nullptr, *d_aa = nullptr;
-    float *d_ew = nullptr, *d_aw = nullptr;
-    unsigned *d_flags = nullptr;
-    auto up = [&](void **dst, const void *src, int64_t n, const char *what) {
-        if (n <= 0 || !src) return;
-        check_hip(hipMalloc(dst, (size_t)n * 4), what);
-        check_hip(hipMemcpyAsync(*dst, src, (size_t)n * 4, hipMemcpyHostToDevice, s), what);
-    };
-    up((void **)&d_eu, eu, m_e, "edge upload");
-    up((void **)&d_ev, ev, m_e, "edge upload");
-    up((void **)&d_ew, ew, m_e, "edge upload");
-    up((void **)&d_au, au, m_a, "assoc upload");
-    up((void **)&d_aa, aa, m_a, "assoc upload");
-    up((void **)&d_aw, aw, m_a, "assoc upload");
-    check_hip(hipMalloc(&d_flags, sizeof(unsigned)), "flags");
-    check_hip(hipMemsetAsync(d_flags, 0, sizeof(unsigned), s), "flags");
-    if (m_e > 0)
-        hipLaunchKernelGGL(k_validate, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_eu, d_ev, d_ew, m_e, g.n_u, g.n_v, 0,
-                           1, d_flags);
-    if (m_a > 0)
-        hipLaunchKernelGGL(k_validate, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_au, d_aa, d_aw, m_a, g.n_u, g.n_a, 2,
-                           3, d_flags);
-    unsigned flags = 0;
-    check_hip(hipMemcpyAsync(&flags, d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, s), "flags D2H");
-    check_hip(hipStreamSynchronize(s), "validation");
-    dfree(d_flags);
-    auto release = [&]() {
-        dfree(d_eu); dfree(d_ev); dfree(d_ew); dfree(d_au); dfree(d_aa); dfree(d_aw);
-    };
-    if (flags & 15u) {
-        release();
-        std::string msg = "ahpp_graph_load:";
-        if (flags & 1u) msg += " edge id out of range;";
-        if (flags & 2u) msg += " edge weight not positive and finite;";
-        if (flags & 4u) msg += " attribute association id out of range;";
-        if (flags & 8u) msg += " attribute value not positive and finite;";
-        throw Failure{-1, msg};
-    }
-    g.unit = !(flags & 16u);
+    {  // The COO upload and the entry scratch end with the block.
+        // Upload COO (a missing weight array means every weight is 1).
+        auto n_of = [](int64_t n, const void *src) { return (size_t)(src && n > 0 ? n : 0); };
+        DevTemp<int32_t> eu_(n_of(m_e, eu), "edge upload"), ev_(n_of(m_e, ev), "edge upload");
+        DevTemp<float> ew_(n_of(m_e, ew), "edge upload");
+        DevTemp<int32_t> au_(n_of(m_a, au), "assoc upload"), aa_(n_of(m_a, aa), "assoc upload");
+        DevTemp<float> aw_(n_of(m_a, aw), "assoc upload");
+        int32_t *d_eu = eu_.get(), *d_ev = ev_.get(), *d_au = au_.get(), *d_aa = aa_.get();
+        float *d_ew = ew_.get(), *d_aw = aw_.get();
+        auto up = [&](void *dst, const void *src, size_t n, const char *what) {
+            if (n) check_hip(hipMemcpyAsync(dst, src, n * 4, hipMemcpyHostToDevice, s), what);
+        };
+        up(d_eu, eu, n_of(m_e, eu), "edge upload");
+        up(d_ev, ev, n_of(m_e, ev), "edge upload");
+        up(d_ew, ew, n_of(m_e, ew), "edge upload");
+        up(d_au, au, n_of(m_a, au), "assoc upload");
+        up(d_aa, aa, n_of(m_a, aa), "assoc upload");
+        up(d_aw, aw, n_of(m_a, aw), "assoc upload");
+        DevTemp<unsigned> flags_(1, "flags");
+        unsigned *d_flags = flags_.get();
+        check_hip(hipMemsetAsync(d_flags, 0, sizeof(unsigned), s), "flags");
+        if (m_e > 0)
+            hipLaunchKernelGGL(k_validate, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_eu, d_ev, d_ew, m_e, g.n_u,
+                               g.n_v, 0, 1, d_flags);
+        if (m_a > 0)
+            hipLaunchKernelGGL(k_validate, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_au, d_aa, d_aw, m_a, g.n_u,
+                               g.n_a, 2, 3, d_flags);
+        unsigned flags = 0;
+        check_hip(hipMemcpyAsync(&flags, d_flags, sizeof(unsigned), hipMemcpyDeviceToHost, s), "flags D2H");
+        check_hip(hipStreamSynchronize(s), "validation");
+        if (flags & 15u) {
+            std::string msg = "ahpp_graph_load:";
+            if (flags & 1u) msg += " edge id out of range;";
+            if (flags & 2u) msg += " edge weight not positive and finite;";
+            if (flags & 4u) msg += " attribute association id out of range;";
+            if (flags & 8u) msg += " attribute value not positive and finite;";
+            throw Failure{-1, msg};
+        }
+        g.unit = !(flags & 16u);
 
-    // Device numbering of U, V and the attributes: by descending number of
-    // CSR entries that name the node, ties by input id.  The random gathers
-    // of a round then find the most referenced nodes packed together (more
-    // of them per cache line).  A V node without an edge is never read and
-    // never receives residue: it gets no row (it sorts last and is cut).
-    // Only U numbers leave the library, and they are mapped back on the way
-    // out (u_new, u_new_host).
-    g.n_v_input = g.n_v;
-    g.u_new = (int32_t *)dev_alloc(g, (size_t)g.n_u * 4, "U numbering");
-    number_by_count(g, g.n_u, {{d_eu, m_e}, {d_au, m_a}}, g.u_new, s);
-    int32_t *v_new = nullptr, *a_new = nullptr;
-    if (g.n_v > 0) check_hip(hipMalloc(&v_new, (size_t)g.n_v * 4), "V numbering");
-    if (g.n_a > 0) check_hip(hipMalloc(&a_new, (size_t)g.n_a * 4), "attribute numbering");
-    const int64_t v_rows = number_by_count(g, g.n_v, {{d_ev, m_e}}, v_new, s);
-    number_by_count(g, g.n_a, {{d_aa, m_a}}, a_new, s);
-    if (m_e > 0) {
-        hipLaunchKernelGGL(k_remap, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_eu, m_e, g.u_new);
-        hipLaunchKernelGGL(k_remap, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_ev, m_e, v_new);
-    }
-    if (m_a > 0) {
-        hipLaunchKernelGGL(k_remap, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_au, m_a, g.u_new);
-        hipLaunchKernelGGL(k_remap, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_aa, m_a, a_new);
-    }
-    check_hip(hipGetLastError(), "numbering launch");
-    g.u_new_host.resize((size_t)g.n_u);
-    check_hip(hipMemcpyAsync(g.u_new_host.data(), g.u_new, (size_t)g.n_u * 4, hipMemcpyDeviceToHost, s), "numbering");
-    check_hip(hipStreamSynchronize(s), "numbering");
-    dfree(v_new);
-    dfree(a_new);
-    g.n_v = v_rows;
+        // Device numbering of U, V and the attributes: by descending number of
+        // CSR entries that name the node, ties by input id.  The random gathers
+        // of a round then find the most referenced nodes packed together (more
+        // of them per cache line).  A V node without an edge is never read and
+        // never receives residue: it gets no row (it sorts last and is cut).
+        // Only U numbers leave the library, and they are mapped back on the way
+        // out (u_new, u_new_host).
+        g.n_v_input = g.n_v;
+        g.u_new = (int32_t *)dev_alloc(g, (size_t)g.n_u * 4, "U numbering");
+        number_by_count(g, g.n_u, {{d_eu, m_e}, {d_au, m_a}}, g.u_new, s);
+        DevTemp<int32_t> v_new_((size_t)std::max<int64_t>(g.n_v, 0), "V numbering");
+        DevTemp<int32_t> a_new_((size_t)std::max<int64_t>(g.n_a, 0), "attribute numbering");
+        int32_t *v_new = v_new_.get(), *a_new = a_new_.get();
+        const int64_t v_rows = number_by_count(g, g.n_v, {{d_ev, m_e}}, v_new, s);
+        number_by_count(g, g.n_a, {{d_aa, m_a}}, a_new, s);
+        if (m_e > 0) {
+            hipLaunchKernelGGL(k_remap, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_eu, m_e, g.u_new);
+            hipLaunchKernelGGL(k_remap, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_ev, m_e, v_new);
+        }
+        if (m_a > 0) {
+            hipLaunchKernelGGL(k_remap, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_au, m_a, g.u_new);
+            hipLaunchKernelGGL(k_remap, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_aa, m_a, a_new);
+        }
+        check_hip(hipGetLastError(), "numbering launch");
+        g.u_new_host.resize((size_t)g.n_u);
+        check_hip(hipMemcpyAsync(g.u_new_host.data(), g.u_new, (size_t)g.n_u * 4, hipMemcpyDeviceToHost, s),
+                  "numbering");
+        check_hip(hipStreamSynchronize(s), "numbering");
+        g.n_v = v_rows;
 
-    // Entries of both CSRs.
-    uint32_t *key = nullptr;
-    int32_t *col = nullptr;
-    float *w = nullptr;
-    if (m > 0) {
-        check_hip(hipMalloc(&key, (size_t)m * 4), "entries");
-        check_hip(hipMalloc(&col, (size_t)m * 4), "entries");
-        check_hip(hipMalloc(&w, (size_t)m * 4), "entries");
+        // Entries of both CSRs.
+        DevTemp<uint32_t> key_((size_t)m, "entries");
+        DevTemp<int32_t> col_((size_t)m, "entries");
+        DevTemp<float> w_((size_t)m, "entries");
+        uint32_t *key = key_.get();
+        int32_t *col = col_.get();
+        float *w = w_.get();
+        // fwd: rows U; edges (col v) then associations (col n_v + a).
+        if (m_e > 0)
+            hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_eu, d_ev, d_ew, m_e, 0, 0u,
+                               key, col, w);
+        if (m_a > 0)
+            hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_au, d_aa, d_aw, m_a,
+                               (int32_t)g.n_v, 0u, key + m_e, col + m_e, w + m_e);
+        build_csr(g, g.fwd, g.n_u, key, col, w, m, !g.unit, s, g.n_v + g.n_a);
+        // back: rows V then attributes (row n_v + a); columns are U ids.
+        if (m_e > 0)
+            hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_ev, d_eu, d_ew, m_e, 0, 0u,
+                               key, col, w);
+        if (m_a > 0)
+            hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_aa, d_au, d_aw, m_a, 0,
+                               (uint32_t)g.n_v, key + m_e, col + m_e, w + m_e);
+        build_csr(g, g.back, g.n_v + g.n_a, key, col, w, m, true, s, g.n_u);
     }
-    // fwd: rows U; edges (col v) then associations (col n_v + a).
-    if (m_e > 0)
-        hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_eu, d_ev, d_ew, m_e, 0, 0u, key,
-                           col, w);
-    if (m_a > 0)
-        hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_au, d_aa, d_aw, m_a,
-                           (int32_t)g.n_v, 0u, key + m_e, col + m_e, w + m_e);
-    build_csr(g, g.fwd, g.n_u, key, col, w, m, !g.unit, s, g.n_v + g.n_a);
-    // back: rows V then attributes (row n_v + a); columns are U ids.
-    if (m_e > 0)
-        hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_ev, d_eu, d_ew, m_e, 0, 0u, key,
-                           col, w);
-    if (m_a > 0)
-        hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_aa, d_au, d_aw, m_a, 0,
-                           (uint32_t)g.n_v, key + m_e, col + m_e, w + m_e);
-    build_csr(g, g.back, g.n_v + g.n_a, key, col, w, m, true, s, g.n_u);
-    dfree(key);
-    dfree(col);
-    dfree(w);
-    release();
 
     // Coefficients: 1/d(u), 1/s(u) in double, then inv_b and the back weights
     // w(u,x) * c(u) with c = (1-beta)(1-alpha)/d(u) or beta(1-alpha)/s(u).
     g.inv_b = (float *)dev_alloc(g, (size_t)std::max<int64_t>(g.n_v + g.n_a, 1) * 4, "inv_b");
-    double *cd = nullptr, *cs = nullptr;
-    unsigned long long *d_dang = nullptr;
-    check_hip(hipMalloc(&cd, (size_t)std::max<int64_t>(g.n_u, 1) * 8), "coefficients");
-    check_hip(hipMalloc(&cs, (size_t)std::max<int64_t>(g.n_u, 1) * 8), "coefficients");
-    check_hip(hipMalloc(&d_dang, 8), "dangling");
+    DevTemp<double> cd_((size_t)std::max<int64_t>(g.n_u, 1), "coefficients");
+    DevTemp<double> cs_((size_t)std::max<int64_t>(g.n_u, 1), "coefficients");
+    DevTemp<unsigned long long> dang_(1, "dangling");
+    double *cd = cd_.get(), *cs = cs_.get();
+    unsigned long long *d_dang = dang_.get();
     check_hip(hipMemsetAsync(d_dang, 0, 8, s), "dangling");
     hipLaunchKernelGGL(k_fwd_coeffs, dim3(grid_for(g.n_u * 64)), dim3(kBlock), 0, s, g.fwd.off, g.fwd.col, g.fwd.w,
                        g.n_u, g.n_v, g.alpha, g.beta, cd, cs, d_dang);
@@ -789,9 +766,6 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
     unsigned long long dang = 0;
     check_hip(hipMemcpyAsync(&dang, d_dang, 8, hipMemcpyDeviceToHost, s), "dangling D2H");
     check_hip(hipStreamSynchronize(s), "coefficients");
-    dfree(d_dang);
-    dfree(cd);
-    dfree(cs);
     g.dangling_u = (int64_t)dang;
     build_hot(g, s);
     g.load_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
