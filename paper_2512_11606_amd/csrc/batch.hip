@@ -499,11 +499,10 @@ struct HotBlock {
 // per-entry work is one 16-byte LDS read and four FMAs into a register row
 // known at compile time; rows with no entry cost nothing.  Each accumulator
 // has one owner and its adds are ordered by block and row, so the result is
-// deterministic.  Held to 64 VGPRs (8 waves per SIMD) so two workgroups share
-// a CU: a few registers spill, and the pass is still 6% faster than with one.
-__global__ void __launch_bounds__(kHotThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
-kb_hot(HotArgs a, const int64_t *__restrict__ hot_off, const int32_t *__restrict__ hot_col,
-       const float *__restrict__ hot_w) {
+// deterministic.
+__global__ void __launch_bounds__(kHotThreads) kb_hot(HotArgs a, const int64_t *__restrict__ hot_off,
+                                                      const int32_t *__restrict__ hot_col,
+                                                      const float *__restrict__ hot_w) {
     __shared__ float4 xs[2][kHotBlockRows * kTileQ / 4];
     const int t = blockIdx.y;
     const TileCtl &tc = a.ctl[t];
