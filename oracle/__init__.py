@@ -22,9 +22,11 @@ Pieces (each names the passage of arXiv 2512.11606 it follows):
 * ``topk``: the k most similar nodes (Exp-4/Exp-6 use of the scores).
 * ``check_query``: Theorem 2's bound and sign, mass conservation, top-k band.
 
-Parity unpinned: the exact intermediate values of ASRP (iteration counts,
-n_p, the phase-switch round) have no printed trace in the paper; only the
-final guarantee (Theorem 2) and the invariant (Lemma 2) are pinned.
+Parity unpinned: the exact intermediate values of ASRP, of Exp-2's other
+schedules and of FP (iteration or push counts, n_p, the phase-switch round)
+have no printed trace in the paper; only the final guarantees (Theorem 2,
+and the per-node thresholds for APP / APP(S) / FP) and the invariant
+(Lemma 2, after every round or push) are pinned.
 """
 
 from __future__ import annotations
