@@ -68,6 +68,17 @@ def _traffic(kernel_kind_name):
     return d.get("bytes_per_launch")
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(g, sources, eps):
     """The oracle's FP64 ASRP (lambda from Theorem 3) on the host cores: one
     query on one thread (latency), then one query per thread on every thread
@@ -83,7 +94,7 @@ def cpu_baseline(g, sources, eps):
     _, _, bad = og.asrp_many(sources[:nth], eps, lam, nthreads=nth)
     dtn = time.perf_counter() - t0
     return {"value": nth / dtn, "unit": "queries/s", "cores": nth, "kind": "oracle",
-            "single_thread_ms": round(dt1 * 1e3, 1),
+            "host_cpus": os.cpu_count(), "cpu_model": _cpu_model(), "single_thread_ms": round(dt1 * 1e3, 1),
             "sample": f"{nth} full FP64 ASRP queries (sources proportional to degree, eps {eps:g}, lambda from "
                       f"Theorem 3) on the same graph, one per thread on {nth} threads, {dtn:.1f} s; one of them "
                       f"alone on 1 thread: {dt1:.1f} s, {st.iterations} rounds"}
