@@ -302,6 +302,10 @@ def main():
     g = synth.make_graph(args.graph)
     dg = ahpp.load_graph(g, device=0)
     torch.cuda.synchronize()
+    ginfo = ahpp.ahpp_graph_info(dg)
+    graph_load = {"build_ms": round(ginfo["load_ms"], 1), "lambda_ms": round(ginfo["lambda_ms"], 1),
+                  "lambda_iters": ginfo["lambda_iters"], "device_bytes": ginfo["device_bytes"],
+                  "note": "host COO to device CSR, numbering, hot lists and Theorem 3 lambda; outside the timed steps"}
     sources = synth.mixed_batch_queries(g, args.batch, 2002)
     tuned = None if args.no_tune else ahpp.ahpp_graph_tune(dg, max_tiles=max(1, args.batch // 256))
 
@@ -379,6 +383,7 @@ def main():
         "plain_latency_ms_p99": round(_percentile(lat, 99), 2),
         "batched_over_plain": round(value / plain_qps, 2),
         "topk_complete": topk_ok,
+        "graph_load": graph_load,
         "tuned_schedule": tuned,
         "serving": serving,
         "plain_tiny": plain_tiny,
