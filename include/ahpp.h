@@ -77,14 +77,14 @@ typedef struct {
 } ahpp_graph_desc_t;
 
 typedef struct {
-    int64_t n_u, n_v, n_attr, n_edges, n_assoc;
+    int64_t n_u, n_v, n_attr, n_edges, n_assoc;  /* as passed to ahpp_graph_load */
     double alpha, beta;
     double lambda;              /* the value eps is divided by (Algorithm 4)   */
     int32_t lambda_iters;       /* rounds used by Theorem 3 (0 if overridden)  */
     int32_t device;
     int64_t dangling_u;         /* U nodes with no edge or no attribute        */
     int64_t device_bytes;       /* device memory held by the graph            */
-    double load_ms, lambda_ms;  /* wall time of the CSR build and of Eq. 6     */
+    double load_ms, lambda_ms;  /* wall time of the build and of Eq. 6         */
 } ahpp_graph_info_t;
 
 /* Per-query statistics.  n_push counts edge visits as Algorithm 4 counts n_p
@@ -104,8 +104,11 @@ typedef struct {
 
 /* Builds the graph on the device: the CSR of U -> (V and attributes) and of
  * (V and attributes) -> U, the normalisers d(u), d(v), s(u), t(a) of Eq. 1 and
- * Eq. 2, the push schedules, and lambda (Theorem 3, Eq. 6).
- * Synchronous.  On success *out owns all device memory of the graph.
+ * Eq. 2, the push schedules, and lambda (Theorem 3, Eq. 6).  The device
+ * numbers nodes by how often the CSRs name them and drops V nodes without an
+ * edge; every id the API takes or returns is the caller's.
+ * Synchronous.  On success *out owns all device memory of the graph; a
+ * failed load frees everything it allocated.
  * Errors: INVALID_ARG (sizes < 0, ids out of range, weights <= 0 or not
  * finite, alpha or beta out of range, out == NULL), OUT_OF_MEMORY, DEVICE. */
 ahpp_status_t ahpp_graph_load(const ahpp_graph_desc_t *desc, ahpp_graph_t **out);
