@@ -351,8 +351,20 @@ __global__ void __launch_bounds__(kBlock) kb_fix(BArgs a) {
     for (int64_t i = wave0; i < a.n_split; i += stride) {
         const SplitRow sr = a.split[i];
         QV s = qv_zero();
-        for (int ch = 0; ch < sr.nch; ++ch) {
-            const QV p = qv_load(part + (int64_t)(sr.first_item + ch) * kTileQ + lane_col());
+        const float *pr = part + (int64_t)sr.first_item * kTileQ + lane_col();
+        int ch = 0;
+        // Eight chunk loads in flight, added in chunk order.
+        for (; ch + 8 <= sr.nch; ch += 8) {
+            QV p[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) p[u] = qv_load(pr + (int64_t)(ch + u) * kTileQ);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int j = 0; j < kVec; ++j) s.v[j] += p[u].v[j];
+        }
+        for (; ch < sr.nch; ++ch) {
+            const QV p = qv_load(pr + (int64_t)ch * kTileQ);
 #pragma unroll
             for (int j = 0; j < kVec; ++j) s.v[j] += p.v[j];
         }
