@@ -42,8 +42,8 @@ typedef struct ahpp_graph ahpp_graph_t;
 typedef enum {
     AHPP_OK = 0,
     AHPP_ERR_INVALID_ARG = -1,   /* bad id, weight, parameter or size          */
-    AHPP_ERR_OUT_OF_MEMORY = -2, /* device allocation failed                    */
-    AHPP_ERR_DEVICE = -3,        /* a HIP runtime call failed                   */
+    AHPP_ERR_OUT_OF_MEMORY = -2, /* device or host allocation failed            */
+    AHPP_ERR_DEVICE = -3,        /* a HIP runtime call failed, or internal error */
     AHPP_ERR_NOT_CONVERGED = -4  /* max_iters rounds ran before the stop rule   */
 } ahpp_status_t;
 

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 
@@ -31,6 +32,44 @@ ahpp_status_t fail(int status, const std::string &msg) {
     g_last_error = msg;
     return (ahpp_status_t)status;
 }
+
+// Runs the body of an entry point and turns every exception into a status,
+// so that none unwinds through the C ABI.
+template <class F>
+ahpp_status_t guarded(const char *fn, F &&body) {
+    try {
+        return body();
+    } catch (const Failure &f) {
+        return fail(f.status, f.msg);
+    } catch (const std::bad_alloc &) {
+        return fail(AHPP_ERR_OUT_OF_MEMORY, std::string(fn) + ": host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(AHPP_ERR_DEVICE, std::string(fn) + ": internal error: " + e.what());
+    } catch (...) {
+        return fail(AHPP_ERR_DEVICE, std::string(fn) + ": internal error");
+    }
+}
+
+// A start/stop event pair for timing a call on its stream; destroyed with
+// the object, also when the call fails half way.
+struct EventPair {
+    hipEvent_t start = nullptr, stop = nullptr;
+    EventPair() {
+        check_hip(hipEventCreate(&start), "event");
+        check_hip(hipEventCreate(&stop), "event");
+    }
+    ~EventPair() {
+        if (start) (void)hipEventDestroy(start);
+        if (stop) (void)hipEventDestroy(stop);
+    }
+    EventPair(const EventPair &) = delete;
+    EventPair &operator=(const EventPair &) = delete;
+    float elapsed_ms() const {
+        float ms = 0.0f;
+        check_hip(hipEventElapsedTime(&ms, start, stop), "event");
+        return ms;
+    }
+};
 
 // Makes `dev` current for the lifetime of the object, restoring the
 // caller's device afterwards.
@@ -207,20 +246,13 @@ ahpp_status_t ahpp_server_create(ahpp_graph_t *h, int64_t max_device_bytes, int3
     if (!h || !out) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_create: NULL argument");
     *out = nullptr;
     if (k < 1 || k > kMaxTopK) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_create: k must be in [1, 2048]");
-    ahpp_server *srv = new (std::nothrow) ahpp_server{nullptr};
-    if (!srv) return fail(AHPP_ERR_OUT_OF_MEMORY, "ahpp_server_create: host allocation failed");
-    try {
+    return guarded("ahpp_server_create", [&] {
         DeviceScope scope(h->g.device);
-        srv->impl = new Server(h->g, max_device_bytes, max_slots, k, max_iters, keep_pi != 0);
-    } catch (const Failure &f) {
-        delete srv;
-        return fail(f.status, f.msg);
-    } catch (const std::exception &e) {
-        delete srv;
-        return fail(AHPP_ERR_OUT_OF_MEMORY, std::string("ahpp_server_create: ") + e.what());
-    }
-    *out = srv;
-    return AHPP_OK;
+        std::unique_ptr<Server> impl(new Server(h->g, max_device_bytes, max_slots, k, max_iters, keep_pi != 0));
+        *out = new ahpp_server{impl.get()};
+        impl.release();
+        return AHPP_OK;
+    });
 }
 
 void ahpp_server_free(ahpp_server_t *srv) {
@@ -242,26 +274,22 @@ ahpp_status_t ahpp_server_submit(ahpp_server_t *srv, int64_t tag, int32_t source
     if (source < 0 || source >= srv->impl->graph().n_u)
         return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_submit: source out of range");
     if (!(eps > 0.0) || std::isinf(eps)) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_submit: eps must be > 0");
-    try {
+    return guarded("ahpp_server_submit", [&] {
         srv->impl->submit(tag, source, eps);
-    } catch (const std::exception &e) {
-        return fail(AHPP_ERR_OUT_OF_MEMORY, std::string("ahpp_server_submit: ") + e.what());
-    }
-    return AHPP_OK;
+        return AHPP_OK;
+    });
 }
 
 ahpp_status_t ahpp_server_step(ahpp_server_t *srv, int32_t rounds, int32_t *n_ready, void *hip_stream) {
     g_last_error.clear();
     if (!srv || !srv->impl) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_step: NULL server");
     if (rounds < 0) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_step: rounds < 0");
-    try {
+    return guarded("ahpp_server_step", [&] {
         DeviceScope scope(srv->impl->graph().device);
         const int n = srv->impl->step(rounds, (hipStream_t)hip_stream);
         if (n_ready) *n_ready = n;
-    } catch (const Failure &f) {
-        return fail(f.status, f.msg);
-    }
-    return AHPP_OK;
+        return AHPP_OK;
+    });
 }
 
 ahpp_status_t ahpp_server_results(ahpp_server_t *srv, int32_t max_n, int64_t *tags, int32_t *topk_idx,
@@ -270,13 +298,11 @@ ahpp_status_t ahpp_server_results(ahpp_server_t *srv, int32_t max_n, int64_t *ta
     g_last_error.clear();
     if (!srv || !srv->impl || !n_out) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_results: NULL argument");
     if (max_n < 0) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_results: max_n < 0");
-    try {
+    return guarded("ahpp_server_results", [&] {
         DeviceScope scope(srv->impl->graph().device);
         *n_out = srv->impl->results(max_n, tags, topk_idx, topk_val, topk_n, stats, pi_out, (hipStream_t)hip_stream);
-    } catch (const Failure &f) {
-        return fail(f.status, f.msg);
-    }
-    return AHPP_OK;
+        return AHPP_OK;
+    });
 }
 
 ahpp_status_t ahpp_server_info(const ahpp_server_t *srv, int32_t *slots, int32_t *running, int32_t *queued,
@@ -291,31 +317,27 @@ ahpp_status_t ahpp_graph_tune(ahpp_graph_t *h, int32_t max_tiles, ahpp_tune_info
     g_last_error.clear();
     if (!h) return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_tune: NULL graph");
     Graph &g = h->g;
-    try {
+    return guarded("ahpp_graph_tune", [&] {
         DeviceScope scope(g.device);
         int cap = batch_tiles_fit(g);
         if (max_tiles > 0) cap = std::min(cap, (int)max_tiles);
         const TuneResult r = batch_tune(g, cap, (hipStream_t)hip_stream);
         if (out) *out = ahpp_tune_info_t{r.tiles, r.wg_mult, r.candidates, 0, r.ms_per_tile_round,
                                          r.default_ms_per_tile_round};
-    } catch (const Failure &f) {
-        return fail(f.status, f.msg);
-    } catch (const std::exception &e) {
-        return fail(AHPP_ERR_OUT_OF_MEMORY, std::string("ahpp_graph_tune: ") + e.what());
-    }
-    return AHPP_OK;
+        return AHPP_OK;
+    });
 }
 
 ahpp_status_t ahpp_profile_enable(ahpp_graph_t *h, int32_t on) {
     g_last_error.clear();
     if (!h) return fail(AHPP_ERR_INVALID_ARG, "ahpp_profile_enable: NULL graph");
     Profiler &p = h->g.prof;
-    try {
+    const ahpp_status_t rc = guarded("ahpp_profile_enable", [&] {
         DeviceScope scope(h->g.device);
         profiler_flush(p);
-    } catch (const Failure &f) {
-        return fail(f.status, f.msg);
-    }
+        return AHPP_OK;
+    });
+    if (rc != AHPP_OK) return rc;
     if (on) {
         for (int k = 0; k < kProfKinds; ++k) {
             p.launches[k] = 0;
@@ -333,12 +355,12 @@ ahpp_status_t ahpp_profile_read(ahpp_graph_t *h, int32_t kind, int64_t *launches
     if (!h) return fail(AHPP_ERR_INVALID_ARG, "ahpp_profile_read: NULL graph");
     if (kind < 0 || kind >= kProfKinds) return fail(AHPP_ERR_INVALID_ARG, "ahpp_profile_read: bad kind");
     Profiler &p = h->g.prof;
-    try {
+    const ahpp_status_t rc = guarded("ahpp_profile_read", [&] {
         DeviceScope scope(h->g.device);
         profiler_flush(p);
-    } catch (const Failure &f) {
-        return fail(f.status, f.msg);
-    }
+        return AHPP_OK;
+    });
+    if (rc != AHPP_OK) return rc;
     if (launches) *launches = p.launches[kind];
     if (total_ms) *total_ms = p.ms[kind];
     if (algo_bytes) *algo_bytes = p.bytes[kind];
@@ -364,9 +386,9 @@ ahpp_status_t ahpp_graph_load(const ahpp_graph_desc_t *d, ahpp_graph_t **out) {
     if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev <= 0)
         return fail(AHPP_ERR_DEVICE, "ahpp_graph_load: no HIP device");
     if (d->device < 0 || d->device >= n_dev) return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: bad device ordinal");
-    ahpp_graph *h = new (std::nothrow) ahpp_graph();
-    if (!h) return fail(AHPP_ERR_OUT_OF_MEMORY, "ahpp_graph_load: host allocation failed");
-    Graph &g = h->g;
+    std::unique_ptr<ahpp_graph> hp(new (std::nothrow) ahpp_graph());
+    if (!hp) return fail(AHPP_ERR_OUT_OF_MEMORY, "ahpp_graph_load: host allocation failed");
+    Graph &g = hp->g;
     g.device = d->device;
     g.n_u = d->n_u;
     g.n_v = d->n_v;
@@ -376,7 +398,7 @@ ahpp_status_t ahpp_graph_load(const ahpp_graph_desc_t *d, ahpp_graph_t **out) {
     g.alpha = d->alpha;
     g.beta = d->beta;
     hipStream_t s = nullptr;
-    try {
+    const ahpp_status_t rc = guarded("ahpp_graph_load", [&] {
         DeviceScope scope(g.device);
         check_hip(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "stream");
         int n_cu = 0;
@@ -398,18 +420,21 @@ ahpp_status_t ahpp_graph_load(const ahpp_graph_desc_t *d, ahpp_graph_t **out) {
         check_hip(hipStreamSynchronize(s), "load");
         check_hip(hipStreamDestroy(s), "stream");
         s = nullptr;
-    } catch (const Failure &f) {
-        if (s) (void)hipStreamDestroy(s);
-        free_graph(g);
-        delete h;
-        return fail(f.status, f.msg);
-    } catch (const std::exception &e) {
-        if (s) (void)hipStreamDestroy(s);
-        free_graph(g);
-        delete h;
-        return fail(AHPP_ERR_OUT_OF_MEMORY, std::string("ahpp_graph_load: ") + e.what());
+        return AHPP_OK;
+    });
+    if (rc != AHPP_OK) {
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+        try {
+            DeviceScope scope(g.device);
+            free_graph(g);
+        } catch (...) {
+        }
+        return rc;
     }
-    *out = h;
+    *out = hp.release();
     return AHPP_OK;
 }
 
@@ -463,12 +488,10 @@ ahpp_status_t query_impl(const char *name, ahpp_graph_t *h, int32_t source, doub
     if (max_iters <= 0) max_iters = 100000;
     hipStream_t s = (hipStream_t)hip_stream;
     int32_t status = 0;
-    try {
+    const ahpp_status_t rc = guarded(name, [&] {
         DeviceScope scope(g.device);
-        hipEvent_t e0, e1;
-        check_hip(hipEventCreate(&e0), "event");
-        check_hip(hipEventCreate(&e1), "event");
-        check_hip(hipEventRecord(e0, s), "event");
+        EventPair ev;
+        check_hip(hipEventRecord(ev.start, s), "event");
         const float eps_f = (float)(eps / g.lambda);
         const int32_t src = g.u_new_host[(size_t)source];
         single_query_init(g, src, eps_f, max_iters, s, schedule, (float)(eps / (double)(g.m_e + g.m_a)));
@@ -478,15 +501,12 @@ ahpp_status_t query_impl(const char *name, ahpp_graph_t *h, int32_t source, doub
         if (scores) to_input_order(g, g.q_pi, scores, s);
         if (k > 0) topk_launch(scores, g.n_u, 0, 1, nullptr, source, k, topk_idx, topk_val, topk_n, g.tk_scratch, s);
         if (resid_out) to_input_order(g, g.q_r, resid_out, s);
-        check_hip(hipEventRecord(e1, s), "event");
+        check_hip(hipEventRecord(ev.stop, s), "event");
         Control ctl;
         check_hip(hipMemcpyAsync(&ctl, g.q_ctl, sizeof(Control), hipMemcpyDeviceToHost, s), "control D2H");
         check_hip(hipStreamSynchronize(s), "query");
         status = ctl.status;
-        float ms = 0.0f;
-        check_hip(hipEventElapsedTime(&ms, e0, e1), "event");
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        const float ms = ev.elapsed_ms();
         if (stats) {
             double sum_r = 0.0;
             single_query_stats(g, &sum_r, s);
@@ -500,9 +520,9 @@ ahpp_status_t query_impl(const char *name, ahpp_graph_t *h, int32_t source, doub
             stats->ms = ms;
             stats->pad = 0;
         }
-    } catch (const Failure &f) {
-        return fail(f.status, f.msg);
-    }
+        return AHPP_OK;
+    });
+    if (rc != AHPP_OK) return rc;
     if (status != 1) return fail(AHPP_ERR_NOT_CONVERGED, fn + ": max_iters reached before the stop rule held");
     return AHPP_OK;
 }
@@ -534,30 +554,23 @@ ahpp_status_t ahpp_query_mc(ahpp_graph_t *h, int32_t source, int64_t n_walks, ui
     if (k > 0 && (!topk_idx || !topk_val || !topk_n))
         return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_mc: top-k outputs required when k > 0");
     hipStream_t s = (hipStream_t)hip_stream;
-    try {
+    return guarded("ahpp_query_mc", [&] {
         DeviceScope scope(g.device);
         ensure_mc_tables(g, s);
-        hipEvent_t e0, e1;
-        check_hip(hipEventCreate(&e0), "event");
-        check_hip(hipEventCreate(&e1), "event");
-        check_hip(hipEventRecord(e0, s), "event");
+        EventPair ev;
+        check_hip(hipEventRecord(ev.start, s), "event");
         // Counts in the residue buffer, scores in the reserve buffer.
         unsigned *count = reinterpret_cast<unsigned *>(g.q_r);
         const McResult r = mc_walks(g, g.u_new_host[(size_t)source], n_walks, seed, 4096, count, s);
         float *scores = pi_out ? pi_out : g.q_pi;
         mc_scores(count, g.u_new, g.n_u, n_walks, scores, s);
         if (k > 0) topk_launch(scores, g.n_u, 0, 1, nullptr, source, k, topk_idx, topk_val, topk_n, g.tk_scratch, s);
-        check_hip(hipEventRecord(e1, s), "event");
+        check_hip(hipEventRecord(ev.stop, s), "event");
         check_hip(hipStreamSynchronize(s), "walks");
-        float ms = 0.0f;
-        check_hip(hipEventElapsedTime(&ms, e0, e1), "event");
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        const float ms = ev.elapsed_ms();
         if (stats) *stats = ahpp_mc_stats_t{n_walks, r.lost, r.truncated, r.steps, ms, 0.0f};
-    } catch (const Failure &f) {
-        return fail(f.status, f.msg);
-    }
-    return AHPP_OK;
+        return AHPP_OK;
+    });
 }
 
 ahpp_status_t ahpp_query_batch(ahpp_graph_t *h, int32_t n_q, const int32_t *sources, const double *eps,
@@ -579,7 +592,7 @@ ahpp_status_t ahpp_query_batch(ahpp_graph_t *h, int32_t n_q, const int32_t *sour
     if (max_iters <= 0) max_iters = 100000;
     hipStream_t s = (hipStream_t)hip_stream;
     bool all_converged = true;
-    try {
+    const ahpp_status_t rc = guarded("ahpp_query_batch", [&] {
         DeviceScope scope(g.device);
         const int tiles_total = (int)((n_q + kTileQ - 1) / kTileQ);
         const int tif = std::min(tiles_total, batch_tiles_in_flight(g));
@@ -588,13 +601,19 @@ ahpp_status_t ahpp_query_batch(ahpp_graph_t *h, int32_t n_q, const int32_t *sour
         if (k > 0) ensure_topk_scratch(g, (int64_t)tif * kTileQ);
         std::vector<float> eps_f((size_t)n_q);
         for (int32_t q = 0; q < n_q; ++q) eps_f[q] = (float)(eps[q] / g.lambda);
-        int32_t *d_src = nullptr;
-        check_hip(hipMallocAsync((void **)&d_src, (size_t)n_q * 4, s), "batch sources");
-        check_hip(hipMemcpyAsync(d_src, sources, (size_t)n_q * 4, hipMemcpyHostToDevice, s), "batch sources");
-        hipEvent_t e0, e1;
-        check_hip(hipEventCreate(&e0), "event");
-        check_hip(hipEventCreate(&e1), "event");
-        check_hip(hipEventRecord(e0, s), "event");
+        // Sources on the device for the top-k's exclusion; freed in stream
+        // order when the call ends, also on failure.
+        struct StreamBuf {
+            int32_t *p = nullptr;
+            hipStream_t s;
+            ~StreamBuf() {
+                if (p) (void)hipFreeAsync(p, s);
+            }
+        } d_src{nullptr, s};
+        check_hip(hipMallocAsync((void **)&d_src.p, (size_t)n_q * 4, s), "batch sources");
+        check_hip(hipMemcpyAsync(d_src.p, sources, (size_t)n_q * 4, hipMemcpyHostToDevice, s), "batch sources");
+        EventPair ev;
+        check_hip(hipEventRecord(ev.start, s), "event");
         std::vector<TileCtl> ctl((size_t)tif);
         std::vector<double> sums((size_t)tif * kTileQ);
         std::vector<ahpp_stats_t> st_all(stats ? (size_t)n_q : 0);
@@ -635,7 +654,7 @@ ahpp_status_t ahpp_query_batch(ahpp_graph_t *h, int32_t n_q, const int32_t *sour
             float *scores = pi_out ? pi_out + q0 * g.n_u : g.batch.out;
             batch_scores(g, g.batch, nt, nq, scores, s);
             if (k > 0)
-                topk_launch(scores, g.n_u, g.n_u, nq, d_src + q0, -1, k, topk_idx + q0 * k, topk_val + q0 * k,
+                topk_launch(scores, g.n_u, g.n_u, nq, d_src.p + q0, -1, k, topk_idx + q0 * k, topk_val + q0 * k,
                             topk_n + q0, g.tk_scratch, s);
             for (int64_t q = 0; q < nq; ++q) {
                 const QueryCtl &c = ctl[q / kTileQ].q[q % kTileQ];
@@ -657,21 +676,20 @@ ahpp_status_t ahpp_query_batch(ahpp_graph_t *h, int32_t n_q, const int32_t *sour
                 }
             }
         }
-        check_hip(hipEventRecord(e1, s), "event");
-        check_hip(hipFreeAsync(d_src, s), "batch sources");
+        check_hip(hipEventRecord(ev.stop, s), "event");
+        int32_t *src_dev = d_src.p;
+        d_src.p = nullptr;
+        check_hip(hipFreeAsync(src_dev, s), "batch sources");
         check_hip(hipStreamSynchronize(s), "batch");
-        float ms = 0.0f;
-        check_hip(hipEventElapsedTime(&ms, e0, e1), "event");
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        const float ms = ev.elapsed_ms();
         if (stats)
             for (int32_t q = 0; q < n_q; ++q) {
                 st_all[q].ms = ms;
                 stats[q] = st_all[q];
             }
-    } catch (const Failure &f) {
-        return fail(f.status, f.msg);
-    }
+        return AHPP_OK;
+    });
+    if (rc != AHPP_OK) return rc;
     if (!all_converged) return fail(AHPP_ERR_NOT_CONVERGED, "ahpp_query_batch: some query reached max_iters");
     return AHPP_OK;
 }
@@ -684,14 +702,12 @@ ahpp_status_t ahpp_topk(const ahpp_graph_t *hc, const float *pi, int32_t k, int3
     Graph &g = h->g;
     if (k < 1 || k > kMaxTopK) return fail(AHPP_ERR_INVALID_ARG, "ahpp_topk: k must be in [1, 2048]");
     if (exclude < -1 || exclude >= g.n_u) return fail(AHPP_ERR_INVALID_ARG, "ahpp_topk: exclude out of range");
-    try {
+    return guarded("ahpp_topk", [&] {
         DeviceScope scope(g.device);
         topk_launch(pi, g.n_u, 0, 1, nullptr, exclude, k, idx_out, val_out, n_out, g.tk_scratch,
                     (hipStream_t)hip_stream);
-    } catch (const Failure &f) {
-        return fail(f.status, f.msg);
-    }
-    return AHPP_OK;
+        return AHPP_OK;
+    });
 }
 
 }  // extern "C"
