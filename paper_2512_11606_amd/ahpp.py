@@ -275,8 +275,9 @@ def ahpp_query_batch(g: Graph, sources: Sequence[int], eps, k: int = 0, max_iter
 def ahpp_topk(g: Graph, pi, k: int, exclude: int = -1, stream=None):
     """Top-k of a device score vector (torch float32 [n_u]): (idx, val, n) tensors."""
     import torch
-    if pi.dtype != torch.float32 or not pi.is_cuda or pi.numel() != g.n_u or not pi.is_contiguous():
-        raise ValueError("pi must be a contiguous float32 device tensor of length n_u")
+    if (pi.dtype != torch.float32 or not pi.is_cuda or pi.device.index != g.device or pi.numel() != g.n_u
+            or not pi.is_contiguous()):
+        raise ValueError("pi must be a contiguous float32 tensor of length n_u on the graph's device")
     ti = torch.empty(max(k, 1), dtype=torch.int32, device=pi.device)
     tv = torch.empty(max(k, 1), dtype=torch.float32, device=pi.device)
     tn = torch.empty(1, dtype=torch.int32, device=pi.device)
