@@ -133,7 +133,8 @@ struct BatchState {
 // kHotBlockRows rows, and adds every hot row's terms in registers (wave g
 // owns the hot rows h with h % kHotWaves == g, one lane per four query
 // columns, so each accumulator has one writer and the sum order is fixed),
-// then adds the chunk partials in chunk order.
+// then adds the chunk partials in chunk order.  The load places the rows on
+// hot indices so that the waves' entry totals are level.
 constexpr int kHotMax = 128;             // at most this many hot rows
 constexpr int kHotWaves = 16;            // waves of the streaming pass; wave g owns h % 16 == g
 constexpr int kHotPerWave = kHotMax / kHotWaves;  // hot rows (register accumulators) per wave

@@ -576,48 +576,60 @@ __global__ void __launch_bounds__(kHotThreads) kb_hot(HotArgs a, const int64_t *
             HotBlock nxt;
             load_block(nxt, b + 1, readlane_i64(cur.off, kHotPerWave));
             const float4 *xb = xs[buf];
-            // Entry k of the block: (row within the block, w').
-            auto entry = [&](int k, int &p, float &w) {
-                if (k < kWave) {
-                    p = __builtin_amdgcn_readlane(cur.p0, k);
-                    w = readlane_f(cur.w0, k);
-                } else if (k < kHotWindow) {
-                    p = __builtin_amdgcn_readlane(cur.p1, k - kWave);
-                    w = readlane_f(cur.w1, k - kWave);
-                } else {  // a block with more entries than the window: read them directly
-                    p = hot_col[e_b + k];
-                    w = hot_w[e_b + k];
-                }
-            };
             auto add = [&](float4 &s, float w, const float4 &x) {
                 s.x += w * x.x;
                 s.y += w * x.y;
                 s.z += w * x.z;
                 s.w += w * x.w;
             };
-#pragma unroll
-            for (int sg = 0; sg < kHotPerWave; ++sg) {
-                const int k0 = (int)(readlane_i64(cur.off, sg) - e_b);
-                const int k1 = (int)(readlane_i64(cur.off, sg + 1) - e_b);
-                int k = k0;
-                // Two entries at a time: both LDS reads are in flight before
-                // the adds, which keep the entry order (groups of four
-                // measured slower: most segments are short).
-                for (; k + 1 < k1; k += 2) {
+            // Entries ka .. kb-1 of the block into s, in order, two at a time
+            // (both LDS reads in flight before the adds; groups of four
+            // measured slower, most segments being short).  get(k, p, w)
+            // yields entry k: (row within the block, w').
+            auto run = [&](float4 &s, int ka, int kb, auto get) {
+                int k = ka;
+                for (; k + 1 < kb; k += 2) {
                     int pa, pb;
                     float wa, wb;
-                    entry(k, pa, wa);
-                    entry(k + 1, pb, wb);
+                    get(k, pa, wa);
+                    get(k + 1, pb, wb);
                     const float4 xa = xb[pa * (kTileQ / 4) + lane];
                     const float4 xc = xb[pb * (kTileQ / 4) + lane];
-                    add(acc[sg], wa, xa);
-                    add(acc[sg], wb, xc);
+                    add(s, wa, xa);
+                    add(s, wb, xc);
                 }
-                if (k < k1) {
+                if (k < kb) {
                     int p;
                     float w;
-                    entry(k, p, w);
-                    add(acc[sg], w, xb[p * (kTileQ / 4) + lane]);
+                    get(k, p, w);
+                    add(s, w, xb[p * (kTileQ / 4) + lane]);
+                }
+            };
+            // Segment bounds relative to the block's first entry: lane s of
+            // rel is where segment s starts (lanes 0 .. kHotPerWave used).
+            const int rel = (int)(cur.off - e_b);
+            int k1 = 0;
+#pragma unroll
+            for (int sg = 0; sg < kHotPerWave; ++sg) {
+                const int k0 = k1;
+                k1 = __builtin_amdgcn_readlane(rel, sg + 1);
+                // The segment's entries come from three places, taken as
+                // three ranges so the loops carry no per-entry branch: the
+                // first kWave entries of the block from lanes of p0/w0, the
+                // next kWave from p1/w1, any further ones from memory.
+                run(acc[sg], k0, min(k1, kWave), [&](int k, int &p, float &w) {
+                    p = __builtin_amdgcn_readlane(cur.p0, k);
+                    w = readlane_f(cur.w0, k);
+                });
+                if (k1 > kWave) {
+                    run(acc[sg], max(k0, kWave), min(k1, kHotWindow), [&](int k, int &p, float &w) {
+                        p = __builtin_amdgcn_readlane(cur.p1, k - kWave);
+                        w = readlane_f(cur.w1, k - kWave);
+                    });
+                    run(acc[sg], max(k0, kHotWindow), k1, [&](int k, int &p, float &w) {
+                        p = hot_col[e_b + k];
+                        w = hot_w[e_b + k];
+                    });
                 }
             }
             stage(buf ^ 1, nxt);

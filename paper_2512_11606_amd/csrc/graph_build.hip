@@ -554,11 +554,32 @@ void build_hot(Graph &g, hipStream_t s) {
     for (int64_t r = 0; r < n_rows; ++r)
         if (off[r + 1] - off[r] >= kHotMinLen) order.push_back((int32_t)r);
     if (order.empty()) return;
-    // Longest first, ties by row id; hot index h follows this order.
+    // Longest first, ties by row id.
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
     if ((int)order.size() > cap) order.resize(cap);
     const int n = (int)order.size();
+    // Hot index h belongs to wave h % kHotWaves (register row h / kHotWaves)
+    // of the streaming pass, whose blocks wait for their slowest wave.  The
+    // rows, longest first, take the free index of the wave with the fewest
+    // entries so far, which levels the waves' totals; each row keeps its own
+    // accumulator, so the sums do not change.
+    {
+        std::vector<int64_t> total(kHotWaves, 0);
+        std::vector<int> used(kHotWaves, 0);
+        std::vector<int32_t> placed((size_t)n, -1);
+        for (int i = 0; i < n; ++i) {
+            int best = -1;
+            for (int wv = 0; wv < kHotWaves; ++wv) {
+                if (wv + used[wv] * kHotWaves >= n) continue;  // no index of this wave left below n
+                if (best < 0 || total[wv] < total[best]) best = wv;
+            }
+            placed[(size_t)(best + used[best] * kHotWaves)] = order[i];
+            ++used[best];
+            total[best] += off[order[i] + 1] - off[order[i]];
+        }
+        order.swap(placed);
+    }
     std::vector<int32_t> len(n);
     std::vector<int64_t> start(n + 1, 0);
     std::vector<uint8_t> skip((size_t)n_rows, 0);
