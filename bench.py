@@ -37,7 +37,10 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILES = {"kb_gather<back>": os.path.join(ROOT, "profiles", "kb_gather_back_m1_traffic.json"),
                  "kb_gather<fwd>": os.path.join(ROOT, "profiles", "kb_gather_fwd_m1_traffic.json"),
                  "kb_hot": os.path.join(ROOT, "profiles", "kb_hot_m1_traffic.json")}
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2512_11606_amd", "csrc", "batch.hip")
+# The batched kernels and what fixes their schedules (constants, hot lists,
+# work items): a counter summary is used only if taken on these exact files.
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2512_11606_amd", "csrc", f)
+                  for f in ("batch.hip", "ahpp_internal.h", "graph_build.hip")]
 
 
 def _percentile(xs, p):
@@ -48,9 +51,12 @@ def _percentile(xs, p):
     return xs[i]
 
 
-def _source_hash(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def _source_hash(paths):
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _traffic(kernel_kind_name):
@@ -63,7 +69,7 @@ def _traffic(kernel_kind_name):
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if d.get("kernel") != kernel_kind_name or d.get("source_sha256_16") != _source_hash(KERNEL_SOURCE):
+    if d.get("kernel") != kernel_kind_name or d.get("source_sha256_16") != _source_hash(KERNEL_SOURCES):
         return None
     return d.get("bytes_per_launch")
 
