@@ -8,8 +8,12 @@
   device answer on the split graph meets Theorem 2 against the exact series of
   the original graph.
 * Walks stay in their component: on the disjoint union of two graphs a query
-  leaves every score and residue of the other component exactly zero, alone
-  and in a batch that mixes sources of both components.
+  leaves every score and residue of the other component exactly zero, alone,
+  in a batch that mixes sources of both components, under Exp-2's other
+  schedules and with the Monte Carlo estimator.
+The Monte Carlo walks keep the first two properties as well: bit for bit
+under power-of-two scaling with the same seed, and within the binomial band
+of the unsplit graph's exact row on the split one.
 """
 
 import types
@@ -62,6 +66,11 @@ def test_power_of_two_scaling_is_bitwise(env):
         assert torch.equal(ra.topk_idx, rb.topk_idx) and torch.equal(ra.topk_val, rb.topk_val), s
     ba, bb = A.ahpp_query_batch(a, srcs, 1e-7, k=40), A.ahpp_query_batch(b, srcs, 1e-7, k=40)
     assert torch.equal(ba.pi, bb.pi) and torch.equal(ba.topk_idx, bb.topk_idx)
+    # The walks draw against prefix sums of the raw weights, which scale
+    # exactly too: the same seed stops every walk at the same node.
+    ma = A.ahpp_query_mc(a, int(srcs[0]), 1_000_000, seed=3)
+    mb = A.ahpp_query_mc(b, int(srcs[0]), 1_000_000, seed=3)
+    assert torch.equal(ma["pi"], mb["pi"])
     a.free()
     b.free()
 
@@ -93,6 +102,14 @@ def test_repeated_pairs_equal_summed_weight(env):
         chk = O.check_query(exact, batch.pi[q].cpu().numpy().astype(np.float64), 1e-7, tol=TOL, k=30, source=s,
                             topk_ids=batch.topk_idx[q, : int(batch.topk_n[q].item())].cpu().numpy())
         assert chk.ok, (s, "batched", chk.detail)
+    # Walks on the split graph: every node within six standard deviations of
+    # the original graph's exact row (stop counts are binomial, Lemma 1).
+    s = int(srcs[0])
+    exact, _ = og.power_series(s)
+    n = 4_000_000
+    est = A.ahpp_query_mc(dh, s, n, seed=9)["pi"].cpu().numpy().astype(np.float64)
+    sd = np.sqrt(np.clip(exact * (1.0 - exact), 0.0, None) / n)
+    assert (np.abs(est - exact) <= 6.0 * sd + 3.0 / n).all()
     og.close()
     dh.free()
 
@@ -129,5 +146,11 @@ def test_disjoint_union_keeps_walks_apart(env):
         chk = O.check_query(exact, pi.astype(np.float64), 1e-7, tol=TOL, resid=r.astype(np.float64), k=25,
                             source=s, topk_ids=ids)
         assert chk.ok, (s, chk.detail)
+        # Exp-2's schedules and the walks stay in the component too.
+        for sch in (1, 3):
+            rs = A.ahpp_query_schedule(du, s, 1e-7, sch, want_resid=True)
+            assert np.all(rs.pi.cpu().numpy()[~own] == 0) and np.all(rs.resid.cpu().numpy()[~own] == 0), (s, sch)
+        mc = A.ahpp_query_mc(du, s, 500_000, seed=q)["pi"].cpu().numpy()
+        assert np.all(mc[~own] == 0) and mc[own].sum() > 0.99, s
     ou.close()
     du.free()
