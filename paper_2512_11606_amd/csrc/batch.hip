@@ -584,7 +584,7 @@ __global__ void __launch_bounds__(kHotThreads) kb_hot(HotArgs a, const int64_t *
             };
             // Entries ka .. kb-1 of the block into s, in order, two at a time
             // (both LDS reads in flight before the adds; groups of four
-            // measured slower, most segments being short).  get(k, p, w)
+            // measured no faster, most segments being short).  get(k, p, w)
             // yields entry k: (row within the block, w').
             auto run = [&](float4 &s, int ka, int kb, auto get) {
                 int k = ka;
