@@ -44,7 +44,11 @@ def run(server: "ahpp.Server", sources: Sequence[int], eps: Sequence[float], rat
             server.submit(nxt, int(sources[nxt]), float(eps[nxt]))
             nxt += 1
         info = server.info()
-        if info["running"] == 0 and info["queued"] == 0 and info["ready"] == 0 and nxt < n:
+        if info["running"] == 0 and info["queued"] == 0 and info["ready"] == 0:
+            if nxt == n:  # everything submitted, nothing left in the server
+                missing = sorted(set(range(n)) - set(finished))
+                raise RuntimeError(f"server finished without returning {len(missing)} queries "
+                                   f"(first tags {missing[:5]})")
             time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
             continue
         server.step(rounds_per_step)
