@@ -125,6 +125,19 @@ def _np_ptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
+def _as_i32(x, what: str) -> np.ndarray:
+    """Contiguous int32 copy of an id array; ids of a wider integer type must
+    fit, since a silent wrap could land on a valid id."""
+    a = np.asarray(x)
+    if a.dtype != np.int32:
+        if a.size and not np.issubdtype(a.dtype, np.integer):
+            raise ValueError(f"{what}: ids must be integers, got {a.dtype}")
+        if a.size and (int(a.min()) < np.iinfo(np.int32).min or int(a.max()) > np.iinfo(np.int32).max):
+            raise ValueError(f"{what}: ids outside the int32 range")
+        a = a.astype(np.int32)
+    return np.ascontiguousarray(a)
+
+
 def _dev_ptr(t) -> Optional[int]:
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
@@ -178,17 +191,15 @@ def ahpp_graph_load(n_u: int, n_v: int, n_attr: int, edge_u, edge_v, edge_w, ass
                     alpha: float = 0.15, beta: float = 0.35, lam: float = 0.0, lambda_iters: int = 0,
                     device: int = 0) -> Graph:
     """Loads COO lists (host arrays) onto `device`; see ahpp_graph_load in ahpp.h."""
-    lib = load_library()
-    eu = np.ascontiguousarray(edge_u, dtype=np.int32)
-    ev = np.ascontiguousarray(edge_v, dtype=np.int32)
+    eu, ev = _as_i32(edge_u, "edge_u"), _as_i32(edge_v, "edge_v")
     ew = None if edge_w is None else np.ascontiguousarray(edge_w, dtype=np.float32)
-    au = np.ascontiguousarray(assoc_u, dtype=np.int32)
-    aa = np.ascontiguousarray(assoc_a, dtype=np.int32)
+    au, aa = _as_i32(assoc_u, "assoc_u"), _as_i32(assoc_a, "assoc_a")
     aw = None if assoc_w is None else np.ascontiguousarray(assoc_w, dtype=np.float32)
     if eu.shape != ev.shape or (ew is not None and ew.shape != eu.shape):
         raise ValueError("edge arrays differ in length")
     if au.shape != aa.shape or (aw is not None and aw.shape != au.shape):
         raise ValueError("association arrays differ in length")
+    lib = load_library()
     d = GraphDesc(int(n_u), int(n_v), int(n_attr), int(eu.size), _np_ptr(eu), _np_ptr(ev), _np_ptr(ew),
                   int(au.size), _np_ptr(au), _np_ptr(aa), _np_ptr(aw), float(alpha), float(beta), float(lam),
                   int(lambda_iters), int(device))
@@ -256,7 +267,7 @@ def ahpp_query_batch(g: Graph, sources: Sequence[int], eps, k: int = 0, max_iter
                      want_stats: bool = True, stream=None, allow_not_converged: bool = False) -> QueryResult:
     """n_q queries answered together; row q of every output belongs to query q."""
     import torch
-    src = np.ascontiguousarray(sources, dtype=np.int32)
+    src = _as_i32(sources, "sources")
     n_q = int(src.size)
     e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (n_q,)))
     dev = torch.device("cuda", g.device)

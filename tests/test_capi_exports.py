@@ -67,3 +67,18 @@ def test_header_documents_each_entry_point():
         i = text.index(n + "(")
         block = text[max(0, i - 1500): i]
         assert "/*" in block, n
+
+
+def test_binding_refuses_ids_that_would_wrap():
+    """Ids given in a wider integer type must fit int32: a wrapped id could be
+    a valid node.  Checked before any call into the library."""
+    import numpy as np
+    from paper_2512_11606_amd import ahpp
+    big = np.array([0, 2 ** 32 + 1], np.int64)
+    ok = np.array([0, 1], np.int64)
+    with pytest.raises(ValueError, match="int32 range"):
+        ahpp.ahpp_graph_load(2, 2, 1, big, ok, None, ok, np.zeros(2, np.int64), None)
+    with pytest.raises(ValueError, match="integers"):
+        ahpp.ahpp_graph_load(2, 2, 1, ok.astype(np.float64), ok, None, ok, np.zeros(2, np.int64), None)
+    assert ahpp._as_i32([3, 4], "x").dtype == np.int32
+    assert ahpp._as_i32(np.arange(3, dtype=np.int32), "x").flags["C_CONTIGUOUS"]
