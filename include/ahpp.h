@@ -236,7 +236,8 @@ ahpp_status_t ahpp_server_info(const ahpp_server_t *s, int32_t *slots, int32_t *
  * a node with no edge (or no attribute) is lost, as the zero row of P loses
  * that mass.  Randomness: SplitMix64 streams keyed by `seed` and the walk
  * index; the counts, and so every output, depend only on the seed.
- *   n_walks: >= 1 (<= 2^40).  pi_out: device float[n_u] (nullable).
+ *   n_walks: 1 .. 2^32 - 1 (stop counts are 32-bit; no count can exceed
+ *            the walks).  pi_out: device float[n_u] (nullable).
  *   k, topk_idx / topk_val / topk_n: as in ahpp_query (device buffers,
  *   source excluded).  stats: host, nullable.
  * Uses the graph's single-query buffers: one call at a time per graph, as

@@ -423,19 +423,33 @@ def check_query(pi_exact: np.ndarray, pi_hat: np.ndarray, eps: float, tol: float
 
 
 def topk_band_ok(pi_exact: np.ndarray, got_ids: np.ndarray, k: int, delta: float, source: int = -1) -> bool:
-    ex = pi_exact.copy()
+    """Top-k acceptance band (the top-k use of the scores in Exp-6, Section 5.3).
+
+    With pi_(k) the exact k-th score (source left out) and delta the allowed
+    error of every score (Theorem 2's eps plus the float tolerance):
+    * at most k distinct ids, the source not among them;
+    * every node scoring above pi_(k) + 2 delta is listed, none below
+      pi_(k) - 2 delta (swaps inside the band are allowed);
+    * a list shorter than k names every node scoring above delta: such a
+      node's approximate score is above zero, so it was a candidate.
+    """
+    ex = np.asarray(pi_exact, dtype=np.float64).copy()
     if 0 <= source < ex.size:
         ex[source] = -np.inf
+    ids = [int(i) for i in np.asarray(got_ids).tolist()]
+    got = set(ids)
+    if len(got) != len(ids) or len(ids) > k:
+        return False
+    if source in got or any(i < 0 or i >= ex.size for i in got):
+        return False
     order = np.lexsort((np.arange(ex.size), -ex))
     kth = ex[order[min(k, ex.size) - 1]]
-    got = set(int(i) for i in got_ids.tolist())
-    if source in got:
-        return False
     must = np.nonzero(ex > kth + 2 * delta)[0]
     banned = np.nonzero((ex < kth - 2 * delta) & np.isfinite(ex))[0]
     if any(int(i) not in got for i in must):
         return False
     if any(int(i) in got for i in banned):
         return False
-    # Returned scores below or at zero are not allowed to pad the list.
-    return len(got) <= k
+    if len(ids) < k and any(int(i) not in got for i in np.nonzero(ex > delta)[0]):
+        return False
+    return True

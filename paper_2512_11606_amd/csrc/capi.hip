@@ -549,7 +549,10 @@ ahpp_status_t ahpp_query_mc(ahpp_graph_t *h, int32_t source, int64_t n_walks, ui
     if (!h) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_mc: NULL graph");
     Graph &g = h->g;
     if (source < 0 || source >= g.n_u) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_mc: source out of range");
-    if (n_walks < 1 || n_walks > (int64_t(1) << 40)) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_mc: n_walks out of range");
+    // Stop counts are 32-bit and no node collects more stops than there are
+    // walks, so n_walks <= 2^32 - 1 keeps every count exact.
+    if (n_walks < 1 || n_walks > (int64_t)UINT32_MAX)
+        return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_mc: n_walks must be in [1, 2^32 - 1]");
     if (k < 0 || k > kMaxTopK) return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_mc: k must be in [0, 2048]");
     if (k > 0 && (!topk_idx || !topk_val || !topk_n))
         return fail(AHPP_ERR_INVALID_ARG, "ahpp_query_mc: top-k outputs required when k > 0");

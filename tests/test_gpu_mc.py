@@ -106,3 +106,21 @@ def test_seed_determinism_and_dangling_loss(env):
     # The lost share equals the mass the exact series loses.
     assert abs(a["stats"]["lost"] / n - (1.0 - exact.sum())) < 6.0 * np.sqrt(0.25 / n)
     dg.free()
+
+
+def test_walk_count_limits(env):
+    """Stop counts are 32-bit: n_walks outside [1, 2^32 - 1] is refused before
+    any walk runs."""
+    ahpp, torch = env
+    g = synth.make_graph("tiny")
+    dg = ahpp.load_graph(g, device=0)
+    try:
+        for n in (0, 2 ** 32, 2 ** 40):
+            _say("walk count limit", n)
+            with pytest.raises(ahpp.AhppError) as e:
+                ahpp.ahpp_query_mc(dg, 3, n, seed=1)
+            assert e.value.status == -1
+        res = ahpp.ahpp_query_mc(dg, 3, 1000, seed=1)
+        assert res["stats"]["walks"] == 1000
+    finally:
+        dg.free()

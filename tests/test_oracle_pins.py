@@ -489,3 +489,53 @@ def test_missing_weights_mean_unit_weights():
     a, _ = O.OracleGraph.from_graph(g).power_series(1)
     b, _ = O.OracleGraph.from_graph(g0).power_series(1)
     assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- acceptance checks
+
+# Exact scores of a hand-made row (source 0): ranked without the source,
+# 1 (0.20) > 2 (0.15) > 4 (0.1000004) > 3 (0.10) > 5 (0.05) > 6 (0.01) > 7 (0).
+BAND_PI = np.array([0.5, 0.20, 0.15, 0.10, 0.1000004, 0.05, 0.01, 0.0])
+
+
+def test_topk_band_accepts_the_exact_list_and_swaps_inside_the_band():
+    # k = 3, delta = 1e-6: pi_(3) = 0.1000004, band [0.0999984, 0.1000024]
+    # holds nodes 3 and 4, so either may take the third place.
+    assert O.topk_band_ok(BAND_PI, np.array([1, 2, 4]), 3, 1e-6, source=0)
+    assert O.topk_band_ok(BAND_PI, np.array([1, 2, 3]), 3, 1e-6, source=0)
+    assert O.topk_band_ok(BAND_PI, np.array([2, 3, 1]), 3, 1e-6, source=0)
+    # A tighter delta puts node 3 below the band.
+    assert not O.topk_band_ok(BAND_PI, np.array([1, 2, 3]), 3, 1e-8, source=0)
+
+
+@pytest.mark.parametrize("ids,why", [
+    ([1, 4, 3], "node 2 scores above pi_(k) + 2 delta and is missing"),
+    ([1, 2, 5], "node 5 scores below pi_(k) - 2 delta"),
+    ([0, 1, 2], "the source is listed"),
+    ([1, 2, 4, 3], "more than k ids"),
+    ([1, 2, 2], "a repeated id"),
+    ([1, 2], "a short list that misses nodes scoring above delta"),
+    ([1, 2, 9], "an id outside U"),
+])
+def test_topk_band_rejects(ids, why):
+    assert not O.topk_band_ok(BAND_PI, np.array(ids), 3, 1e-6, source=0), why
+    assert not O.check_query(BAND_PI, BAND_PI, 1e-7, k=3, source=0, topk_ids=np.array(ids)).ok, why
+
+
+def test_topk_band_short_list_when_few_scores_are_positive():
+    # Only nodes 1 and 2 score above delta = 0.02 (node 6 scores 0.01 <= delta
+    # and may come out as zero); k = 6 then allows the list [1, 2, 4, 3, 5].
+    assert O.topk_band_ok(BAND_PI, np.array([1, 2, 4, 3, 5]), 6, 0.02, source=0)
+    assert not O.topk_band_ok(BAND_PI, np.array([1, 2, 4, 3]), 6, 1e-6, source=0)
+
+
+def test_check_query_rejects_a_mass_error(tiny_oracle, tiny_Pi):
+    """Lemma 2 (Eq. 5) summed over U: sum pi_hat + sum r = 1 without dangling nodes."""
+    pi_hat, r, _, _ = tiny_oracle.asrp(7, 1e-6, tiny_oracle.lambda_thm3())
+    chk = O.check_query(tiny_Pi[7], pi_hat, 1e-6, resid=r)
+    assert chk.ok and chk.mass_err < 1e-12
+    for d in (1e-4, -1e-4):
+        bad = r.copy()
+        bad[int(np.argmax(r))] += d
+        chk = O.check_query(tiny_Pi[7], pi_hat, 1e-6, resid=bad)
+        assert not chk.ok and chk.mass_err == pytest.approx(1e-4, rel=1e-6)
