@@ -141,6 +141,25 @@ ahpp_status_t ahpp_query(ahpp_graph_t *g, int32_t source, double eps, int32_t ma
                          int32_t k, int32_t *topk_idx, float *topk_val, int32_t *topk_n,
                          ahpp_stats_t *stats, void *hip_stream);
 
+/* ahpp_query for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result, bit for bit, but every per-query buffer
+ * lives in a fixed 64 MiB device array that the library holds on each GPU
+ * from graph load until the process ends, so the call makes no hipMalloc,
+ * hipFree, event or captured graph.
+ *   Arguments and outputs as ahpp_query (outputs are the caller's device
+ *   buffers, as there); stats->ms is the host wall time of the call.
+ *   Limit: the graph's query buffers (about 12 bytes per U node, 4 per V node
+ *   and attribute, plus partials; ~15 MB for 1M U nodes) must fit in 64 MiB,
+ *   else INVALID_ARG.
+ *   Every call on one GPU shares that GPU's array and finds it holding the
+ *   last call's contents (the call clears what must start at zero): calls
+ *   that overlap on one GPU, from any thread, graph or stream, race. */
+ahpp_status_t ahpp_query_noalloc(ahpp_graph_t *g, int32_t source, double eps, int32_t max_iters,
+                                 float *pi_out, float *resid_out,
+                                 int32_t k, int32_t *topk_idx, float *topk_val, int32_t *topk_n,
+                                 ahpp_stats_t *stats, void *hip_stream);
+
 /* The same query under the push schedules the paper compares in Exp-2
  * (the rounds of Algorithm 3 in every case):
  *   0 ASRP    Algorithm 4 (= ahpp_query).

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libahpp.so")
 
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CONVERGED = 0, -1, -2, -3, -4
 
-EXPORTED = ("ahpp_graph_load", "ahpp_graph_info", "ahpp_graph_free", "ahpp_query", "ahpp_query_schedule",
+EXPORTED = ("ahpp_graph_load", "ahpp_graph_info", "ahpp_graph_free", "ahpp_query", "ahpp_query_noalloc",
+            "ahpp_query_schedule",
             "ahpp_query_batch", "ahpp_topk",
             "ahpp_server_create", "ahpp_server_free", "ahpp_server_submit", "ahpp_server_step",
             "ahpp_server_results", "ahpp_server_info", "ahpp_graph_tune", "ahpp_query_mc", "ahpp_profile_enable",
@@ -83,6 +84,8 @@ def load_library(path: str = LIB_PATH):
     lib.ahpp_graph_free.argtypes = [P]
     lib.ahpp_query.restype = ctypes.c_int
     lib.ahpp_query.argtypes = [P, i32, dbl, i32, P, P, i32, P, P, P, P, P]
+    lib.ahpp_query_noalloc.restype = ctypes.c_int
+    lib.ahpp_query_noalloc.argtypes = [P, i32, dbl, i32, P, P, i32, P, P, P, P, P]
     lib.ahpp_query_batch.restype = ctypes.c_int
     lib.ahpp_query_batch.argtypes = [P, i32, P, P, i32, P, i32, P, P, P, P, P]
     lib.ahpp_topk.restype = ctypes.c_int
@@ -236,6 +239,28 @@ def ahpp_query(g: Graph, source: int, eps: float, k: int = 0, max_iters: int = 0
     status = _check(load_library().ahpp_query(g._h, int(source), float(eps), int(max_iters), _dev_ptr(pi),
                                               _dev_ptr(resid), int(k), _dev_ptr(ti), _dev_ptr(tv), _dev_ptr(tn),
                                               ctypes.byref(st) if want_stats else None, _stream(g.device, stream)),
+                    allow_not_converged)
+    return QueryResult(pi, resid, ti, tv, tn, [st.as_dict()] if want_stats else [], status)
+
+
+def ahpp_query_noalloc(g: Graph, source: int, eps: float, k: int = 0, max_iters: int = 0, want_pi: bool = True,
+                       want_resid: bool = False, want_stats: bool = True, stream=None,
+                       allow_not_converged: bool = False) -> QueryResult:
+    """ahpp_query whose per-query buffers live in the library's fixed device
+    scratch (no device allocation inside the call; see ahpp.h).  The output
+    tensors are allocated here, by the caller side."""
+    import torch
+    dev = torch.device("cuda", g.device)
+    pi = torch.empty(g.n_u, dtype=torch.float32, device=dev) if want_pi else None
+    resid = torch.empty(g.n_u, dtype=torch.float32, device=dev) if want_resid else None
+    ti = torch.empty(max(k, 1), dtype=torch.int32, device=dev) if k > 0 else None
+    tv = torch.empty(max(k, 1), dtype=torch.float32, device=dev) if k > 0 else None
+    tn = torch.empty(1, dtype=torch.int32, device=dev) if k > 0 else None
+    st = Stats()
+    status = _check(load_library().ahpp_query_noalloc(g._h, int(source), float(eps), int(max_iters), _dev_ptr(pi),
+                                                      _dev_ptr(resid), int(k), _dev_ptr(ti), _dev_ptr(tv),
+                                                      _dev_ptr(tn), ctypes.byref(st) if want_stats else None,
+                                                      _stream(g.device, stream)),
                     allow_not_converged)
     return QueryResult(pi, resid, ti, tv, tn, [st.as_dict()] if want_stats else [], status)
 

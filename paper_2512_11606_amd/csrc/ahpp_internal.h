@@ -75,6 +75,22 @@ struct Control {
     int32_t pad0;
 };
 
+// Device buffers of one single-source query: the graph's own (allocated at
+// load) or views into caller-free scratch (ahpp_query_noalloc).
+struct QueryBufs {
+    float *r = nullptr;                    // [n_u] residues (device numbering)
+    float *pi = nullptr;                   // [n_u] reserves (device numbering)
+    float *z = nullptr;                    // [n_v + n_a] V / attribute residues over their normaliser
+    float *out = nullptr;                  // [n_u] a U vector in input order (top-k input when no output is given)
+    Control *ctl = nullptr;
+    float *part = nullptr;                 // chunk partial sums, max(n_items) slots
+    float *blk_max = nullptr;              // per-workgroup maxima, 2 * grid_cap
+    unsigned long long *blk_np = nullptr;  // per-workgroup n_p partials, 4 * grid_cap
+    double *sums = nullptr;                // per-workgroup residue sums, kSumBlocks
+    void *tk = nullptr;                    // top-k scratch of one query (nullable: the graph's)
+};
+constexpr int kSumBlocks = 1024;           // workgroups of the residue-sum reduction
+
 // Constants of the stop/switch rule of one graph.
 struct Rule {
     float alpha;
@@ -230,12 +246,7 @@ struct Graph {
     int64_t device_bytes = 0;
     double load_ms = 0, lambda_ms = 0;
     // Single-query state (allocated at load).
-    float *q_r = nullptr, *q_pi = nullptr, *q_z = nullptr;
-    float *q_out = nullptr;         // a U vector in input order (top-k input when no output is given)
-    Control *q_ctl = nullptr;
-    float *part_item = nullptr;            // chunk partial sums, max(n_items) slots
-    float *blk_max = nullptr;              // per-workgroup maxima, 2 * grid_cap
-    unsigned long long *blk_np = nullptr;  // per-workgroup n_p partials, 4 * grid_cap
+    QueryBufs q;
     // Batched engine (allocated on first use, grown on demand).
     BatchState batch;
     Profiler prof;
@@ -300,17 +311,42 @@ void free_graph(Graph &g);
 // push.hip
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 void alloc_query_state(Graph &g);
+void free_query_state(QueryBufs &b);
+// Bytes of one query's buffers laid out by carve_query_bufs (256-byte
+// aligned pieces), and the buffers carved from `base`.
+size_t query_bufs_bytes(const Graph &g);
+QueryBufs carve_query_bufs(const Graph &g, void *base);
 // out[i] = in[u_new[i]]: a U vector of the device numbering in input order.
 void to_input_order(const Graph &g, const float *in, float *out, hipStream_t s);
 // schedule: 0 ASRP, 1 APP, 2 APP(S), 3 APP(E) (Exp-2); r_max = eps / (|E| + |E_A|).
-void single_query_init(Graph &g, int32_t source, float eps_f, int32_t max_iters, hipStream_t s, int32_t schedule = 0,
-                       float r_max = 0.0f);
-void single_query_round(Graph &g, hipStream_t s);
-void single_query_rounds(Graph &g, int n, hipStream_t s);   // as batch_rounds
+void single_query_init(Graph &g, const QueryBufs &b, int32_t source, float eps_f, int32_t max_iters, hipStream_t s,
+                       int32_t schedule = 0, float r_max = 0.0f);
+// One round; `timed` lets the launch profiler time it (when it is on).
+void single_query_round(Graph &g, const QueryBufs &b, hipStream_t s, bool timed = true);
+// n rounds.  `own`: b is the graph's own buffers, so the rounds may be
+// replayed from a captured HIP graph (which names them) and timed by the
+// launch profiler; otherwise every round is plain launches, untimed.
+void single_query_rounds(Graph &g, const QueryBufs &b, int n, hipStream_t s, bool own);
 bool graphs_enabled(const Graph &g);
 hipGraphExec_t capture_graph(Graph &g, const char *what, const std::function<void(hipStream_t)> &record);
-void single_query_stats(Graph &g, double *sum_r, hipStream_t s);
+void single_query_stats(Graph &g, const QueryBufs &b, double *sum_r, hipStream_t s);
 double compute_lambda(Graph &g, int T, hipStream_t s);
+
+// noalloc.hip: a file-scope device array of kNoallocScratchBytes per GPU for
+// ahpp_query_noalloc.  noalloc_setup (at graph load, with `device` current)
+// looks up its device address once per device; noalloc_scratch returns it
+// (nullptr before set-up).
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+void noalloc_setup(int device);
+void *noalloc_scratch(int device);
+
+// capi.hip: the body of a single-source query on buffers b (see
+// single_query_rounds for `own`; with own == false nothing is allocated and
+// no event, captured graph or profiler record is made, and stats->ms is the
+// host wall time of the call).  Returns the control status (1 converged).
+int32_t run_query(Graph &g, const QueryBufs &b, bool own, int32_t source, double eps, int32_t schedule,
+                  int32_t max_iters, float *pi_out, float *resid_out, int32_t k, int32_t *topk_idx, float *topk_val,
+                  int32_t *topk_n, ahpp_stats_t *stats, hipStream_t s);
 
 // batch.hip
 struct AdmitReq {

@@ -135,18 +135,18 @@ int rounds_left(const Graph &g, float max_r, float eps_f) {
 
 // Enqueues rounds in chunks sized by rounds_left until the control block
 // reports done; rounds enqueued past the stop are empty launches.
-void run_single(Graph &g, hipStream_t s) {
+void run_single(Graph &g, const QueryBufs &b, bool own, hipStream_t s) {
     int chunk = 4, launched = 0;
     Control c;
     for (;;) {
-        single_query_rounds(g, chunk, s);
+        single_query_rounds(g, b, chunk, s, own);
         launched += chunk;
-        check_hip(hipMemcpyAsync(&c, g.q_ctl, sizeof(Control), hipMemcpyDeviceToHost, s), "poll");
+        check_hip(hipMemcpyAsync(&c, b.ctl, sizeof(Control), hipMemcpyDeviceToHost, s), "poll");
         check_hip(hipStreamSynchronize(s), "poll");
         if (c.done) break;
         chunk = rounds_left(g, c.last_max, c.eps_f);
     }
-    if (g.prof.on) {
+    if (own && g.prof.on) {
         profiler_void_tail(g.prof, 0, launched - c.iter);
         profiler_void_tail(g.prof, 1, launched - c.iter);
     }
@@ -230,6 +230,49 @@ void *dev_alloc(Graph &g, size_t bytes, const char *what) {
     }
     g.device_bytes += (int64_t)bytes;
     return p;
+}
+
+int32_t run_query(Graph &g, const QueryBufs &b, bool own, int32_t source, double eps, int32_t schedule,
+                  int32_t max_iters, float *pi_out, float *resid_out, int32_t k, int32_t *topk_idx, float *topk_val,
+                  int32_t *topk_n, ahpp_stats_t *stats, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<EventPair> ev;
+    if (own) {
+        ev.reset(new EventPair());
+        check_hip(hipEventRecord(ev->start, s), "event");
+    }
+    const float eps_f = (float)(eps / g.lambda);
+    const int32_t src = g.u_new_host[(size_t)source];
+    single_query_init(g, b, src, eps_f, max_iters, s, schedule, (float)(eps / (double)(g.m_e + g.m_a)));
+    run_single(g, b, own, s);
+    // Scores in input order (the top-k breaks ties by input id).
+    float *scores = pi_out ? pi_out : (k > 0 ? b.out : nullptr);
+    if (scores) to_input_order(g, b.pi, scores, s);
+    if (k > 0)
+        topk_launch(scores, g.n_u, 0, 1, nullptr, source, k, topk_idx, topk_val, topk_n, b.tk ? b.tk : g.tk_scratch,
+                    s);
+    if (resid_out) to_input_order(g, b.r, resid_out, s);
+    if (ev) check_hip(hipEventRecord(ev->stop, s), "event");
+    Control ctl;
+    check_hip(hipMemcpyAsync(&ctl, b.ctl, sizeof(Control), hipMemcpyDeviceToHost, s), "control D2H");
+    check_hip(hipStreamSynchronize(s), "query");
+    const float ms = ev ? ev->elapsed_ms()
+                        : (float)std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                              .count();
+    if (stats) {
+        double sum_r = 0.0;
+        single_query_stats(g, b, &sum_r, s);
+        stats->iters = ctl.iter;
+        stats->sync_switch_iter = ctl.switch_iter;
+        stats->converged = ctl.status == 1;
+        stats->reserved = 0;
+        stats->n_push = (int64_t)ctl.n_p;
+        stats->max_residual = ctl.last_max;
+        stats->sum_residual = sum_r;
+        stats->ms = ms;
+        stats->pad = 0;
+    }
+    return ctl.status;
 }
 
 }  // namespace ahpp
@@ -405,6 +448,7 @@ ahpp_status_t ahpp_graph_load(const ahpp_graph_desc_t *d, ahpp_graph_t **out) {
         check_hip(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, g.device), "device attributes");
         g.n_cu = n_cu > 0 ? n_cu : 1;
         g.grid_cap = g.n_cu * kBlocksPerCu;
+        noalloc_setup(g.device);
         build_graph(g, d->edge_u, d->edge_v, d->edge_w, d->assoc_u, d->assoc_a, d->assoc_w, s);
         alloc_query_state(g);
         ensure_topk_scratch(g, 1);
@@ -490,36 +534,8 @@ ahpp_status_t query_impl(const char *name, ahpp_graph_t *h, int32_t source, doub
     int32_t status = 0;
     const ahpp_status_t rc = guarded(name, [&] {
         DeviceScope scope(g.device);
-        EventPair ev;
-        check_hip(hipEventRecord(ev.start, s), "event");
-        const float eps_f = (float)(eps / g.lambda);
-        const int32_t src = g.u_new_host[(size_t)source];
-        single_query_init(g, src, eps_f, max_iters, s, schedule, (float)(eps / (double)(g.m_e + g.m_a)));
-        run_single(g, s);
-        // Scores in input order (the top-k breaks ties by input id).
-        float *scores = pi_out ? pi_out : (k > 0 ? g.q_out : nullptr);
-        if (scores) to_input_order(g, g.q_pi, scores, s);
-        if (k > 0) topk_launch(scores, g.n_u, 0, 1, nullptr, source, k, topk_idx, topk_val, topk_n, g.tk_scratch, s);
-        if (resid_out) to_input_order(g, g.q_r, resid_out, s);
-        check_hip(hipEventRecord(ev.stop, s), "event");
-        Control ctl;
-        check_hip(hipMemcpyAsync(&ctl, g.q_ctl, sizeof(Control), hipMemcpyDeviceToHost, s), "control D2H");
-        check_hip(hipStreamSynchronize(s), "query");
-        status = ctl.status;
-        const float ms = ev.elapsed_ms();
-        if (stats) {
-            double sum_r = 0.0;
-            single_query_stats(g, &sum_r, s);
-            stats->iters = ctl.iter;
-            stats->sync_switch_iter = ctl.switch_iter;
-            stats->converged = ctl.status == 1;
-            stats->reserved = 0;
-            stats->n_push = (int64_t)ctl.n_p;
-            stats->max_residual = ctl.last_max;
-            stats->sum_residual = sum_r;
-            stats->ms = ms;
-            stats->pad = 0;
-        }
+        status = run_query(g, g.q, true, source, eps, schedule, max_iters, pi_out, resid_out, k, topk_idx, topk_val,
+                           topk_n, stats, s);
         return AHPP_OK;
     });
     if (rc != AHPP_OK) return rc;
@@ -533,6 +549,40 @@ ahpp_status_t ahpp_query(ahpp_graph_t *h, int32_t source, double eps, int32_t ma
                          ahpp_stats_t *stats, void *hip_stream) {
     return query_impl("ahpp_query", h, source, eps, 0, max_iters, pi_out, resid_out, k, topk_idx, topk_val, topk_n,
                       stats, hip_stream);
+}
+
+ahpp_status_t ahpp_query_noalloc(ahpp_graph_t *h, int32_t source, double eps, int32_t max_iters, float *pi_out,
+                                 float *resid_out, int32_t k, int32_t *topk_idx, float *topk_val, int32_t *topk_n,
+                                 ahpp_stats_t *stats, void *hip_stream) {
+    g_last_error.clear();
+    const std::string fn("ahpp_query_noalloc");
+    if (!h) return fail(AHPP_ERR_INVALID_ARG, fn + ": NULL graph");
+    Graph &g = h->g;
+    if (source < 0 || source >= g.n_u) return fail(AHPP_ERR_INVALID_ARG, fn + ": source out of range");
+    if (!(eps > 0.0) || std::isinf(eps)) return fail(AHPP_ERR_INVALID_ARG, fn + ": eps must be > 0 and finite");
+    if (k < 0 || k > kMaxTopK) return fail(AHPP_ERR_INVALID_ARG, fn + ": k must be in [0, 2048]");
+    if (k > 0 && (!topk_idx || !topk_val || !topk_n))
+        return fail(AHPP_ERR_INVALID_ARG, fn + ": top-k outputs required when k > 0");
+    const size_t need = query_bufs_bytes(g);
+    if (need > kNoallocScratchBytes)
+        return fail(AHPP_ERR_INVALID_ARG, fn + ": the graph needs " + std::to_string(need) +
+                                              " bytes of query scratch, above the fixed " +
+                                              std::to_string(kNoallocScratchBytes) + " (use ahpp_query)");
+    if (max_iters <= 0) max_iters = 100000;
+    hipStream_t s = (hipStream_t)hip_stream;
+    int32_t status = 0;
+    const ahpp_status_t rc = guarded("ahpp_query_noalloc", [&] {
+        DeviceScope scope(g.device);
+        void *base = noalloc_scratch(g.device);
+        if (!base) throw Failure{AHPP_ERR_DEVICE, fn + ": scratch of the device was not set up"};
+        const QueryBufs b = carve_query_bufs(g, base);
+        status = run_query(g, b, false, source, eps, 0, max_iters, pi_out, resid_out, k, topk_idx, topk_val, topk_n,
+                           stats, s);
+        return AHPP_OK;
+    });
+    if (rc != AHPP_OK) return rc;
+    if (status != 1) return fail(AHPP_ERR_NOT_CONVERGED, fn + ": max_iters reached before the stop rule held");
+    return AHPP_OK;
 }
 
 ahpp_status_t ahpp_query_schedule(ahpp_graph_t *h, int32_t source, double eps, int32_t schedule, int32_t max_iters,
@@ -563,9 +613,9 @@ ahpp_status_t ahpp_query_mc(ahpp_graph_t *h, int32_t source, int64_t n_walks, ui
         EventPair ev;
         check_hip(hipEventRecord(ev.start, s), "event");
         // Counts in the residue buffer, scores in the reserve buffer.
-        unsigned *count = reinterpret_cast<unsigned *>(g.q_r);
+        unsigned *count = reinterpret_cast<unsigned *>(g.q.r);
         const McResult r = mc_walks(g, g.u_new_host[(size_t)source], n_walks, seed, 4096, count, s);
-        float *scores = pi_out ? pi_out : g.q_pi;
+        float *scores = pi_out ? pi_out : g.q.pi;
         mc_scores(count, g.u_new, g.n_u, n_walks, scores, s);
         if (k > 0) topk_launch(scores, g.n_u, 0, 1, nullptr, source, k, topk_idx, topk_val, topk_n, g.tk_scratch, s);
         check_hip(hipEventRecord(ev.stop, s), "event");

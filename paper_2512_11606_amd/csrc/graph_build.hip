@@ -816,14 +816,10 @@ void free_graph(Graph &g) {
     dfree(g.u_new);
     g.u_new = nullptr;
     g.u_new_host.clear();
-    dfree(g.q_out);
-    g.q_out = nullptr;
-    for (void *p : {(void *)g.inv_b, (void *)g.q_r, (void *)g.q_pi, (void *)g.q_z, (void *)g.q_ctl,
-                    (void *)g.part_item, (void *)g.blk_max, (void *)g.blk_np, g.tk_scratch})
+    free_query_state(g.q);
+    for (void *p : {(void *)g.inv_b, g.tk_scratch})
         dfree(p);
-    g.inv_b = g.q_r = g.q_pi = g.q_z = g.part_item = g.blk_max = nullptr;
-    g.q_ctl = nullptr;
-    g.blk_np = nullptr;
+    g.inv_b = nullptr;
     g.tk_scratch = nullptr;
 }
 

@@ -488,21 +488,73 @@ void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_f32, dim3(capped(n, kBlock, 4096)), dim3(kBlock), 0, s, p, v, n);
 }
 
-void alloc_query_state(Graph &g) {
-    if (g.q_r) return;
+namespace {
+// Sizes (elements) of the pieces of one query's buffers.
+struct QuerySizes {
+    size_t n_u, n_z, items, grid_cap;
+};
+QuerySizes query_sizes(const Graph &g) {
     auto n1 = [](int64_t n) { return (size_t)(n > 0 ? n : 1); };
-    g.q_r = (float *)dev_alloc(g, n1(g.n_u) * 4, "query residues");
-    g.q_pi = (float *)dev_alloc(g, n1(g.n_u) * 4, "query reserves");
-    g.q_out = (float *)dev_alloc(g, n1(g.n_u) * 4, "query scores in input order");
-    g.q_z = (float *)dev_alloc(g, n1(g.n_v + g.n_a) * 4, "query V/attribute residues");
-    g.q_ctl = (Control *)dev_alloc(g, sizeof(Control), "query control");
-    g.part_item = (float *)dev_alloc(g, n1(std::max(g.fwd.n_items, g.back.n_items)) * 4, "chunk partials");
-    g.blk_max = (float *)dev_alloc(g, (size_t)2 * g.grid_cap * 4, "workgroup maxima");
-    g.blk_np = (unsigned long long *)dev_alloc(g, (size_t)4 * g.grid_cap * 8, "workgroup push counts");
+    return QuerySizes{n1(g.n_u), n1(g.n_v + g.n_a), n1(std::max(g.fwd.n_items, g.back.n_items)),
+                      (size_t)g.grid_cap};
+}
+size_t round_up_256(size_t b) { return (b + 255) & ~(size_t)255; }
+}  // namespace
+
+void alloc_query_state(Graph &g) {
+    if (g.q.r) return;
+    const QuerySizes n = query_sizes(g);
+    QueryBufs &b = g.q;
+    b.r = (float *)dev_alloc(g, n.n_u * 4, "query residues");
+    b.pi = (float *)dev_alloc(g, n.n_u * 4, "query reserves");
+    b.out = (float *)dev_alloc(g, n.n_u * 4, "query scores in input order");
+    b.z = (float *)dev_alloc(g, n.n_z * 4, "query V/attribute residues");
+    b.ctl = (Control *)dev_alloc(g, sizeof(Control), "query control");
+    b.part = (float *)dev_alloc(g, n.items * 4, "chunk partials");
+    b.blk_max = (float *)dev_alloc(g, 2 * n.grid_cap * 4, "workgroup maxima");
+    b.blk_np = (unsigned long long *)dev_alloc(g, 4 * n.grid_cap * 8, "workgroup push counts");
+    b.sums = (double *)dev_alloc(g, (size_t)kSumBlocks * 8, "residue sums");
+    b.tk = nullptr;  // the graph's top-k scratch
 }
 
-void single_query_init(Graph &g, int32_t source, float eps_f, int32_t max_iters, hipStream_t s, int32_t schedule,
-                       float r_max) {
+void free_query_state(QueryBufs &b) {
+    for (void *p : {(void *)b.r, (void *)b.pi, (void *)b.out, (void *)b.z, (void *)b.ctl, (void *)b.part,
+                    (void *)b.blk_max, (void *)b.blk_np, (void *)b.sums})
+        dfree(p);
+    b = QueryBufs{};
+}
+
+size_t query_bufs_bytes(const Graph &g) {
+    const QuerySizes n = query_sizes(g);
+    return 3 * round_up_256(n.n_u * 4) + round_up_256(n.n_z * 4) + round_up_256(sizeof(Control)) +
+           round_up_256(n.items * 4) + round_up_256(2 * n.grid_cap * 4) + round_up_256(4 * n.grid_cap * 8) +
+           round_up_256((size_t)kSumBlocks * 8) + round_up_256(topk_scratch_bytes(1));
+}
+
+QueryBufs carve_query_bufs(const Graph &g, void *base) {
+    const QuerySizes n = query_sizes(g);
+    char *p = (char *)base;
+    auto take = [&](size_t bytes) {
+        char *q = p;
+        p += round_up_256(bytes);
+        return (void *)q;
+    };
+    QueryBufs b;
+    b.r = (float *)take(n.n_u * 4);
+    b.pi = (float *)take(n.n_u * 4);
+    b.out = (float *)take(n.n_u * 4);
+    b.z = (float *)take(n.n_z * 4);
+    b.ctl = (Control *)take(sizeof(Control));
+    b.part = (float *)take(n.items * 4);
+    b.blk_max = (float *)take(2 * n.grid_cap * 4);
+    b.blk_np = (unsigned long long *)take(4 * n.grid_cap * 8);
+    b.sums = (double *)take((size_t)kSumBlocks * 8);
+    b.tk = take(topk_scratch_bytes(1));
+    return b;
+}
+
+void single_query_init(Graph &g, const QueryBufs &b, int32_t source, float eps_f, int32_t max_iters, hipStream_t s,
+                       int32_t schedule, float r_max) {
     if ((schedule == 1 || schedule == 2) && !g.deg_u) {
         g.deg_u = (float *)dev_alloc(g, (size_t)std::max<int64_t>(g.n_u, 1) * 4, "node degrees");
         if (g.single_round_graph) {  // captured with no degree array
@@ -512,53 +564,53 @@ void single_query_init(Graph &g, int32_t source, float eps_f, int32_t max_iters,
         hipLaunchKernelGGL(k_degrees, dim3(capped(g.n_u, kBlock, 4096)), dim3(kBlock), 0, s, g.fwd.off, g.n_u,
                            g.deg_u);
     }
-    launch_fill_f32(g.q_r, 0.0f, g.n_u, s);
-    launch_fill_f32(g.q_pi, 0.0f, g.n_u, s);
-    hipLaunchKernelGGL(k_query_init, dim3(1), dim3(64), 0, s, g.q_ctl, g.q_r, source, eps_f, max_iters, schedule,
+    launch_fill_f32(b.r, 0.0f, g.n_u, s);
+    launch_fill_f32(b.pi, 0.0f, g.n_u, s);
+    hipLaunchKernelGGL(k_query_init, dim3(1), dim3(64), 0, s, b.ctl, b.r, source, eps_f, max_iters, schedule,
                        r_max, (const float *)g.deg_u);
     check_hip(hipGetLastError(), "query init");
 }
 
-void single_query_round(Graph &g, hipStream_t s) {
+void single_query_round(Graph &g, const QueryBufs &b, hipStream_t s, bool timed) {
     const Plan p = make_plan(g);
-    GatherArgs back{view(g.back), g.q_r, g.q_z, nullptr, g.inv_b, g.part_item, g.q_ctl, 0.0f, (float)g.alpha,
-                    nullptr, g.blk_np, g.deg_u};
+    const int prof_back = timed ? 0 : -1, prof_fwd = timed ? 1 : -1;
+    GatherArgs back{view(g.back), b.r, b.z, nullptr, g.inv_b, b.part, b.ctl, 0.0f, (float)g.alpha,
+                    nullptr, b.blk_np, g.deg_u};
     // Algorithmic bytes: CSR entries (column, weight) and gathered residue per
     // entry, offsets and per-row state per row.
     const double wb = g.fwd.w ? 8.0 : 4.0;
-    launch_gather<kBack>(g, false, back, p.back, p.back_fix, s, 0,
+    launch_gather<kBack>(g, false, back, p.back, p.back_fix, s, prof_back,
                          12.0 * g.back.nnz + 16.0 * g.back.n_rows);
-    GatherArgs fwd{view(g.fwd), g.q_z, g.q_r, g.q_pi, nullptr, g.part_item, g.q_ctl, 0.0f, (float)g.alpha,
-                   g.blk_max, g.blk_np + 2 * g.grid_cap, g.deg_u};
-    launch_gather<kFwdAcc>(g, g.unit, fwd, p.fwd, p.fwd_fix, s, 1, (wb + 4.0) * g.fwd.nnz + 24.0 * g.fwd.n_rows);
-    Partials part{g.blk_max, (int)p.fwd, g.blk_max + g.grid_cap, (int)p.fwd_fix,
-                  {g.blk_np, g.blk_np + g.grid_cap, g.blk_np + 2 * g.grid_cap, g.blk_np + 3 * g.grid_cap},
+    GatherArgs fwd{view(g.fwd), b.z, b.r, b.pi, nullptr, b.part, b.ctl, 0.0f, (float)g.alpha,
+                   b.blk_max, b.blk_np + 2 * g.grid_cap, g.deg_u};
+    launch_gather<kFwdAcc>(g, g.unit, fwd, p.fwd, p.fwd_fix, s, prof_fwd,
+                           (wb + 4.0) * g.fwd.nnz + 24.0 * g.fwd.n_rows);
+    Partials part{b.blk_max, (int)p.fwd, b.blk_max + g.grid_cap, (int)p.fwd_fix,
+                  {b.blk_np, b.blk_np + g.grid_cap, b.blk_np + 2 * g.grid_cap, b.blk_np + 3 * g.grid_cap},
                   {(int)p.back, (int)p.back_fix, (int)p.fwd, (int)p.fwd_fix}};
-    hipLaunchKernelGGL(k_control, dim3(1), dim3(kControlThreads), 0, s, g.q_ctl, part, make_rule(g));
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(kControlThreads), 0, s, b.ctl, part, make_rule(g));
     check_hip(hipGetLastError(), "round launch");
 }
 
-void single_query_rounds(Graph &g, int n, hipStream_t s) {
-    if (!graphs_enabled(g)) {
-        for (int i = 0; i < n; ++i) single_query_round(g, s);
+void single_query_rounds(Graph &g, const QueryBufs &b, int n, hipStream_t s, bool own) {
+    if (!own || !graphs_enabled(g)) {
+        for (int i = 0; i < n; ++i) single_query_round(g, b, s, own);
         return;
     }
     if (!g.single_round_graph)
-        g.single_round_graph = capture_graph(g, "single round capture", [&](hipStream_t cs) { single_query_round(g, cs); });
+        g.single_round_graph =
+            capture_graph(g, "single round capture", [&](hipStream_t cs) { single_query_round(g, g.q, cs); });
     for (int i = 0; i < n; ++i) check_hip(hipGraphLaunch(g.single_round_graph, s), "round graph launch");
 }
 
-void single_query_stats(Graph &g, double *sum_r, hipStream_t s) {
-    const unsigned grid = capped(g.n_u, kBlock, 1024);
-    double *d = nullptr;
-    check_hip(hipMallocAsync((void **)&d, grid * sizeof(double), s), "stats scratch");
-    hipLaunchKernelGGL(k_sum_f64, dim3(grid), dim3(kBlock), 0, s, g.q_r, g.n_u, d);
-    std::vector<double> h(grid);
-    check_hip(hipMemcpyAsync(h.data(), d, grid * sizeof(double), hipMemcpyDeviceToHost, s), "stats D2H");
-    check_hip(hipFreeAsync(d, s), "stats scratch");
+void single_query_stats(Graph &g, const QueryBufs &b, double *sum_r, hipStream_t s) {
+    const unsigned grid = capped(g.n_u, kBlock, kSumBlocks);
+    hipLaunchKernelGGL(k_sum_f64, dim3(grid), dim3(kBlock), 0, s, b.r, g.n_u, b.sums);
+    double h[kSumBlocks];
+    check_hip(hipMemcpyAsync(h, b.sums, grid * sizeof(double), hipMemcpyDeviceToHost, s), "stats D2H");
     check_hip(hipStreamSynchronize(s), "stats");
     double t = 0.0;
-    for (double v : h) t += v;
+    for (unsigned i = 0; i < grid; ++i) t += h[i];
     *sum_r = t;
 }
 
@@ -566,23 +618,23 @@ void single_query_stats(Graph &g, double *sum_r, hipStream_t s) {
 // pi_T = sum_{l<T} alpha (1-alpha)^l 1 P^l, lambda = max_i pi_T(u_i) + |U| (1-alpha)^T.
 // Each sweep is the round above with every U node pushed (threshold -1).
 double compute_lambda(Graph &g, int T, hipStream_t s) {
-    float *y = g.q_r, *acc = g.q_pi, *z = g.q_z;
+    float *y = g.q.r, *acc = g.q.pi, *z = g.q.z;
     const Plan p = make_plan(g);
     launch_fill_f32(y, 1.0f, g.n_u, s);
     launch_fill_f32(acc, 0.0f, g.n_u, s);
     launch_fill_f32(z, 0.0f, g.n_v + g.n_a, s);
     for (int t = 0; t < T; ++t) {
-        GatherArgs back{view(g.back), y, z, nullptr, g.inv_b, g.part_item, nullptr, -1.0f, (float)g.alpha, nullptr,
+        GatherArgs back{view(g.back), y, z, nullptr, g.inv_b, g.q.part, nullptr, -1.0f, (float)g.alpha, nullptr,
                         nullptr};
         launch_gather<kBack>(g, false, back, p.back, p.back_fix, s);
-        GatherArgs fwd{view(g.fwd), z, y, acc, nullptr, g.part_item, nullptr, -1.0f, (float)g.alpha, nullptr, nullptr};
+        GatherArgs fwd{view(g.fwd), z, y, acc, nullptr, g.q.part, nullptr, -1.0f, (float)g.alpha, nullptr, nullptr};
         launch_gather<kFwdLambda>(g, g.unit, fwd, p.fwd, p.fwd_fix, s);
         check_hip(hipGetLastError(), "lambda launch");
     }
     const unsigned grid = capped(g.n_u, kBlock, g.grid_cap);
-    hipLaunchKernelGGL(k_max_f32, dim3(grid), dim3(kBlock), 0, s, acc, g.n_u, g.blk_max);
+    hipLaunchKernelGGL(k_max_f32, dim3(grid), dim3(kBlock), 0, s, acc, g.n_u, g.q.blk_max);
     std::vector<float> h(grid);
-    check_hip(hipMemcpyAsync(h.data(), g.blk_max, grid * sizeof(float), hipMemcpyDeviceToHost, s), "lambda D2H");
+    check_hip(hipMemcpyAsync(h.data(), g.q.blk_max, grid * sizeof(float), hipMemcpyDeviceToHost, s), "lambda D2H");
     check_hip(hipStreamSynchronize(s), "lambda");
     float mx = 0.0f;
     for (float v : h) mx = v > mx ? v : mx;
