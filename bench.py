@@ -9,13 +9,15 @@ uniform over U.  Inputs are generated on the host and loaded into HBM before
 the timed region; the timed region covers the whole batch (rounds of
 Algorithm 4 and the top-k) for `--steps` batches.
 
-Also reported: the plain single-query push on the same GPU (sources drawn
-proportional to degree) with p50 / p99 latency; a serving run of the
-continuous-batching server on the same graph (Poisson arrivals, sources
-proportional to degree, eps uniform on {1e-5, 1e-6, 1e-7, 1e-8}, latency from
-arrival to top-k on the host); the roofline of the dominant gather kernel
-(algorithmic bytes / HIP-event time, against 8 TB/s HBM); and the CPU
-oracle's FP64 ASRP on one query of the same graph.
+Also reported: the plain single-query push on the same GPU (100 sources drawn
+proportional to degree) with p50 / p99 latency; per-query completion times
+inside the batch; a serving sweep of the continuous-batching server on the
+5M/2M/100M serving graph (capacity, then Poisson arrivals at four offered
+rates up past it; sources proportional to degree, eps uniform on {1e-5,
+1e-6, 1e-7, 1e-8}; latency from arrival to top-k on the host); the roofline
+of the dominant gather kernel (compulsory bytes / HIP-event time, against
+8 TB/s HBM, beside the counter-measured traffic); and the CPU oracle's FP64
+ASRP on a sample of the batch's own sources.
 
 Prints one JSON line.
 """
@@ -26,6 +28,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -75,6 +78,14 @@ def _traffic(kernel_kind_name):
 
 
 def _cpu_model():
+    """The host CPU's model name as lscpu prints it (/proc/cpuinfo if lscpu is missing)."""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.strip().startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
@@ -85,25 +96,38 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(g, sources, eps):
-    """The oracle's FP64 ASRP (lambda from Theorem 3) on the host cores: one
-    query on one thread (latency), then one query per thread on every thread
-    the oracle's OpenMP runtime offers (throughput, the reported value)."""
+CPU_SAMPLE = 16        # queries of the headline batch timed on the host
+CPU_THREADS_MAX = 16   # the host share of one GPU
+
+
+def cpu_baseline(g, batch_sources, eps):
+    """The oracle's FP64 ASRP (lambda from Theorem 3) on the host cores, on a
+    sample of the headline batch's own sources (as many of its hub sources as
+    of its uniform ones): one query per thread; the value is the sample over
+    the wall time, latency the per-query thread times."""
+    import numpy as np
+
     import oracle
+    half = len(batch_sources) // 2
+    n = min(CPU_SAMPLE, len(batch_sources))
+    sample = np.concatenate([batch_sources[: n // 2], batch_sources[half: half + n - n // 2]]).astype(np.int32)
     og = oracle.OracleGraph.from_graph(g)
     lam = og.lambda_thm3()
+    nth = max(1, min(oracle.max_threads(), CPU_THREADS_MAX, sample.size))
     t0 = time.perf_counter()
-    _, _, st, ok = og.asrp(int(sources[0]), eps, lam)
-    dt1 = time.perf_counter() - t0
-    nth = max(1, min(oracle.max_threads(), len(sources)))
-    t0 = time.perf_counter()
-    _, _, bad = og.asrp_many(sources[:nth], eps, lam, nthreads=nth)
+    _, stats, bad = og.asrp_many(sample, eps, lam, nthreads=nth)
     dtn = time.perf_counter() - t0
-    return {"value": nth / dtn, "unit": "queries/s", "cores": nth, "kind": "oracle",
-            "host_cpus": os.cpu_count(), "cpu_model": _cpu_model(), "single_thread_ms": round(dt1 * 1e3, 1),
-            "sample": f"{nth} full FP64 ASRP queries (sources proportional to degree, eps {eps:g}, lambda from "
-                      f"Theorem 3) on the same graph, one per thread on {nth} threads, {dtn:.1f} s; one of them "
-                      f"alone on 1 thread: {dt1:.1f} s, {st.iterations} rounds"}
+    secs = sorted(og.last_secs.tolist())
+    og.close()
+    return {"value": round(sample.size / dtn, 3), "unit": "queries/s", "cores": nth, "kind": "oracle",
+            "latency_ms_p50": round(_percentile(secs, 50) * 1e3, 1),
+            "latency_ms_p99": round(_percentile(secs, 99) * 1e3, 1),
+            "rounds_mean": round(sum(st.iterations for st in stats) / len(stats), 1), "failed": bad,
+            "host_cpus": os.cpu_count(), "cpu_model": _cpu_model(),
+            "sample": f"{sample.size} sources of the timed batch ({n // 2} of its top-1% hub sources, "
+                      f"{n - n // 2} of its uniform ones), full FP64 ASRP at eps {eps:g} with lambda from "
+                      f"Theorem 3, one query per thread on {nth} threads: {dtn:.1f} s wall; latency = each "
+                      f"query's own thread time (p99 of {sample.size} is about the maximum)"}
 
 
 SERVE_EPS = (1e-5, 1e-6, 1e-7, 1e-8)
@@ -115,9 +139,9 @@ SERVE_EPS = (1e-5, 1e-6, 1e-7, 1e-8)
 PAPER_AMAZON_ASRP_MS = (158896.0, 188102.0)
 
 
-def amazon_leg(ahpp, synth, g, with_cpu, n=16):
-    """Plain single-query latency on the Amazon-shaped graph at eps = 1e-6,
-    beside the oracle's FP64 ASRP on one of the same queries (one thread)."""
+def amazon_leg(ahpp, synth, g, n=16):
+    """Plain single-query latency on the Amazon-shaped graph at eps = 1e-6 (the
+    oracle's time on one of the same queries is in the CPU baseline leg)."""
     dg = ahpp.load_graph(g, device=0)
     srcs = synth.degree_queries(g, n, 2005)
     ahpp.ahpp_query(dg, int(srcs[0]), 1e-6, k=50)
@@ -132,15 +156,6 @@ def amazon_leg(ahpp, synth, g, with_cpu, n=16):
            "latency_ms_p99": round(_percentile(lat, 99), 2), "lambda": round(dg.lam, 2),
            "paper_asrp_ms_amazon": list(PAPER_AMAZON_ASRP_MS)}
     dg.free()
-    if with_cpu:
-        import oracle
-        og = oracle.OracleGraph.from_graph(g)
-        lam = og.lambda_thm3()
-        t0 = time.perf_counter()
-        _, _, st, _ = og.asrp(int(srcs[0]), 1e-6, lam)
-        out["cpu_oracle_ms_one_thread"] = round((time.perf_counter() - t0) * 1e3, 1)
-        out["cpu_oracle_rounds"] = st.iterations
-        og.close()
     return out
 
 
@@ -241,43 +256,113 @@ def tiny_leg(ahpp, synth, n=200):
             "latency_ms_p99": round(_percentile(lat, 99), 3), "queries_per_s": round(n / (sum(lat) / 1e3), 1)}
 
 
-def serve_leg(ahpp, synth, g, dg, args):
-    """Continuous batching under Poisson arrivals on the loaded graph."""
+SWEEP_FRACS = (0.3, 0.6, 0.9, 1.3)   # offered load as a fraction of the measured capacity
+
+
+def serve_sweep_leg(ahpp, synth, args):
+    """Continuous batching on the 5M/2M/100M serving graph: capacity from a
+    closed burst (every query queued at once), then Poisson arrivals at
+    fractions of it, the last one past it; per rate p50 / p99 latency from
+    arrival to top-k on the host."""
     from paper_2512_11606_amd import serve
+    t_gen = time.perf_counter()
+    g = synth.make_graph(args.serve_graph)
+    dg = ahpp.load_graph(g, device=0)
+    load_s = time.perf_counter() - t_gen
     n = args.serve_queries
-    sources = synth.degree_queries(g, n, 2003)
-    pick = (synth.CounterRNG(2003, "serve_eps").uniform(n) * len(SERVE_EPS)).astype(int)
+    n_burst = 2 * args.serve_slots
+    total = n_burst + n * len(SWEEP_FRACS)
+    sources = synth.degree_queries(g, total, 2003)
+    pick = (synth.CounterRNG(2003, "serve_eps").uniform(total) * len(SERVE_EPS)).astype(int)
     eps = [SERVE_EPS[min(i, len(SERVE_EPS) - 1)] for i in pick]
     srv = ahpp.Server(dg, k=50, max_slots=args.serve_slots)
+    out = {"workload": f"serving on {args.serve_graph} ({g.n_u}/{g.n_v}/{g.m_e} edges, {g.n_attr} attributes x "
+                       f"{g.m_a // g.n_u}), sources proportional to degree, eps uniform on "
+                       f"{list(SERVE_EPS)}, k 50, {srv.info()['slots']} slots, {args.serve_rounds} rounds per step",
+           "graph_gen_and_load_s": round(load_s, 1), "rates": []}
     try:
-        summary, res = serve.run(srv, sources, eps, rate_qps=args.serve_rate, rounds_per_step=args.serve_rounds,
-                                 max_wall_s=180.0)
+        print(f"[bench] serving burst of {n_burst}", file=sys.stderr, flush=True)
+        summ, res = serve.run(srv, sources[:n_burst], eps[:n_burst], rate_qps=1e9,
+                              rounds_per_step=args.serve_rounds, max_wall_s=300.0)
+        cap = summ["served_qps"]
+        out["capacity_qps"] = round(cap, 2)
+        out["burst"] = {kk: (round(v, 2) if isinstance(v, float) else v) for kk, v in summ.items()}
+        for i, frac in enumerate(SWEEP_FRACS):
+            lo = n_burst + i * n
+            rate = frac * cap
+            print(f"[bench] serving {n} queries at {rate:.1f} q/s", file=sys.stderr, flush=True)
+            summ, res = serve.run(srv, sources[lo:lo + n], eps[lo:lo + n], rate_qps=rate,
+                                  rounds_per_step=args.serve_rounds, seed=3003 + i, max_wall_s=300.0)
+            summ["converged"] = sum(1 for r in res.values() if r["stats"]["converged"] == 1)
+            summ["load_fraction"] = frac
+            out["rates"].append({kk: (round(v, 2) if isinstance(v, float) else v) for kk, v in summ.items()})
     finally:
         srv.close()
-    summary["converged"] = sum(1 for r in res.values() if r["stats"]["converged"] == 1)
-    summary["eps_set"] = list(SERVE_EPS)
-    summary["k"] = 50
-    return {kk: (round(v, 2) if isinstance(v, float) else v) for kk, v in summary.items()}
+        dg.free()
+    out["note"] = (f"offered 2k-50k queries/s is {2000 / max(cap, 1e-9):.0f}x-{50000 / max(cap, 1e-9):.0f}x "
+                   f"the measured capacity of one GPU on this graph")
+    return out
+
+
+def amazon_cpu_leg(synth, n=16):
+    """The oracle's FP64 ASRP, one thread, on the first source of the
+    Amazon-shaped latency leg (eps 1e-6): context for the paper's figure."""
+    import oracle
+    g = synth.make_graph("amazon")
+    src = int(synth.degree_queries(g, n, 2005)[0])
+    og = oracle.OracleGraph.from_graph(g)
+    lam = og.lambda_thm3()
+    t0 = time.perf_counter()
+    _, _, st, _ = og.asrp(src, 1e-6, lam)
+    out = {"source": src, "ms_one_thread": round((time.perf_counter() - t0) * 1e3, 1), "rounds": st.iterations}
+    og.close()
+    return out
+
+
+def roofline_of(prof, names):
+    """Roofline of the kernel kind with the most time: compulsory bytes per
+    launch over its mean HIP-event time, against the HBM peak; beside it the
+    gathered-model rate and, if a counter summary of the current kernel
+    source is committed, the measured traffic and its ratio to compulsory."""
+    dom_kind = max(prof, key=lambda kk: prof[kk]["ms"])
+    dom = prof[dom_kind]
+    name = names[dom_kind]
+    launches = max(dom["launches"], 1)
+    avg_ms = dom["ms"] / launches
+    comp = dom["compulsory"] / launches
+    gathered = dom["bytes"] / launches
+    achieved = comp / (avg_ms * 1e-3) / 1e9
+    traffic = _traffic(name)
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": name,
+           "launches": dom["launches"], "avg_ms": round(avg_ms, 4), "compulsory_bytes_per_launch": comp,
+           "gathered_bytes_per_launch": gathered,
+           "gathered_GBps": round(gathered / (avg_ms * 1e-3) / 1e9, 1)}
+    if traffic:
+        out["traffic_GBps"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
+        out["traffic_frac"] = round(out["traffic_GBps"] / HBM_PEAK_GBS, 4)
+        out["wasted_traffic"] = round(traffic / comp, 3)
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=1024)
-    ap.add_argument("--plain", type=int, default=32, help="plain single queries timed for latency")
+    ap.add_argument("--plain", type=int, default=100, help="plain single queries timed for latency")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
     ap.add_argument("--no-tiny", action="store_true", help="skip the small-graph latency run")
     ap.add_argument("--no-tune", action="store_true", help="keep the untuned batch schedule")
     ap.add_argument("--no-amazon", action="store_true", help="skip the Amazon-shaped latency and scaling runs")
     ap.add_argument("--no-scaling", action="store_true", help="skip the 50-100%% sampled-graph scaling run")
     ap.add_argument("--no-mc", action="store_true", help="skip the Monte Carlo run")
     ap.add_argument("--no-schedules", action="store_true", help="skip the ASRP / APP / APP(S) / APP(E) comparison")
-    ap.add_argument("--serve-queries", type=int, default=800)
-    ap.add_argument("--serve-rate", type=float, default=150.0, help="offered load, queries/s")
-    ap.add_argument("--serve-slots", type=int, default=256)
+    ap.add_argument("--serve-graph", default="serve5m")
+    ap.add_argument("--serve-queries", type=int, default=500, help="queries per offered rate of the sweep")
+    ap.add_argument("--serve-slots", type=int, default=512)
     ap.add_argument("--serve-rounds", type=int, default=4, help="rounds per server step")
     ap.add_argument("--graph", default="m1")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -304,6 +389,9 @@ def main():
 
     from paper_2512_11606_amd import ahpp, synth
 
+    def say(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     eps, k = 1e-7, 50
     g = synth.make_graph(args.graph)
     dg = ahpp.load_graph(g, device=0)
@@ -315,15 +403,20 @@ def main():
     sources = synth.mixed_batch_queries(g, args.batch, 2002)
     tuned = None if args.no_tune else ahpp.ahpp_graph_tune(dg, max_tiles=max(1, args.batch // 256))
 
+    say("warmup")
     for _ in range(args.warmup):
         ahpp.ahpp_query_batch(dg, sources, eps, k=k, want_pi=False, want_stats=False)
     torch.cuda.synchronize()
 
+    say("timed steps")
     ahpp.ahpp_profile_enable(dg, True)
     torch.cuda.synchronize()
+    step_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        a = time.perf_counter()
         res = ahpp.ahpp_query_batch(dg, sources, eps, k=k, want_pi=False, want_stats=False)
+        step_ms.append((time.perf_counter() - a) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = {kind: ahpp.ahpp_profile_read(dg, kind)
@@ -333,45 +426,60 @@ def main():
     value = args.batch * args.steps / elapsed
     topk_ok = int(res.topk_n.min().item()) == k
 
+    # Per-query completion inside one more (untimed) batch: the round at which
+    # each query's stop rule held, as a share of the batch's rounds, times the
+    # batch time (every result is returned when the call returns).
+    say("per-query statistics")
+    st_res = ahpp.ahpp_query_batch(dg, sources, eps, k=k, want_pi=False, want_stats=True)
+    iters = np.array([st["iters"] for st in st_res.stats], dtype=np.float64)
+    batch_ms = float(st_res.stats[0]["ms"])
+    done_ms = iters / iters.max() * batch_ms
+    completion = {"p50": round(float(np.percentile(done_ms, 50)), 1), "p99": round(float(np.percentile(done_ms, 99)), 1),
+                  "rounds_min": int(iters.min()), "rounds_max": int(iters.max()),
+                  "note": "each query's stop round / the batch's rounds x the batch's device time; the call returns "
+                          "all results together"}
+
     # Plain single-query push: per-query latency (host call to results).
+    say("plain queries")
     plain_src = synth.degree_queries(g, args.plain, 2001)
     ahpp.ahpp_query(dg, int(plain_src[0]), eps, k=k)
     lat = []
-    for s in plain_src.tolist():
+    for s_ in plain_src.tolist():
         a = time.perf_counter()
-        ahpp.ahpp_query(dg, s, eps, k=k, want_pi=False, want_stats=False)
+        ahpp.ahpp_query(dg, s_, eps, k=k, want_pi=False, want_stats=False)
         lat.append((time.perf_counter() - a) * 1e3)
     plain_qps = len(lat) / (sum(lat) / 1e3)
 
-    serving = None if args.no_serve else serve_leg(ahpp, synth, g, dg, args)
-    plain_tiny = None if args.no_tiny else tiny_leg(ahpp, synth)
-    monte_carlo = None if args.no_mc else mc_leg(ahpp, synth, g, dg)
-    schedules = None if args.no_schedules else schedule_leg(ahpp, synth, g, dg)
+    plain_tiny = monte_carlo = schedules = None
+    if not args.no_tiny:
+        say("small graph")
+        plain_tiny = tiny_leg(ahpp, synth)
+    if not args.no_mc:
+        say("monte carlo")
+        monte_carlo = mc_leg(ahpp, synth, g, dg)
+    if not args.no_schedules:
+        say("push schedules")
+        schedules = schedule_leg(ahpp, synth, g, dg)
+    names = {ahpp.PROF_BATCH_BACK: "kb_gather<back>", ahpp.PROF_BATCH_FWD: "kb_gather<fwd>",
+             ahpp.PROF_BATCH_HOT: "kb_hot"}
+    roofline = roofline_of(prof, names)
+    kernels = {names[kk]: {"launches": prof[kk]["launches"],
+                           "avg_ms": round(prof[kk]["ms"] / max(prof[kk]["launches"], 1), 4),
+                           "compulsory_GBps": round(prof[kk]["compulsory"] / max(prof[kk]["ms"], 1e-9) / 1e6, 1),
+                           "gathered_GBps": round(prof[kk]["bytes"] / max(prof[kk]["ms"], 1e-9) / 1e6, 1)}
+               for kk in names}
+    dg.free()
     amazon = scaling = None
     if not args.no_amazon:
+        say("amazon-shaped graph")
         g_am = synth.make_graph("amazon")
-        amazon = amazon_leg(ahpp, synth, g_am, not args.no_cpu)
+        amazon = amazon_leg(ahpp, synth, g_am)
         scaling = None if args.no_scaling else scaling_leg(ahpp, synth, g_am)
         del g_am
-
-    dom_kind = max(prof, key=lambda kk: prof[kk]["ms"])
-    dom = prof[dom_kind]
-    name = {ahpp.PROF_BATCH_BACK: "kb_gather<back>", ahpp.PROF_BATCH_FWD: "kb_gather<fwd>",
-            ahpp.PROF_BATCH_HOT: "kb_hot"}[dom_kind]
-    avg_ms = dom["ms"] / max(dom["launches"], 1)
-    bytes_per_launch = dom["bytes"] / max(dom["launches"], 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = _traffic(name)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": name,
-                "launches": dom["launches"], "avg_ms": round(avg_ms, 4),
-                "algo_bytes_per_launch": bytes_per_launch}
-    if traffic:
-        # Measured HBM bytes (counters) over the same launch time.  Above the
-        # algorithmic rate's share when rows stay in cache: then `achieved`
-        # exceeds the HBM peak and this is the kernel's HBM utilisation.
-        roofline["traffic_GBps"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
-        roofline["traffic_frac"] = round(roofline["traffic_GBps"] / HBM_PEAK_GBS, 4)
+    serving = None
+    if not args.no_serve:
+        say("serving sweep")
+        serving = serve_sweep_leg(ahpp, synth, args)
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -381,10 +489,15 @@ def main():
                                "Zipf(2.1) bipartite graph with 10k attributes x 20 (Zipf 1.5)",
                    "graph": args.graph, "n_u": g.n_u, "n_v": g.n_v, "m_e": g.m_e, "n_attr": g.n_attr, "m_a": g.m_a,
                    "eps": eps, "k": k, "batch": args.batch, "alpha": 0.15, "beta": 0.35,
-                   "lambda": round(dg.lam, 3)},
-        "batch_query_latency_ms_p50": round(elapsed / args.steps * 1e3, 2),
-        "batch_query_latency_ms_p99": round(elapsed / args.steps * 1e3, 2),
+                   "lambda": round(ginfo["lam"], 3)},
+        "precision": "residues, reserves and carries float32; pushes handed between half-steps as bfloat16 rounded "
+                     "toward zero, the exact remainder kept in the float32 state (Theorem 2's bound holds as stated)",
+        "hip_graphs": "off: the batch runs plain launches (replaying a captured round measured no faster)",
+        "batch_call_ms_p50": round(_percentile(step_ms, 50), 2),
+        "batch_call_ms_p99": round(_percentile(step_ms, 99), 2),
+        "batch_query_completion_ms": completion,
         "plain_qps": round(plain_qps, 2),
+        "plain_queries": len(lat),
         "plain_latency_ms_p50": round(_percentile(lat, 50), 2),
         "plain_latency_ms_p99": round(_percentile(lat, 99), 2),
         "batched_over_plain": round(value / plain_qps, 2),
@@ -398,18 +511,16 @@ def main():
         "push_schedules": schedules,
         "amazon_scaling": scaling,
         "roofline": roofline,
-        "kernels": {kname: {"launches": prof[kk]["launches"],
-                            "avg_ms": round(prof[kk]["ms"] / max(prof[kk]["launches"], 1), 4),
-                            "algo_GBps": round(prof[kk]["bytes"] / max(prof[kk]["ms"], 1e-9) / 1e6, 1)}
-                    for kk, kname in ((ahpp.PROF_BATCH_BACK, "kb_gather<back>"), (ahpp.PROF_BATCH_FWD, "kb_gather<fwd>"),
-                                      (ahpp.PROF_BATCH_HOT, "kb_hot"))},
+        "kernels": kernels,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(g, plain_src, eps)
+        say("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(g, sources, eps)
+        if not args.no_amazon:
+            out["cpu_baseline"]["amazon_shaped"] = amazon_cpu_leg(synth)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
-    dg.free()
 
 
 if __name__ == "__main__":

@@ -299,9 +299,16 @@ ahpp_status_t ahpp_graph_tune(ahpp_graph_t *g, int32_t max_tiles, ahpp_tune_info
 /* Kernel timing (diagnostics, used by the benchmark's roofline figures).
  * While enabled, the library brackets every launch of its gather kernels with
  * HIP events on the launch stream and adds, per kernel kind, the launch
- * count, the summed elapsed time and the algorithmic bytes of the launch
- * (CSR entries and offsets once per launch, one 4-byte residue per entry and
- * query, and the per-row, per-query state the epilogue reads and writes).
+ * count, the summed elapsed time and two byte counts of each launch:
+ *   algo_bytes:       the gathered model -- CSR entries and offsets once, one
+ *                     residue value per (entry, running query) (4 bytes in the
+ *                     single-query path, the 2-byte transport value in the
+ *                     batched path), and the per-(row, query) state the
+ *                     epilogue reads and writes;
+ *   compulsory_bytes: the CSR once, the gathered vector once per running
+ *                     query (each of its rows once), and the same per-row
+ *                     state: the least a launch can move, so compulsory bytes
+ *                     over the launch time never exceed the HBM bandwidth.
  * Kinds: 0 single-query V/attribute gather, 1 single-query U gather,
  *        2 batched V/attribute gather (rows other than the hot rows),
  *        3 batched U gather, 4 batched hot-row pass (the longest V/attribute
@@ -312,7 +319,7 @@ ahpp_status_t ahpp_graph_tune(ahpp_graph_t *g, int32_t max_tiles, ahpp_tune_info
  * kind), DEVICE. */
 ahpp_status_t ahpp_profile_enable(ahpp_graph_t *g, int32_t on);
 ahpp_status_t ahpp_profile_read(ahpp_graph_t *g, int32_t kind, int64_t *launches, double *total_ms,
-                                double *algo_bytes);
+                                double *algo_bytes, double *compulsory_bytes);
 
 /* Text of the last error on the calling thread ("" if none). */
 const char *ahpp_last_error(void);

@@ -91,7 +91,7 @@ def _load():
     lib.og_push_schedule.restype = ctypes.c_int
     lib.og_push_schedule.argtypes = [P, dbl, dbl, i32, dbl, dbl, i32, i64, P, P, P, P, P]
     lib.og_asrp_many.restype = ctypes.c_int
-    lib.og_asrp_many.argtypes = [P, dbl, dbl, i32, P, dbl, dbl, i64, ctypes.c_int, P, P]
+    lib.og_asrp_many.argtypes = [P, dbl, dbl, i32, P, dbl, dbl, i64, ctypes.c_int, P, P, P]
     lib.og_max_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -262,10 +262,12 @@ class OracleGraph:
         src = np.ascontiguousarray(sources, dtype=np.int32)
         pi = np.zeros((src.size, self.n_u)) if keep_pi else None
         st = (_Stats * max(1, src.size))()
+        secs = np.zeros(max(1, src.size))
         bad = _load().og_asrp_many(self._h, alpha, beta, int(src.size), _ptr(src), eps, lam, int(max_iters),
-                                   int(nthreads), _ptr(pi), ctypes.cast(st, ctypes.c_void_p))
+                                   int(nthreads), _ptr(pi), ctypes.cast(st, ctypes.c_void_p), _ptr(secs))
         stats = [PushStats(s.iterations, s.switch_iteration, s.n_push, s.max_residual, s.sum_residual)
                  for s in st[: src.size]]
+        self.last_secs = secs[: src.size]
         return pi, stats, bad
 
 

@@ -529,17 +529,20 @@ int og_push_schedule(const og_graph *g, double alpha, double beta, int32_t sourc
 /* Runs og_asrp for n_src sources, one source per thread (queries are
  * independent).  pi_out is n_src x n_u row-major (nullable).  Returns the
  * number of queries that failed. */
+/* secs (nullable): wall time of each query on its thread. */
 int og_asrp_many(const og_graph *g, double alpha, double beta, int32_t n_src, const int32_t *src, double eps,
-                 double lambda, int64_t max_iters, int nthreads, double *pi_out, og_stats *st) {
+                 double lambda, int64_t max_iters, int nthreads, double *pi_out, og_stats *st, double *secs) {
     int bad = 0;
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
     for (int32_t q = 0; q < n_src; ++q) {
+        const double t0 = omp_get_wtime();
         double *pi = pi_out ? pi_out + (size_t)q * (size_t)g->n_u
                             : (double *)malloc((size_t)g->n_u * sizeof(double));
         int rc = og_asrp(g, alpha, beta, src[q], eps, lambda, max_iters, pi, NULL, st ? &st[q] : NULL);
         if (rc != 0) bad += 1;
         if (!pi_out) free(pi);
+        if (secs) secs[q] = omp_get_wtime() - t0;
     }
     return bad;
 }

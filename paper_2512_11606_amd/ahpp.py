@@ -111,7 +111,7 @@ def load_library(path: str = LIB_PATH):
     lib.ahpp_profile_enable.restype = ctypes.c_int
     lib.ahpp_profile_enable.argtypes = [P, i32]
     lib.ahpp_profile_read.restype = ctypes.c_int
-    lib.ahpp_profile_read.argtypes = [P, i32, P, P, P]
+    lib.ahpp_profile_read.argtypes = [P, i32, P, P, P, P]
     lib.ahpp_last_error.restype = ctypes.c_char_p
     lib.ahpp_last_error.argtypes = []
     _lib = lib
@@ -365,12 +365,16 @@ def ahpp_graph_tune(g: Graph, max_tiles: int = 0, stream=None) -> dict:
 
 
 def ahpp_profile_read(g: Graph, kind: int) -> dict:
-    """Launch count, summed elapsed ms and algorithmic bytes of one kernel kind."""
+    """Launch count, summed elapsed ms, gathered-model bytes and compulsory
+    bytes of one kernel kind (see ahpp.h)."""
     n = ctypes.c_int64(0)
     ms = ctypes.c_double(0.0)
     by = ctypes.c_double(0.0)
-    _check(load_library().ahpp_profile_read(g._h, int(kind), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
-    return {"launches": int(n.value), "ms": float(ms.value), "bytes": float(by.value)}
+    comp = ctypes.c_double(0.0)
+    _check(load_library().ahpp_profile_read(g._h, int(kind), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
+                                            ctypes.byref(comp)))
+    return {"launches": int(n.value), "ms": float(ms.value), "bytes": float(by.value),
+            "compulsory": float(comp.value)}
 
 
 class Server:

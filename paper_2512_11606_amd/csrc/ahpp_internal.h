@@ -111,6 +111,8 @@ struct QueryCtl {
     unsigned long long n_p;
     float last_max;
     int32_t source;       // -1 for an empty lane
+    float theta_q;        // threshold the transport rows Q were cut with (the previous round's theta)
+    int32_t pad;
 };
 
 struct TileCtl {
@@ -124,9 +126,11 @@ struct TileCtl {
 struct BatchState {
     int tiles = 0;                  // tiles allocated
     int grid_x = 0;                 // workgroups per tile of the gather kernels
-    float *r = nullptr;             // [tiles][n_u][kTileQ]
-    float *pi = nullptr;            // [tiles][n_u][kTileQ]
-    float *z = nullptr;             // [tiles][n_v + n_a][kTileQ]
+    float *r = nullptr;             // [tiles][n_u][kTileQ] residues
+    float *pi = nullptr;            // [tiles][n_u][kTileQ] reserves
+    uint16_t *q = nullptr;          // [tiles][n_u][kTileQ] bf16 transport of r (what a push moves)
+    float *c = nullptr;             // [tiles][n_v + n_a][kTileQ] V / attribute carries (z - zh)
+    uint16_t *zh = nullptr;         // [tiles][n_v + n_a][kTileQ] bf16 transport of z = r_V / d(v), r_A / t(a)
     float *part = nullptr;          // [tiles][max(n_items)][kTileQ]
     TileCtl *ctl = nullptr;         // [tiles]
     float *blk_max = nullptr;       // [tiles][2][grid_x][kTileQ]
@@ -190,7 +194,8 @@ constexpr int kProfKinds = 5;
 struct ProfLaunch {
     int kind;
     hipEvent_t start, stop;
-    double bytes;
+    double bytes;       // gathered-model bytes of the launch
+    double compulsory;  // compulsory bytes of the launch
 };
 struct Profiler {
     bool on = false;
@@ -198,15 +203,16 @@ struct Profiler {
     int64_t launches[kProfKinds] = {};
     double ms[kProfKinds] = {};
     double bytes[kProfKinds] = {};
+    double compulsory[kProfKinds] = {};
 };
 // Records `kind` around the launches issued by f() when profiling is on.
 template <class F>
-void profiled(Profiler &p, int kind, double bytes, hipStream_t s, F f) {
+void profiled(Profiler &p, int kind, double bytes, double compulsory, hipStream_t s, F f) {
     if (!p.on) {
         f();
         return;
     }
-    ProfLaunch l{kind, nullptr, nullptr, bytes};
+    ProfLaunch l{kind, nullptr, nullptr, bytes, compulsory};
     if (hipEventCreate(&l.start) != hipSuccess || hipEventCreate(&l.stop) != hipSuccess) {
         f();
         return;

@@ -15,6 +15,28 @@
 //
 // A query that has stopped keeps threshold +inf: it pushes nothing, so its
 // state no longer changes while the rest of its tile runs on.
+//
+// Transport precision.  Residues and reserves stay float32, but what one
+// half-step hands to the other moves as bfloat16 rounded toward zero (the top
+// 16 bits of the float), with the exact remainder kept where it was:
+//   * a U node that clears the threshold (r(u) > theta, compared in float32
+//     as Algorithm 4 does) pushes q(u) = rz16(r(u)) <= r(u) and keeps
+//     r(u) - q(u) (exact in float32) as residue.  The forward half-step of
+//     one round writes Q(u) = r(u) > theta ? rz16(r(u)) : 0 for the next,
+//     which the back gather reads; the next forward epilogue recomputes the
+//     same value from r(u) and that round's theta (theta_q), so both halves
+//     push the same amount;
+//   * a V / attribute row x hands on zh(x) = rz16(z(x)) and keeps the carry
+//     c(x) = z(x) - zh(x) for its next round; the forward gather reads the
+//     bf16 table ZH.
+// A push of any amount up to the residue keeps Lemma 2's invariant once the
+// carries count as residues at their rows (they are mass on its way from V /
+// the attributes to U), so with r'(u) = r(u) + sum_x w(u,x) c(x), the residue
+// a push of every carry would leave, pi - pi_hat = sum_j r'(j) pi(j, .).
+// Since c(x) < 2^-7 zh(x), r'(u) <= r(u) + 2^-7 s(u) with s(u) the sum this
+// round pulled in, and the stop rule tests that bound against eps_f, so
+// Theorem 2's eps holds as stated.  The random row gathers, which set the
+// time of a round, move 512 bytes per tile row instead of 1 KB.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -32,7 +54,7 @@ static_assert(kVec == 4 || kVec == 2 || kVec == 1, "kVec must be 1, 2 or 4");
 static_assert(kTileQ <= kBlock, "one workgroup thread per tile query");
 
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kInFlight = 8;  // gathers issued before the first is used
+constexpr int kInFlight = 16;  // gathers issued before the first is used (8 bytes per lane each)
 constexpr int kMaskWords = kTileQ / 64;
 enum BMode { kBBack = 0, kBFwd = 1 };
 
@@ -77,6 +99,20 @@ __device__ __forceinline__ void qv_store(float *p, const QV &a) {
     }
 }
 
+// Transport values: bfloat16 rounded toward zero, i.e. the top 16 bits of a
+// float; kVec of them per lane (8 bytes).
+constexpr float kCarryBound = 0.0078125f;  // 2^-7: carry < kCarryBound * rz16(value)
+
+__device__ __forceinline__ float rz16(float v) { return __uint_as_float(__float_as_uint(v) & 0xFFFF0000u); }
+
+// Stores rz16 of the four values (the top 16 bits of each).
+__device__ __forceinline__ void qh_store(uint16_t *p, const QV &a) {
+    uint2 t;
+    t.x = (__float_as_uint(a.v[0]) >> 16) | (__float_as_uint(a.v[1]) & 0xFFFF0000u);
+    t.y = (__float_as_uint(a.v[2]) >> 16) | (__float_as_uint(a.v[3]) & 0xFFFF0000u);
+    *reinterpret_cast<uint2 *>(p) = t;
+}
+
 struct BArgs {
     const int64_t *__restrict__ off;
     const int32_t *__restrict__ col;
@@ -85,13 +121,14 @@ struct BArgs {
     int64_t n_items;
     const SplitRow *__restrict__ split;
     int64_t n_split;
-    const float *x;        // gathered tile vector (tile 0), rows of kTileQ
-    float *y;              // written tile vector (tile 0)
+    const uint16_t *x;     // gathered bf16 table (tile 0), rows of kTileQ: Q (kBBack) or ZH (kBFwd)
+    float *y;              // written float rows (tile 0): carries (kBBack) or residues (kBFwd)
+    uint16_t *yh;          // written bf16 rows (tile 0): ZH (kBBack) or Q (kBFwd)
     float *pi;             // reserves (tile 0), kBFwd
     const float *inv_b;    // kBBack row scale
     float *part;           // chunk partials (tile 0), [item][kTileQ]
     TileCtl *ctl;          // tile 0
-    int64_t x_stride, y_stride, pi_stride, part_stride;  // floats per tile
+    int64_t x_stride, y_stride, pi_stride, part_stride;  // elements per tile (y and yh share y_stride)
     float *blk_max;        // [tile][2][batch_cap][kTileQ] slot base of this launch
     unsigned long long *blk_np;  // [tile][5][batch_cap][kTileQ] slot base
     int64_t blk_stride_f, blk_stride_u;   // elements per tile
@@ -118,20 +155,29 @@ template <>
 struct BEpi<kBBack> {
     struct Pre {
         float scale;
+        QV c;  // carries of the row
     };
-    float *z;
+    float *c;
+    uint16_t *zh;
     QV theta;
     unsigned long long np[kVec];
     float mx[kVec];
-    __device__ Pre pre(int64_t, float scale) const { return Pre{scale}; }
+    __device__ Pre pre(int64_t row, float scale) const { return Pre{scale, qv_load(c + row * kTileQ + lane_col())}; }
+    // z = carry + inv_b * sum; hands on zh = rz16(z), keeps z - zh.  A
+    // stopped query (threshold +inf) hands on nothing and keeps its carries.
     __device__ void full(int64_t row, const QV &s, const Pre &p, int64_t len) {
-        QV v;
+        const int64_t i = row * kTileQ + lane_col();
+        QV nc, h;
 #pragma unroll
         for (int j = 0; j < kVec; ++j) {
-            v.v[j] = p.scale * s.v[j];
-            if (v.v[j] > 0.0f) np[j] += (unsigned long long)len;
+            const float v = p.c.v[j] + p.scale * s.v[j];
+            const bool live = theta.v[j] != FLT_MAX;
+            h.v[j] = live ? rz16(v) : 0.0f;
+            nc.v[j] = live ? v - h.v[j] : p.c.v[j];
+            if (live && v > 0.0f) np[j] += (unsigned long long)len;
         }
-        qv_store(z + row * kTileQ + lane_col(), v);
+        qv_store(c + i, nc);
+        qh_store(zh + i, h);
     }
 };
 
@@ -142,7 +188,9 @@ struct BEpi<kBFwd> {
     };
     float *r;
     float *pi;
+    uint16_t *q;
     QV theta;
+    QV theta_q;
     float alpha;
     unsigned long long np[kVec];
     float mx[kVec];
@@ -150,19 +198,27 @@ struct BEpi<kBFwd> {
         const int64_t i = row * kTileQ + lane_col();
         return Pre{qv_load(r + i), qv_load(pi + i)};
     }
+    // u pushed in the back half-step the Q value of its residue (rz16(r) if r
+    // cleared the threshold Q was cut with, else 0) and keeps the exact rest;
+    // the next round's Q is cut with this round's threshold.  The stop
+    // statistic bounds the residue left once the carries are pushed too.
     __device__ void full(int64_t row, const QV &s, const Pre &p, int64_t len) {
         const int64_t i = row * kTileQ + lane_col();
-        QV nr, np_;
+        QV nr, np_, nq;
 #pragma unroll
         for (int j = 0; j < kVec; ++j) {
-            const bool pushed = p.r.v[j] > theta.v[j];
-            np_.v[j] = pushed ? p.pi.v[j] + alpha * p.r.v[j] : p.pi.v[j];
+            const bool live = theta.v[j] != FLT_MAX;
+            const float qv = live && p.r.v[j] > theta_q.v[j] ? rz16(p.r.v[j]) : 0.0f;
+            const bool pushed = qv > 0.0f;
+            np_.v[j] = pushed ? p.pi.v[j] + alpha * qv : p.pi.v[j];
             if (pushed) np[j] += (unsigned long long)len;
-            nr.v[j] = (pushed ? 0.0f : p.r.v[j]) + s.v[j];
-            mx[j] = fmaxf(mx[j], nr.v[j]);
+            nr.v[j] = (p.r.v[j] - qv) + s.v[j];
+            nq.v[j] = nr.v[j] > theta.v[j] ? nr.v[j] : 0.0f;
+            mx[j] = fmaxf(mx[j], nr.v[j] + kCarryBound * s.v[j]);
         }
         qv_store(pi + i, np_);
         qv_store(r + i, nr);
+        qh_store(q + i, nq);
     }
 };
 
@@ -170,7 +226,7 @@ struct BEpi<kBFwd> {
 // flushing each completed row of [r0, r0 + n_rows) through the epilogue.
 // Row ends are relative to e0; rows may be empty.
 template <bool kUnit, int kMode, class RowEnd, class RowScale>
-__device__ __forceinline__ void run_entries(const BArgs &a, const float *__restrict__ xt, int64_t r0, int n_rows,
+__device__ __forceinline__ void run_entries(const BArgs &a, const uint16_t *__restrict__ xt, int64_t r0, int n_rows,
                                             int64_t e0, int ne, BEpi<kMode> &epi, RowEnd row_end,
                                             RowScale row_scale, QV *acc_out) {
     using Pre = typename BEpi<kMode>::Pre;
@@ -196,22 +252,26 @@ __device__ __forceinline__ void run_entries(const BArgs &a, const float *__restr
         float my_w = 1.0f;
         if constexpr (!kUnit) my_w = lane < cnt ? a.w[e0 + base + lane] : 0.0f;
         for (int k0 = 0; k0 < cnt; k0 += kInFlight) {
-            QV v[kInFlight];
+            uint2 v[kInFlight];  // packed transport values, unpacked when added
 #pragma unroll
             for (int u = 0; u < kInFlight; ++u) {
                 const int k = k0 + u < kWave ? k0 + u : kWave - 1;
                 const int32_t c = __builtin_amdgcn_readlane(my_c, k);
-                v[u] = k0 + u < cnt ? qv_load(xt + (int64_t)c * kTileQ + lc) : qv_zero();
+                v[u] = k0 + u < cnt ? *reinterpret_cast<const uint2 *>(xt + (int64_t)c * kTileQ + lc)
+                                    : make_uint2(0u, 0u);
             }
 #pragma unroll
             for (int u = 0; u < kInFlight; ++u) {
                 const int k = k0 + u;
                 if (k < cnt) {
                     const float wk = kUnit ? 1.0f : readlane_f(my_w, k);
+                    const float xu[kVec] = {__uint_as_float(v[u].x << 16), __uint_as_float(v[u].x & 0xFFFF0000u),
+                                            __uint_as_float(v[u].y << 16), __uint_as_float(v[u].y & 0xFFFF0000u)};
 #pragma unroll
                     for (int q = 0; q < kVec; ++q) {
-                        float xv = v[u].v[q];
-                        if constexpr (kMode == kBBack) xv = xv > epi.theta.v[q] ? xv : 0.0f;
+                        float xv = xu[q];
+                        // Q is already cut by the threshold; a stopped query pushes nothing.
+                        if constexpr (kMode == kBBack) xv = epi.theta.v[q] != FLT_MAX ? xv : 0.0f;
                         acc.v[q] += kUnit ? xv : wk * xv;
                     }
                     const int e = base + k + 1;
@@ -238,13 +298,20 @@ template <int kMode>
 __device__ __forceinline__ BEpi<kMode> make_bepi(const BArgs &a, int t, const QV &theta) {
     BEpi<kMode> e;
     if constexpr (kMode == kBBack) {
-        e.z = a.y + t * a.y_stride;
+        e.c = a.y + t * a.y_stride;
+        e.zh = a.yh + t * a.y_stride;
     } else {
         e.r = a.y + t * a.y_stride;
+        e.q = a.yh + t * a.y_stride;
         e.pi = a.pi + t * a.pi_stride;
         e.alpha = a.alpha;
     }
     e.theta = theta;
+    if constexpr (kMode == kBFwd) {
+        const int q0 = (threadIdx.x & 63) * kVec;
+#pragma unroll
+        for (int j = 0; j < kVec; ++j) e.theta_q.v[j] = a.ctl[t].q[q0 + j].theta_q;
+    }
 #pragma unroll
     for (int j = 0; j < kVec; ++j) {
         e.np[j] = 0;
@@ -263,7 +330,7 @@ __device__ __forceinline__ QV lane_theta(const TileCtl &tc) {
 
 // Per-workgroup max and n_p of every query of the tile, one slot per query.
 template <int kMode>
-__device__ __forceinline__ void bflush(const BArgs &a, int t, BEpi<kMode> &epi) {
+__device__ __forceinline__ void bflush(const BArgs &a, int t, int j, BEpi<kMode> &epi) {
     __shared__ float smx[kWavesPerBlock][kTileQ];
     __shared__ unsigned long long snp[kWavesPerBlock][kTileQ];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -282,7 +349,7 @@ __device__ __forceinline__ void bflush(const BArgs &a, int t, BEpi<kMode> &epi) 
             m = fmaxf(m, smx[i][q]);
             n += snp[i][q];
         }
-        const int64_t o = (int64_t)blockIdx.x * kTileQ + q;
+        const int64_t o = (int64_t)j * kTileQ + q;
         if (a.blk_max) a.blk_max[t * a.blk_stride_f + o] = m;
         if (a.blk_np) a.blk_np[t * a.blk_stride_u + o] = n;
     }
@@ -290,14 +357,14 @@ __device__ __forceinline__ void bflush(const BArgs &a, int t, BEpi<kMode> &epi) 
 
 template <bool kUnit, int kMode>
 __global__ void __launch_bounds__(kBlock) kb_gather(BArgs a) {
-    const int t = blockIdx.y;
+    const int t = blockIdx.y, wg = blockIdx.x;
     const TileCtl &tc = a.ctl[t];
     if (tc.all_done) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const float *xt = a.x + t * a.x_stride;
+    const uint16_t *xt = a.x + t * a.x_stride;
     float *part = a.part + t * a.part_stride;
     BEpi<kMode> epi = make_bepi<kMode>(a, t, lane_theta(tc));
-    const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t wave0 = (int64_t)wg * kWavesPerBlock + (threadIdx.x >> 6);
     const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t it = wave0; it < a.n_items; it += stride) {
         const WorkItem item = a.items[it];
@@ -335,18 +402,18 @@ __global__ void __launch_bounds__(kBlock) kb_gather(BArgs a) {
             if (!whole) qv_store(part + it * kTileQ + lane_col(), acc);
         }
     }
-    bflush<kMode>(a, t, epi);
+    bflush<kMode>(a, t, wg, epi);
 }
 
 // Rows cut into chunks: one wave per row adds its chunk sums per query.
 template <int kMode>
 __global__ void __launch_bounds__(kBlock) kb_fix(BArgs a) {
-    const int t = blockIdx.y;
+    const int t = blockIdx.y, wg = blockIdx.x;
     const TileCtl &tc = a.ctl[t];
     if (tc.all_done) return;
     const float *part = a.part + t * a.part_stride;
     BEpi<kMode> epi = make_bepi<kMode>(a, t, lane_theta(tc));
-    const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t wave0 = (int64_t)wg * kWavesPerBlock + (threadIdx.x >> 6);
     const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t i = wave0; i < a.n_split; i += stride) {
         const SplitRow sr = a.split[i];
@@ -371,7 +438,7 @@ __global__ void __launch_bounds__(kBlock) kb_fix(BArgs a) {
         const float scale = kMode == kBBack ? a.inv_b[sr.row] : 0.0f;
         epi.full(sr.row, s, epi.pre(sr.row, scale), a.off[sr.row + 1] - a.off[sr.row]);
     }
-    bflush<kMode>(a, t, epi);
+    bflush<kMode>(a, t, wg, epi);
 }
 
 // One workgroup per tile, one thread per query: max r and n_p from the
@@ -438,6 +505,7 @@ __global__ void __launch_bounds__(kTileQ) kb_control(TileCtl *ctl, const float *
     QueryCtl &c = tc.q[q];
     int done = c.done;
     if (!done) {
+        c.theta_q = c.theta;  // the threshold this round's forward half-step cut Q with
         const unsigned long long n_p = c.n_p + np;
         const int iter = c.iter + 1;
         c.n_p = n_p;
@@ -475,7 +543,7 @@ __global__ void __launch_bounds__(kTileQ) kb_control(TileCtl *ctl, const float *
 // ---------------------------------------------------------------- hot rows
 
 struct HotArgs {
-    const float *r;         // residues (tile 0)
+    const uint16_t *q;      // bf16 transport residues Q (tile 0)
     int64_t r_stride;
     float *part;            // chunk partials (tile 0), [n_chunks][n_hot][kTileQ]
     int64_t part_stride;
@@ -495,7 +563,7 @@ static_assert(kHotPerWave < kWave, "a block's segment offsets sit one per lane")
 // What a wave needs for one block of U rows, loaded one block ahead with
 // vector loads (coalesced, many in flight) and read back with readlane.
 struct HotBlock {
-    float4 x[kHotStage];   // the thread's share of the block's residues (raw)
+    uint2 x[kHotStage];    // the thread's share of the block's transport residues (4 x bf16 each)
     int64_t off;           // lane s <= kHotPerWave: start of the wave's segment s (s = kHotPerWave: the end)
     int32_t p0, p1;        // entries e_b + lane and e_b + 64 + lane: row within the block
     float w0, w1;          //   and back weight
@@ -527,7 +595,7 @@ __global__ void __launch_bounds__(kHotThreads) kb_hot(HotArgs a, const int64_t *
     float sth[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) sth[k] = tc.q[scol + k].theta;
-    const float *rt = a.r + t * a.r_stride;
+    const uint16_t *rt = a.q + t * a.r_stride;
     float *pt = a.part + t * a.part_stride;
     const int c = blockIdx.x;
     const int64_t u0 = a.chunk_start[c], u1 = a.chunk_start[c + 1];
@@ -545,8 +613,7 @@ __global__ void __launch_bounds__(kHotThreads) kb_hot(HotArgs a, const int64_t *
 #pragma unroll
         for (int i = 0; i < kHotStage; ++i) {
             const int64_t u = ub + (tid + i * kHotThreads) / (kTileQ / 4);
-            blk.x[i] = u < u1 ? *reinterpret_cast<const float4 *>(rt + u * kTileQ + scol)
-                              : make_float4(0.f, 0.f, 0.f, 0.f);
+            blk.x[i] = u < u1 ? *reinterpret_cast<const uint2 *>(rt + u * kTileQ + scol) : make_uint2(0u, 0u);
         }
         blk.off = (lane <= kHotPerWave && b < nb) ? seg[b * kHotPerWave + lane] : 0;
         blk.p0 = e_b + lane < e_end ? hot_col[e_b + lane] : 0;
@@ -557,11 +624,12 @@ __global__ void __launch_bounds__(kHotThreads) kb_hot(HotArgs a, const int64_t *
     auto stage = [&](int buf, const HotBlock &blk) {
 #pragma unroll
         for (int i = 0; i < kHotStage; ++i) {
-            float4 v = blk.x[i];
-            v.x = v.x > sth[0] ? v.x : 0.0f;
-            v.y = v.y > sth[1] ? v.y : 0.0f;
-            v.z = v.z > sth[2] ? v.z : 0.0f;
-            v.w = v.w > sth[3] ? v.w : 0.0f;
+            float4 v = make_float4(__uint_as_float(blk.x[i].x << 16), __uint_as_float(blk.x[i].x & 0xFFFF0000u),
+                                   __uint_as_float(blk.x[i].y << 16), __uint_as_float(blk.x[i].y & 0xFFFF0000u));
+            v.x = sth[0] != FLT_MAX ? v.x : 0.0f;
+            v.y = sth[1] != FLT_MAX ? v.y : 0.0f;
+            v.z = sth[2] != FLT_MAX ? v.z : 0.0f;
+            v.w = sth[3] != FLT_MAX ? v.w : 0.0f;
             xs[buf][tid + i * kHotThreads] = v;
         }
     };
@@ -651,7 +719,8 @@ struct HotReduceArgs {
     int64_t part_stride;
     const int32_t *rows, *len;
     const float *inv_b;
-    float *z;               // tile 0
+    float *c;               // carries (tile 0)
+    uint16_t *zh;           // bf16 transport rows ZH (tile 0)
     int64_t z_stride;
     unsigned long long *blk_np;  // n_p slot of this launch (tile 0)
     int64_t blk_stride_u;
@@ -659,8 +728,10 @@ struct HotReduceArgs {
     int n_hot, n_chunks;
 };
 
-// One workgroup per (hot row, tile): z(x) = inv_b(x) * (chunk partials added
-// in chunk order), and the row's entry count for the queries it pushes.
+// One workgroup per (hot row, tile): z(x) = carry + inv_b(x) * (chunk
+// partials added in chunk order), handed on as rz16(z) with the rest kept as
+// carry (as the back gather's epilogue), and the row's entry count for the
+// queries it pushes.
 __global__ void __launch_bounds__(kBlock) kb_hot_reduce(HotReduceArgs a) {
     const int h = blockIdx.x, t = blockIdx.y;
     if (a.ctl[t].all_done) return;
@@ -678,15 +749,22 @@ __global__ void __launch_bounds__(kBlock) kb_hot_reduce(HotReduceArgs a) {
     }
     for (; c < a.n_chunks; ++c) s += pt[c * cs];
     const int32_t x = a.rows[h];
-    const float v = a.inv_b[x] * s;
-    a.z[t * a.z_stride + (int64_t)x * kTileQ + q] = v;
-    a.blk_np[t * a.blk_stride_u + (int64_t)h * kTileQ + q] = v > 0.0f ? (unsigned long long)a.len[h] : 0ull;
+    const int64_t i = t * a.z_stride + (int64_t)x * kTileQ + q;
+    const float c0 = a.c[i];
+    const float v = c0 + a.inv_b[x] * s;
+    const bool live = a.ctl[t].q[q].theta != FLT_MAX;
+    const float h16 = live ? rz16(v) : 0.0f;
+    a.c[i] = live ? v - h16 : c0;
+    a.zh[i] = (uint16_t)(__float_as_uint(h16) >> 16);
+    a.blk_np[t * a.blk_stride_u + (int64_t)h * kTileQ + q] = live && v > 0.0f ? (unsigned long long)a.len[h] : 0ull;
 }
 
 __global__ void kb_fill(float *p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.0f;
 }
+
+constexpr uint16_t kOneBf16 = 0x3F80;  // 1.0f as bfloat16
 
 struct InitQuery {
     int32_t source;
@@ -695,8 +773,8 @@ struct InitQuery {
 
 // One workgroup per tile, one thread per query: start query q of the tile
 // (or leave the slot empty).
-__global__ void __launch_bounds__(kTileQ) kb_init(TileCtl *ctl, float *r, int64_t r_stride, const InitQuery *qs,
-                                                  int64_t n_valid, int32_t max_iters) {
+__global__ void __launch_bounds__(kTileQ) kb_init(TileCtl *ctl, float *r, uint16_t *qh, int64_t r_stride,
+                                                  const InitQuery *qs, int64_t n_valid, int32_t max_iters) {
     __shared__ int running_any[kTileQ / kWave];
     const int t = blockIdx.x, q = threadIdx.x;
     const int64_t gq = (int64_t)t * kTileQ + q;
@@ -705,8 +783,13 @@ __global__ void __launch_bounds__(kTileQ) kb_init(TileCtl *ctl, float *r, int64_
     const int32_t src = live ? qs[gq].source : -1;
     const float eps_f = live ? qs[gq].eps_f : 1.0f;
     const bool run = live && 1.0f > eps_f;
-    if (live) r[t * r_stride + (int64_t)src * kTileQ + q] = 1.0f;
+    if (live) {
+        r[t * r_stride + (int64_t)src * kTileQ + q] = 1.0f;
+        qh[t * r_stride + (int64_t)src * kTileQ + q] = kOneBf16;
+    }
     c.theta = run ? eps_f : FLT_MAX;
+    c.theta_q = 0.0f;  // Q holds the unit residue of the source, as cut with threshold 0
+    c.pad = 0;
     c.eps_f = eps_f;
     c.done = run ? 0 : 1;
     c.phase = 1;
@@ -727,9 +810,11 @@ __global__ void __launch_bounds__(kTileQ) kb_init(TileCtl *ctl, float *r, int64_
     }
 }
 
-// Zeroes the residue and reserve of the queries set in the tile's mask words
-// (masks[t * kMaskWords + q / 64] bit q % 64), in every row.
-__global__ void __launch_bounds__(kBlock) kb_clear_lanes(float *r, float *pi, int64_t tile_u, int64_t n_u,
+// Zeroes the residue, transport residue and reserve (U rows) and the carry
+// (V / attribute rows) of the queries set in the tile's mask words
+// (masks[t * kMaskWords + q / 64] bit q % 64).
+__global__ void __launch_bounds__(kBlock) kb_clear_lanes(float *r, uint16_t *qh, float *pi, int64_t tile_u,
+                                                         int64_t n_u, float *c, int64_t tile_x, int64_t n_x,
                                                          const unsigned long long *masks) {
     const int t = blockIdx.y;
     const unsigned long long *m = masks + (int64_t)t * kMaskWords;
@@ -747,20 +832,30 @@ __global__ void __launch_bounds__(kBlock) kb_clear_lanes(float *r, float *pi, in
         some = some || mine[j];
     }
     if (!some) return;
-    float *rt = r + t * tile_u, *pt = pi + t * tile_u;
-    for (int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + wid; u < n_u; u += (int64_t)gridDim.x * kWavesPerBlock) {
+    float *rt = r + t * tile_u, *pt = pi + t * tile_u, *ct = c + t * tile_x;
+    uint16_t *qt = qh + t * tile_u;
+    const int64_t step = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t u = (int64_t)blockIdx.x * kWavesPerBlock + wid; u < n_u; u += step) {
 #pragma unroll
         for (int j = 0; j < kVec; ++j) {
             if (mine[j]) {
-                rt[u * kTileQ + lane * kVec + j] = 0.0f;
-                pt[u * kTileQ + lane * kVec + j] = 0.0f;
+                const int64_t i = u * kTileQ + lane * kVec + j;
+                rt[i] = 0.0f;
+                pt[i] = 0.0f;
+                qt[i] = 0;
             }
         }
+    }
+    for (int64_t x = (int64_t)blockIdx.x * kWavesPerBlock + wid; x < n_x; x += step) {
+#pragma unroll
+        for (int j = 0; j < kVec; ++j)
+            if (mine[j]) ct[x * kTileQ + lane * kVec + j] = 0.0f;
     }
 }
 
 // Starts admitted queries: unit residue at the source and a fresh control.
-__global__ void kb_admit(TileCtl *ctl, float *r, int64_t tile_u, const AdmitReq *req, int n, int32_t max_iters) {
+__global__ void kb_admit(TileCtl *ctl, float *r, uint16_t *qh, int64_t tile_u, const AdmitReq *req, int n,
+                         int32_t max_iters) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const AdmitReq a = req[i];
@@ -768,7 +863,10 @@ __global__ void kb_admit(TileCtl *ctl, float *r, int64_t tile_u, const AdmitReq 
     QueryCtl &c = tc.q[a.lane];
     const bool run = 1.0f > a.eps_f;
     r[a.tile * tile_u + (int64_t)a.source * kTileQ + a.lane] = 1.0f;
+    qh[a.tile * tile_u + (int64_t)a.source * kTileQ + a.lane] = kOneBf16;
     c.theta = run ? a.eps_f : FLT_MAX;
+    c.theta_q = 0.0f;
+    c.pad = 0;
     c.eps_f = a.eps_f;
     c.done = run ? 0 : 1;
     c.phase = 1;
@@ -876,6 +974,7 @@ struct BPlan {
     unsigned back, back_fix, fwd, fwd_fix;
 };
 
+
 // Workgroups per tile: enough waves to cover the items, at most the
 // per-launch budget spread over the tiles in flight.
 // The back schedule of the batched engine: every row, or only the cold rows
@@ -909,7 +1008,8 @@ BPlan bplan(const Graph &g, int nt) {
 
 void free_batch_state(BatchState &b) {
     for (auto &e : b.round_graphs) (void)hipGraphExecDestroy(e.second);
-    for (void *p : {(void *)b.r, (void *)b.pi, (void *)b.z, (void *)b.part, (void *)b.ctl, (void *)b.blk_max,
+    for (void *p : {(void *)b.r, (void *)b.pi, (void *)b.q, (void *)b.c, (void *)b.zh, (void *)b.part, (void *)b.ctl,
+                    (void *)b.blk_max,
                     (void *)b.blk_np, (void *)b.red_max, (void *)b.red_np, (void *)b.hot_part, (void *)b.out,
                     (void *)b.sums})
         dfree(p);
@@ -920,7 +1020,8 @@ int64_t batch_tile_bytes(const Graph &g, bool with_out) {
     const int64_t items = std::max<int64_t>(std::max(g.fwd.n_items, g.back.n_items), 1);
     const int64_t Q = kTileQ;
     const int64_t hot = (int64_t)g.hot.n_chunks * g.hot.n;
-    return Q * 4 * (2 * g.n_u + std::max<int64_t>(g.n_v + g.n_a, 1) + items + hot + (with_out ? g.n_u : 0)) +
+    // Per (node, query): r, pi (4 + 4 B) and q (2 B) for U; carry (4 B) and zh (2 B) for V and attributes.
+    return Q * (10 * g.n_u + 6 * std::max<int64_t>(g.n_v + g.n_a, 1) + 4 * (items + hot + (with_out ? g.n_u : 0))) +
            (int64_t)sizeof(TileCtl) + (int64_t)batch_cap(g) * Q * (2 * 4 + 5 * 8) + (int64_t)g.grid_cap * Q * 8 +
            (int64_t)kCtlSlices * Q * 12;
 }
@@ -932,7 +1033,10 @@ void ensure_batch_state(Graph &g, BatchState &b, int tiles, bool with_out) {
     const size_t T = (size_t)tiles, Q = kTileQ;
     b.r = (float *)dev_alloc(g, T * g.n_u * Q * 4, "batch residues");
     b.pi = (float *)dev_alloc(g, T * g.n_u * Q * 4, "batch reserves");
-    b.z = (float *)dev_alloc(g, T * std::max<int64_t>(g.n_v + g.n_a, 1) * Q * 4, "batch V/attribute residues");
+    const size_t n_x = (size_t)std::max<int64_t>(g.n_v + g.n_a, 1);
+    b.q = (uint16_t *)dev_alloc(g, T * g.n_u * Q * 2, "batch transport residues");
+    b.c = (float *)dev_alloc(g, T * n_x * Q * 4, "batch V/attribute carries");
+    b.zh = (uint16_t *)dev_alloc(g, T * n_x * Q * 2, "batch V/attribute transport residues");
     b.part = (float *)dev_alloc(g, T * items * Q * 4, "batch chunk partials");
     b.ctl = (TileCtl *)dev_alloc(g, T * sizeof(TileCtl), "batch control");
     b.blk_max = (float *)dev_alloc(g, T * 2 * batch_cap(g) * Q * 4, "batch workgroup maxima");
@@ -947,18 +1051,30 @@ void ensure_batch_state(Graph &g, BatchState &b, int tiles, bool with_out) {
     b.grid_x = batch_cap(g);
 }
 
+namespace {
+// Zeroes r, pi, q and the carries of tiles [0, nt) (zh is rewritten by every
+// round's V / attribute half-step before it is read).
+void clear_tiles(Graph &g, BatchState &b, int nt, hipStream_t s) {
+    const int64_t tile_u = g.n_u * kTileQ, tile_x = std::max<int64_t>(g.n_v + g.n_a, 1) * kTileQ;
+    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.r, (int64_t)nt * tile_u);
+    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.pi, (int64_t)nt * tile_u);
+    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, reinterpret_cast<float *>(b.q),
+                       (int64_t)nt * tile_u / 2);
+    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.c, (int64_t)nt * tile_x);
+}
+}  // namespace
+
 void batch_init(Graph &g, BatchState &b, int nt, const int32_t *sources, const float *eps_f, int64_t n_q,
                 int32_t max_iters, hipStream_t s) {
     const int64_t tile_u = g.n_u * kTileQ;
-    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.r, (int64_t)nt * tile_u);
-    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.pi, (int64_t)nt * tile_u);
+    clear_tiles(g, b, nt, s);
     std::vector<InitQuery> hq((size_t)nt * kTileQ);
     const int64_t n_valid = std::min<int64_t>(n_q, (int64_t)nt * kTileQ);
     for (int64_t i = 0; i < n_valid; ++i) hq[i] = InitQuery{g.u_new_host[(size_t)sources[i]], eps_f[i]};
     InitQuery *dq = nullptr;
     check_hip(hipMallocAsync((void **)&dq, hq.size() * sizeof(InitQuery), s), "batch init");
     check_hip(hipMemcpyAsync(dq, hq.data(), hq.size() * sizeof(InitQuery), hipMemcpyHostToDevice, s), "batch init");
-    hipLaunchKernelGGL(kb_init, dim3(nt), dim3(kTileQ), 0, s, b.ctl, b.r, tile_u, dq, n_valid, max_iters);
+    hipLaunchKernelGGL(kb_init, dim3(nt), dim3(kTileQ), 0, s, b.ctl, b.r, b.q, tile_u, dq, n_valid, max_iters);
     check_hip(hipFreeAsync(dq, s), "batch init");
     check_hip(hipGetLastError(), "batch init launch");
 }
@@ -967,29 +1083,37 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
     const BPlan p = bplan(g, nt);
     const BackSched bs = back_sched(g);
     const HotSet &hs = g.hot;
-    const int64_t tile_u = g.n_u * kTileQ, tile_z = std::max<int64_t>(g.n_v + g.n_a, 1) * kTileQ;
+    const int64_t tile_u = g.n_u * kTileQ, tile_x = std::max<int64_t>(g.n_v + g.n_a, 1) * kTileQ;
     const int64_t tile_part = std::max<int64_t>(std::max(g.fwd.n_items, g.back.n_items), 1) * kTileQ;
     const int64_t sf = 2 * (int64_t)batch_cap(g) * kTileQ, su = 5 * (int64_t)batch_cap(g) * kTileQ;
     BArgs back{g.back.off, g.back.col, g.back.w, bs.items, bs.n_items, bs.split, bs.n_split,
-               b.r, b.z, nullptr, g.inv_b, b.part, b.ctl, tile_u, tile_z, 0, tile_part, nullptr, b.blk_np, sf, su,
-               (float)g.alpha};
+               b.q, b.c, b.zh, nullptr, g.inv_b, b.part, b.ctl, tile_u, tile_x, 0, tile_part, nullptr, b.blk_np, sf,
+               su, (float)g.alpha};
     // Slots of the n_p partials: 0 back, 1 back fix, 2 fwd, 3 fwd fix, 4 hot
     // rows; of the max partials: 0 fwd, 1 fwd fix; slots are batch_cap
     // workgroups apart.
     const int64_t slot = (int64_t)batch_cap(g) * kTileQ;
-    // Algorithmic bytes of a launch: CSR entries and offsets once, 4 bytes
-    // per (entry, running query), and the per-(row, query) state the
-    // epilogue reads and writes.  The hot-row pass reads the hot list and
-    // its segment offsets once and each query's residue of every U row once,
-    // and writes and re-reads its chunk partials.
+    // Bytes of a launch, two ways (q = running queries).  Gathered: the CSR
+    // entries and offsets once, one 2-byte transport value per (entry, query),
+    // and the per-(row, query) state the epilogue reads and writes.
+    // Compulsory: the CSR once, the gathered transport table once per query
+    // (every column once), and the same per-row state; the gap between the
+    // two is what caches must absorb.  The hot-row pass reads the hot list
+    // and its segment offsets once and each query's transport row of every U
+    // node once, and writes and re-reads its chunk partials (both counts).
     const double q = (double)b.live_q;
     const double wb = g.fwd.w ? 8.0 : 4.0;
-    const double back_bytes = 8.0 * bs.nnz + 12.0 * bs.rows + q * (4.0 * bs.nnz + 4.0 * bs.rows);
-    const double fwd_bytes = wb * g.fwd.nnz + 8.0 * g.fwd.n_rows + q * (4.0 * g.fwd.nnz + 16.0 * g.fwd.n_rows);
+    const double n_x = (double)std::max<int64_t>(g.n_v + g.n_a, 1);
+    const double back_csr = 8.0 * bs.nnz + 12.0 * bs.rows, back_row = 10.0 * bs.rows;  // carry r/w, zh w
+    const double fwd_csr = wb * g.fwd.nnz + 8.0 * g.fwd.n_rows, fwd_row = 18.0 * g.fwd.n_rows;  // r, pi r/w, q w
+    const double back_bytes = back_csr + q * (2.0 * bs.nnz + back_row);
+    const double back_comp = back_csr + q * (2.0 * g.n_u + back_row);
+    const double fwd_bytes = fwd_csr + q * (2.0 * g.fwd.nnz + fwd_row);
+    const double fwd_comp = fwd_csr + q * (2.0 * n_x + fwd_row);
     const double hot_bytes = 8.0 * hs.list.nnz + 8.0 * (hs.list.n_rows + 1) + 12.0 * hs.n +
-                             q * (4.0 * g.n_u + 8.0 * hs.n_chunks * hs.n + 4.0 * hs.n);
+                             q * (2.0 * g.n_u + 8.0 * hs.n_chunks * hs.n + 10.0 * hs.n);
     if (p.back)
-        profiled(g.prof, 2, back_bytes, s, [&] {
+        profiled(g.prof, 2, back_bytes, back_comp, s, [&] {
             hipLaunchKernelGGL((kb_gather<false, kBBack>), dim3(p.back, nt), dim3(kBlock), 0, s, back);
         });
     if (p.back_fix) {
@@ -999,22 +1123,24 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
     }
     if (hs.n > 0) {
         const int64_t tile_hot = (int64_t)hs.n_chunks * hs.n * kTileQ;
-        HotArgs ha{b.r,           tile_u,      b.hot_part, tile_hot, b.ctl, hs.chunk_start,
+        HotArgs ha{b.q,           tile_u,      b.hot_part, tile_hot, b.ctl, hs.chunk_start,
                    hs.blk_base,   hs.n_blocks, hs.n,       hs.n_chunks};
-        HotReduceArgs ra{b.hot_part, tile_hot, hs.rows, hs.len, g.inv_b, b.z, tile_z, b.blk_np + 4 * slot, su, b.ctl,
-                         hs.n, hs.n_chunks};
-        profiled(g.prof, 4, hot_bytes, s, [&] {
+        HotReduceArgs ra{b.hot_part, tile_hot, hs.rows, hs.len, g.inv_b, b.c, b.zh, tile_x, b.blk_np + 4 * slot, su,
+                         b.ctl, hs.n, hs.n_chunks};
+        profiled(g.prof, 4, hot_bytes, hot_bytes, s, [&] {
             hipLaunchKernelGGL(kb_hot, dim3((unsigned)hs.n_chunks, nt), dim3(kHotThreads), 0, s, ha,
                                (const int64_t *)hs.list.off, (const int32_t *)hs.list.col, (const float *)hs.list.w);
             hipLaunchKernelGGL(kb_hot_reduce, dim3((unsigned)hs.n, nt), dim3(kBlock), 0, s, ra);
         });
     }
     BArgs fwd{g.fwd.off, g.fwd.col, g.fwd.w, g.fwd.items, g.fwd.n_items, g.fwd.split, g.fwd.n_split,
-              b.z, b.r, b.pi, nullptr, b.part, b.ctl, tile_z, tile_u, tile_u, tile_part, b.blk_max,
+              b.zh, b.r, b.q, b.pi, nullptr, b.part, b.ctl, tile_x, tile_u, tile_u, tile_part, b.blk_max,
               b.blk_np + 2 * slot, sf, su, (float)g.alpha};
-    profiled(g.prof, 3, fwd_bytes, s, [&] {
-        if (g.unit) hipLaunchKernelGGL((kb_gather<true, kBFwd>), dim3(p.fwd, nt), dim3(kBlock), 0, s, fwd);
-        else hipLaunchKernelGGL((kb_gather<false, kBFwd>), dim3(p.fwd, nt), dim3(kBlock), 0, s, fwd);
+    profiled(g.prof, 3, fwd_bytes, fwd_comp, s, [&] {
+        if (g.unit)
+            hipLaunchKernelGGL((kb_gather<true, kBFwd>), dim3(p.fwd, nt), dim3(kBlock), 0, s, fwd);
+        else
+            hipLaunchKernelGGL((kb_gather<false, kBFwd>), dim3(p.fwd, nt), dim3(kBlock), 0, s, fwd);
     });
     if (p.fwd_fix) {
         BArgs a = fwd;
@@ -1128,9 +1254,8 @@ void batch_resid_sums(Graph &g, BatchState &b, int t0, int nt, double *sums, hip
 
 void batch_empty(Graph &g, BatchState &b, int nt, hipStream_t s) {
     const int64_t tile_u = g.n_u * kTileQ;
-    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.r, (int64_t)nt * tile_u);
-    hipLaunchKernelGGL(kb_fill, dim3(4096), dim3(kBlock), 0, s, b.pi, (int64_t)nt * tile_u);
-    hipLaunchKernelGGL(kb_init, dim3(nt), dim3(kTileQ), 0, s, b.ctl, b.r, tile_u, (const InitQuery *)nullptr,
+    clear_tiles(g, b, nt, s);
+    hipLaunchKernelGGL(kb_init, dim3(nt), dim3(kTileQ), 0, s, b.ctl, b.r, b.q, tile_u, (const InitQuery *)nullptr,
                        (int64_t)0, (int32_t)1);
     check_hip(hipGetLastError(), "batch empty launch");
 }
@@ -1150,8 +1275,11 @@ void batch_admit(Graph &g, BatchState &b, const std::vector<AdmitReq> &reqs, int
     check_hip(hipMemcpyAsync(dr, dev_reqs.data(), dev_reqs.size() * sizeof(AdmitReq), hipMemcpyHostToDevice, s),
               "admit");
     const unsigned gx = capped(g.n_u, kWavesPerBlock * 16, 1024);
-    hipLaunchKernelGGL(kb_clear_lanes, dim3(gx, b.tiles), dim3(kBlock), 0, s, b.r, b.pi, tile_u, g.n_u, dm);
+    const int64_t n_x = std::max<int64_t>(g.n_v + g.n_a, 1);
+    hipLaunchKernelGGL(kb_clear_lanes, dim3(gx, b.tiles), dim3(kBlock), 0, s, b.r, b.q, b.pi, tile_u, g.n_u, b.c,
+                       n_x * kTileQ, n_x, dm);
     hipLaunchKernelGGL(kb_admit, dim3(capped((int64_t)reqs.size(), kBlock, 1 << 20)), dim3(kBlock), 0, s, b.ctl, b.r,
+                       b.q,
                        tile_u, dr, (int)reqs.size(), max_iters);
     check_hip(hipFreeAsync(dm, s), "admit");
     check_hip(hipFreeAsync(dr, s), "admit");

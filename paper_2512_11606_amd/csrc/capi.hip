@@ -167,6 +167,7 @@ void profiler_flush(Profiler &p) {
             p.launches[l.kind] += 1;
             p.ms[l.kind] += ms;
             p.bytes[l.kind] += l.bytes;
+            p.compulsory[l.kind] += l.compulsory;
         }
         (void)hipEventDestroy(l.start);
         (void)hipEventDestroy(l.stop);
@@ -386,6 +387,7 @@ ahpp_status_t ahpp_profile_enable(ahpp_graph_t *h, int32_t on) {
             p.launches[k] = 0;
             p.ms[k] = 0.0;
             p.bytes[k] = 0.0;
+            p.compulsory[k] = 0.0;
         }
     }
     p.on = on != 0;
@@ -393,7 +395,7 @@ ahpp_status_t ahpp_profile_enable(ahpp_graph_t *h, int32_t on) {
 }
 
 ahpp_status_t ahpp_profile_read(ahpp_graph_t *h, int32_t kind, int64_t *launches, double *total_ms,
-                                double *algo_bytes) {
+                                double *algo_bytes, double *compulsory_bytes) {
     g_last_error.clear();
     if (!h) return fail(AHPP_ERR_INVALID_ARG, "ahpp_profile_read: NULL graph");
     if (kind < 0 || kind >= kProfKinds) return fail(AHPP_ERR_INVALID_ARG, "ahpp_profile_read: bad kind");
@@ -407,6 +409,7 @@ ahpp_status_t ahpp_profile_read(ahpp_graph_t *h, int32_t kind, int64_t *launches
     if (launches) *launches = p.launches[kind];
     if (total_ms) *total_ms = p.ms[kind];
     if (algo_bytes) *algo_bytes = p.bytes[kind];
+    if (compulsory_bytes) *compulsory_bytes = p.compulsory[kind];
     return AHPP_OK;
 }
 

@@ -451,13 +451,13 @@ Plan make_plan(const Graph &g) {
 // after the gather's.
 template <int kMode>
 void launch_gather(Graph &g, bool unit, const GatherArgs &a, unsigned grid, unsigned grid_fix, hipStream_t s,
-                   int prof_kind = -1, double prof_bytes = 0.0) {
+                   int prof_kind = -1, double prof_bytes = 0.0, double prof_comp = 0.0) {
     if (grid) {
         auto go = [&] {
             if (unit) hipLaunchKernelGGL((k_gather<true, kMode>), dim3(grid), dim3(kBlock), 0, s, a);
             else hipLaunchKernelGGL((k_gather<false, kMode>), dim3(grid), dim3(kBlock), 0, s, a);
         };
-        if (prof_kind >= 0) profiled(g.prof, prof_kind, prof_bytes, s, go);
+        if (prof_kind >= 0) profiled(g.prof, prof_kind, prof_bytes, prof_comp, s, go);
         else go();
     }
     if (grid_fix) {
@@ -579,12 +579,15 @@ void single_query_round(Graph &g, const QueryBufs &b, hipStream_t s, bool timed)
     // Algorithmic bytes: CSR entries (column, weight) and gathered residue per
     // entry, offsets and per-row state per row.
     const double wb = g.fwd.w ? 8.0 : 4.0;
+    // Compulsory: the CSR once, the gathered vector once, the per-row state.
     launch_gather<kBack>(g, false, back, p.back, p.back_fix, s, prof_back,
-                         12.0 * g.back.nnz + 16.0 * g.back.n_rows);
+                         12.0 * g.back.nnz + 16.0 * g.back.n_rows,
+                         8.0 * g.back.nnz + 16.0 * g.back.n_rows + 4.0 * g.n_u);
     GatherArgs fwd{view(g.fwd), b.z, b.r, b.pi, nullptr, b.part, b.ctl, 0.0f, (float)g.alpha,
                    b.blk_max, b.blk_np + 2 * g.grid_cap, g.deg_u};
     launch_gather<kFwdAcc>(g, g.unit, fwd, p.fwd, p.fwd_fix, s, prof_fwd,
-                           (wb + 4.0) * g.fwd.nnz + 24.0 * g.fwd.n_rows);
+                           (wb + 4.0) * g.fwd.nnz + 24.0 * g.fwd.n_rows,
+                           wb * g.fwd.nnz + 24.0 * g.fwd.n_rows + 4.0 * (g.n_v + g.n_a));
     Partials part{b.blk_max, (int)p.fwd, b.blk_max + g.grid_cap, (int)p.fwd_fix,
                   {b.blk_np, b.blk_np + g.grid_cap, b.blk_np + 2 * g.grid_cap, b.blk_np + 3 * g.grid_cap},
                   {(int)p.back, (int)p.back_fix, (int)p.fwd, (int)p.fwd_fix}};
