@@ -69,7 +69,7 @@ def test_bench_batch_matches_oracle(big):
         pi = pis[q].cpu().numpy().astype(np.float64)
         chk = O.check_query(exact, pi, eps, tol=TOL, k=k, source=s, topk_ids=ti[q])
         assert chk.ok, (q, s, chk.detail)
-        print(f"query {q}: max |err| {chk.max_abs_err:.3e}")
+        _say(f"query {q}: max |err| {chk.max_abs_err:.3e} = {chk.max_abs_err / eps:.3f} eps")
 
 
 @pytest.mark.timeout(900)
