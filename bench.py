@@ -100,11 +100,13 @@ CPU_SAMPLE = 16        # queries of the headline batch timed on the host
 CPU_THREADS_MAX = 16   # the host share of one GPU
 
 
-def cpu_baseline(g, batch_sources, eps):
+def cpu_baseline(g, batch_sources, eps, batch_rows=None):
     """The oracle's FP64 ASRP (lambda from Theorem 3) on the host cores, on a
     sample of the headline batch's own sources (as many of its hub sources as
     of its uniform ones): one query per thread; the value is the sample over
-    the wall time, latency the per-query thread times."""
+    the wall time, latency the per-query thread times.  batch_rows (query
+    index -> the batch's score row): the observed error of those rows
+    against the oracle's exact series, max |pi - pi_hat| / eps."""
     import numpy as np
 
     import oracle
@@ -118,8 +120,15 @@ def cpu_baseline(g, batch_sources, eps):
     _, stats, bad = og.asrp_many(sample, eps, lam, nthreads=nth)
     dtn = time.perf_counter() - t0
     secs = sorted(og.last_secs.tolist())
+    observed = None
+    if batch_rows:
+        observed = {}
+        for q, row in batch_rows.items():
+            exact, _ = og.power_series(int(batch_sources[q]))
+            observed[str(q)] = round(float(np.abs(exact - row).max()) / eps, 4)
     og.close()
     return {"value": round(sample.size / dtn, 3), "unit": "queries/s", "cores": nth, "kind": "oracle",
+            "observed_error_over_eps": observed,
             "latency_ms_p50": round(_percentile(secs, 50) * 1e3, 1),
             "latency_ms_p99": round(_percentile(secs, 99) * 1e3, 1),
             "rounds_mean": round(sum(st.iterations for st in stats) / len(stats), 1), "failed": bad,
@@ -430,7 +439,10 @@ def main():
     # each query's stop rule held, as a share of the batch's rounds, times the
     # batch time (every result is returned when the call returns).
     say("per-query statistics")
-    st_res = ahpp.ahpp_query_batch(dg, sources, eps, k=k, want_pi=False, want_stats=True)
+    st_res = ahpp.ahpp_query_batch(dg, sources, eps, k=k, want_pi=True, want_stats=True)
+    sample_q = sorted({0, args.batch // 2 - 1, args.batch // 2, args.batch - 1})
+    batch_rows = {q: st_res.pi[q].cpu().numpy().astype(np.float64) for q in sample_q}
+    st_res.pi = None
     iters = np.array([st["iters"] for st in st_res.stats], dtype=np.float64)
     batch_ms = float(st_res.stats[0]["ms"])
     done_ms = iters / iters.max() * batch_ms
@@ -515,7 +527,8 @@ def main():
     }
     if not args.no_cpu:
         say("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(g, sources, eps)
+        out["cpu_baseline"] = cpu_baseline(g, sources, eps, batch_rows)
+        out["observed_error_over_eps"] = out["cpu_baseline"]["observed_error_over_eps"]
         if not args.no_amazon:
             out["cpu_baseline"]["amazon_shaped"] = amazon_cpu_leg(synth)
     else:

@@ -61,7 +61,13 @@ typedef enum {
  *   lambda > 0 overrides the Theorem 3 estimate; lambda <= 0 asks the library
  *   to compute Eq. 6 with lambda_iters rounds (<= 0: the smallest T with
  *   n_u (1-alpha)^T <= 0.01) and round it up by a factor 1 + 1e-4.
- *   device: HIP device ordinal that will hold the graph. */
+ *   device: HIP device ordinal that will hold the graph.
+ *   cache_dir: NULL or "" for none; else a directory where the load keeps the
+ *     lambda it computes under the key of the inputs (ahpp_graph_key) and
+ *     where a later load with the same key reads it instead of running the
+ *     Theorem 3 sweeps.  The library reads and writes only files named
+ *     ahpp-<32 hex digits>.lambda there; a missing or unreadable entry, or
+ *     one that fails to store, only means lambda is computed. */
 typedef struct {
     int64_t n_u, n_v, n_attr;
     int64_t n_edges;
@@ -74,6 +80,7 @@ typedef struct {
     double lambda;
     int32_t lambda_iters;
     int32_t device;
+    const char *cache_dir;
 } ahpp_graph_desc_t;
 
 typedef struct {
@@ -84,7 +91,11 @@ typedef struct {
     int32_t device;
     int64_t dangling_u;         /* U nodes with no edge or no attribute        */
     int64_t device_bytes;       /* device memory held by the graph            */
-    double load_ms, lambda_ms;  /* wall time of the build and of Eq. 6         */
+    double load_ms, lambda_ms;  /* wall time of the build and of Eq. 6 (or of reading it from the cache) */
+    uint64_t key[2];            /* ahpp_graph_key of the inputs, computed on the device at load */
+    int32_t lambda_cached;      /* 0 no cache dir, 1 lambda read from the cache, 2 computed and stored,
+                                   -1 computed, storing failed */
+    int32_t reserved;
 } ahpp_graph_info_t;
 
 /* Per-query statistics.  n_push counts edge visits as Algorithm 4 counts n_p
@@ -115,6 +126,17 @@ ahpp_status_t ahpp_graph_load(const ahpp_graph_desc_t *desc, ahpp_graph_t **out)
 
 /* Fills *info (host). */
 ahpp_status_t ahpp_graph_info(const ahpp_graph_t *g, ahpp_graph_info_t *info);
+
+/* The 128-bit key of a graph description (host only, no device needed): a
+ * hash of the sizes, of every element of the six COO arrays with its
+ * position, of whether each weight array is given, of alpha and beta, and
+ * of the Theorem 3 round count the load would use (0 when lambda is given).
+ * Any changed id, weight or parameter changes it; it is what ahpp_graph_load
+ * computes on the device and files lambda under (cache_dir).  Ids and
+ * weights are not validated here.  key: host uint64_t[2].
+ * Errors: INVALID_ARG (NULL argument, sizes, NULL arrays with a count > 0,
+ * alpha, beta or lambda out of range). */
+ahpp_status_t ahpp_graph_key(const ahpp_graph_desc_t *desc, uint64_t *key);
 
 /* Releases the graph and every device buffer it owns.  NULL is ignored. */
 void ahpp_graph_free(ahpp_graph_t *g);

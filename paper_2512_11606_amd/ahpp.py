@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libahpp.so")
 
 OK, ERR_INVALID_ARG, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CONVERGED = 0, -1, -2, -3, -4
 
-EXPORTED = ("ahpp_graph_load", "ahpp_graph_info", "ahpp_graph_free", "ahpp_query", "ahpp_query_noalloc",
+EXPORTED = ("ahpp_graph_load", "ahpp_graph_info", "ahpp_graph_key", "ahpp_graph_free", "ahpp_query", "ahpp_query_noalloc",
             "ahpp_query_schedule",
             "ahpp_query_batch", "ahpp_topk",
             "ahpp_server_create", "ahpp_server_free", "ahpp_server_submit", "ahpp_server_step",
@@ -43,7 +43,7 @@ class GraphDesc(ctypes.Structure):
                 ("edge_w", ctypes.c_void_p), ("n_assoc", ctypes.c_int64), ("assoc_u", ctypes.c_void_p),
                 ("assoc_a", ctypes.c_void_p), ("assoc_w", ctypes.c_void_p), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("lam", ctypes.c_double), ("lambda_iters", ctypes.c_int32),
-                ("device", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("cache_dir", ctypes.c_char_p)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -51,7 +51,8 @@ class GraphInfo(ctypes.Structure):
                 ("n_edges", ctypes.c_int64), ("n_assoc", ctypes.c_int64), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("lam", ctypes.c_double), ("lambda_iters", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("dangling_u", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("load_ms", ctypes.c_double), ("lambda_ms", ctypes.c_double)]
+                ("load_ms", ctypes.c_double), ("lambda_ms", ctypes.c_double), ("key", ctypes.c_uint64 * 2),
+                ("lambda_cached", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -80,6 +81,8 @@ def load_library(path: str = LIB_PATH):
     lib.ahpp_graph_load.argtypes = [ctypes.POINTER(GraphDesc), ctypes.POINTER(ctypes.c_void_p)]
     lib.ahpp_graph_info.restype = ctypes.c_int
     lib.ahpp_graph_info.argtypes = [P, ctypes.POINTER(GraphInfo)]
+    lib.ahpp_graph_key.restype = ctypes.c_int
+    lib.ahpp_graph_key.argtypes = [ctypes.POINTER(GraphDesc), ctypes.POINTER(ctypes.c_uint64)]
     lib.ahpp_graph_free.restype = None
     lib.ahpp_graph_free.argtypes = [P]
     lib.ahpp_query.restype = ctypes.c_int
@@ -190,10 +193,9 @@ class Graph:
             pass
 
 
-def ahpp_graph_load(n_u: int, n_v: int, n_attr: int, edge_u, edge_v, edge_w, assoc_u, assoc_a, assoc_w,
-                    alpha: float = 0.15, beta: float = 0.35, lam: float = 0.0, lambda_iters: int = 0,
-                    device: int = 0) -> Graph:
-    """Loads COO lists (host arrays) onto `device`; see ahpp_graph_load in ahpp.h."""
+def _graph_desc(n_u: int, n_v: int, n_attr: int, edge_u, edge_v, edge_w, assoc_u, assoc_a, assoc_w,
+                alpha: float, beta: float, lam: float, lambda_iters: int, device: int, cache_dir: Optional[str]):
+    """A GraphDesc and the arrays it points at (which must outlive it)."""
     eu, ev = _as_i32(edge_u, "edge_u"), _as_i32(edge_v, "edge_v")
     ew = None if edge_w is None else np.ascontiguousarray(edge_w, dtype=np.float32)
     au, aa = _as_i32(assoc_u, "assoc_u"), _as_i32(assoc_a, "assoc_a")
@@ -202,26 +204,47 @@ def ahpp_graph_load(n_u: int, n_v: int, n_attr: int, edge_u, edge_v, edge_w, ass
         raise ValueError("edge arrays differ in length")
     if au.shape != aa.shape or (aw is not None and aw.shape != au.shape):
         raise ValueError("association arrays differ in length")
-    lib = load_library()
     d = GraphDesc(int(n_u), int(n_v), int(n_attr), int(eu.size), _np_ptr(eu), _np_ptr(ev), _np_ptr(ew),
                   int(au.size), _np_ptr(au), _np_ptr(aa), _np_ptr(aw), float(alpha), float(beta), float(lam),
-                  int(lambda_iters), int(device))
+                  int(lambda_iters), int(device), None if not cache_dir else os.fsencode(cache_dir))
+    return d, (eu, ev, ew, au, aa, aw)
+
+
+def ahpp_graph_load(n_u: int, n_v: int, n_attr: int, edge_u, edge_v, edge_w, assoc_u, assoc_a, assoc_w,
+                    alpha: float = 0.15, beta: float = 0.35, lam: float = 0.0, lambda_iters: int = 0,
+                    device: int = 0, cache_dir: Optional[str] = None) -> Graph:
+    """Loads COO lists (host arrays) onto `device`; see ahpp_graph_load in ahpp.h."""
+    d, keep = _graph_desc(n_u, n_v, n_attr, edge_u, edge_v, edge_w, assoc_u, assoc_a, assoc_w, alpha, beta, lam,
+                          lambda_iters, device, cache_dir)
     h = ctypes.c_void_p()
-    _check(lib.ahpp_graph_load(ctypes.byref(d), ctypes.byref(h)))
+    _check(load_library().ahpp_graph_load(ctypes.byref(d), ctypes.byref(h)))
+    del keep
     return Graph(h, int(device))
 
 
 def load_graph(g, alpha: float = 0.15, beta: float = 0.35, lam: float = 0.0, lambda_iters: int = 0,
-               device: int = 0) -> Graph:
+               device: int = 0, cache_dir: Optional[str] = None) -> Graph:
     """ahpp_graph_load for an object with the fields of synth.AttributedBipartiteGraph."""
     return ahpp_graph_load(g.n_u, g.n_v, g.n_attr, g.edge_u, g.edge_v, g.edge_w, g.assoc_u, g.assoc_a, g.assoc_w,
-                           alpha, beta, lam, lambda_iters, device)
+                           alpha, beta, lam, lambda_iters, device, cache_dir)
+
+
+def ahpp_graph_key(g, alpha: float = 0.15, beta: float = 0.35, lam: float = 0.0, lambda_iters: int = 0) -> tuple:
+    """Host-side key of a graph's inputs (ahpp_graph_key in ahpp.h), as two ints."""
+    d, keep = _graph_desc(g.n_u, g.n_v, g.n_attr, g.edge_u, g.edge_v, g.edge_w, g.assoc_u, g.assoc_a, g.assoc_w,
+                          alpha, beta, lam, lambda_iters, 0, None)
+    key = (ctypes.c_uint64 * 2)()
+    _check(load_library().ahpp_graph_key(ctypes.byref(d), key))
+    del keep
+    return int(key[0]), int(key[1])
 
 
 def ahpp_graph_info(g: Graph) -> dict:
     info = GraphInfo()
     _check(load_library().ahpp_graph_info(g._h, ctypes.byref(info)))
-    return {f: getattr(info, f) for f, _ in info._fields_}
+    out = {f: getattr(info, f) for f, _ in info._fields_ if f != "reserved"}
+    out["key"] = (int(info.key[0]), int(info.key[1]))
+    return out
 
 
 def ahpp_query(g: Graph, source: int, eps: float, k: int = 0, max_iters: int = 0, want_pi: bool = True,

@@ -251,6 +251,8 @@ struct Graph {
     int64_t dangling_u = 0;
     int64_t device_bytes = 0;
     double load_ms = 0, lambda_ms = 0;
+    uint64_t key[2] = {0, 0};       // key of the inputs (prep_cache.hip)
+    int32_t lambda_cached = 0;      // 0 no cache, 1 read from the cache, 2 computed and stored, -1 store failed
     // Single-query state (allocated at load).
     QueryBufs q;
     // Batched engine (allocated on first use, grown on demand).
@@ -309,9 +311,26 @@ McResult mc_walks(Graph &g, int32_t source, int64_t n_walks, uint64_t seed, int 
 // Walk counts (device numbering) to scores in input order.
 void mc_scores(const unsigned *count, const int32_t *u_new, int64_t n, int64_t n_walks, float *out, hipStream_t s);
 
-// graph_build.hip
+// prep_cache.hip: the 128-bit key of a graph's inputs (sizes, the six COO
+// arrays, alpha, beta, the Theorem 3 round count; the same value on the
+// device, over the uploaded arrays, and on the host), and the cache of
+// lambda (Eq. 6) under that key in a directory.
+struct KeyInput {
+    int64_t n_u, n_v, n_attr, n_edges, n_assoc;
+    bool has_ew, has_aw;
+    double alpha, beta;
+    int32_t lambda_iters;
+};
+void coo_key_device(const KeyInput &in, const int32_t *eu, const int32_t *ev, const float *ew, const int32_t *au,
+                    const int32_t *aa, const float *aw, uint64_t key[2], hipStream_t s);
+void coo_key_host(const KeyInput &in, const int32_t *eu, const int32_t *ev, const float *ew, const int32_t *au,
+                  const int32_t *aa, const float *aw, uint64_t key[2]);
+bool lambda_cache_read(const std::string &dir, const KeyInput &in, const uint64_t key[2], double *lambda);
+bool lambda_cache_write(const std::string &dir, const KeyInput &in, const uint64_t key[2], double lambda);
+
+// graph_build.hip (also computes g.key on the device from the uploaded COO)
 void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew, const int32_t *au,
-                 const int32_t *aa, const float *aw, hipStream_t s);
+                 const int32_t *aa, const float *aw, const KeyInput &kin, hipStream_t s);
 void free_graph(Graph &g);
 
 // push.hip

@@ -123,6 +123,39 @@ int default_lambda_iters(int64_t n_u, double alpha) {
     return std::max(1, (int)t);
 }
 
+// What the key of a description covers; the round count is the one the load
+// uses for Theorem 3 (0 when lambda is given).
+KeyInput key_input(const ahpp_graph_desc_t &d) {
+    KeyInput k;
+    k.n_u = d.n_u;
+    k.n_v = d.n_v;
+    k.n_attr = d.n_attr;
+    k.n_edges = d.n_edges;
+    k.n_assoc = d.n_assoc;
+    k.has_ew = d.edge_w != nullptr && d.n_edges > 0;
+    k.has_aw = d.assoc_w != nullptr && d.n_assoc > 0;
+    k.alpha = d.alpha;
+    k.beta = d.beta;
+    k.lambda_iters = d.lambda > 0 ? 0 : (d.lambda_iters > 0 ? d.lambda_iters : default_lambda_iters(d.n_u, d.alpha));
+    return k;
+}
+
+// The checks of a description that need no device (sizes, pointers, alpha,
+// beta, lambda); ids and weights are checked on the device at load.
+std::string desc_error(const ahpp_graph_desc_t *d) {
+    if (d->n_u <= 0 || d->n_v < 0 || d->n_attr < 0 || d->n_edges < 0 || d->n_assoc < 0)
+        return "sizes must be >= 0 and n_u >= 1";
+    if (d->n_u > INT32_MAX || d->n_v > INT32_MAX || d->n_attr > INT32_MAX || 2 * d->n_u > INT32_MAX ||
+        d->n_v + d->n_attr > INT32_MAX)
+        return "node counts exceed the int32 id range";
+    if ((d->n_edges > 0 && (!d->edge_u || !d->edge_v)) || (d->n_assoc > 0 && (!d->assoc_u || !d->assoc_a)))
+        return "id arrays must not be NULL when their count is > 0";
+    if (!(d->alpha > 0.0 && d->alpha < 1.0)) return "alpha must be in (0,1)";
+    if (!(d->beta >= 0.0 && d->beta <= 1.0)) return "beta must be in [0,1]";
+    if (std::isnan(d->lambda) || std::isinf(d->lambda)) return "lambda must be finite";
+    return "";
+}
+
 // Runs rounds until the control block reports done; the host checks after
 // chunks of rounds that grow from 4 to 32.
 // Rounds still needed, estimated from the max residue: the synchronous phase
@@ -417,17 +450,8 @@ ahpp_status_t ahpp_graph_load(const ahpp_graph_desc_t *d, ahpp_graph_t **out) {
     g_last_error.clear();
     if (!d || !out) return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: desc and out must not be NULL");
     *out = nullptr;
-    if (d->n_u <= 0 || d->n_v < 0 || d->n_attr < 0 || d->n_edges < 0 || d->n_assoc < 0)
-        return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: sizes must be >= 0 and n_u >= 1");
-    if (d->n_u > INT32_MAX || d->n_v > INT32_MAX || d->n_attr > INT32_MAX || 2 * d->n_u > INT32_MAX ||
-        d->n_v + d->n_attr > INT32_MAX)
-        return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: node counts exceed the int32 id range");
-    if ((d->n_edges > 0 && (!d->edge_u || !d->edge_v)) || (d->n_assoc > 0 && (!d->assoc_u || !d->assoc_a)))
-        return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: id arrays must not be NULL when their count is > 0");
-    if (!(d->alpha > 0.0 && d->alpha < 1.0)) return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: alpha must be in (0,1)");
-    if (!(d->beta >= 0.0 && d->beta <= 1.0)) return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: beta must be in [0,1]");
-    if (std::isnan(d->lambda) || std::isinf(d->lambda))
-        return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: lambda must be finite");
+    const std::string bad = desc_error(d);
+    if (!bad.empty()) return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_load: " + bad);
     int n_dev = 0;
     if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev <= 0)
         return fail(AHPP_ERR_DEVICE, "ahpp_graph_load: no HIP device");
@@ -452,7 +476,8 @@ ahpp_status_t ahpp_graph_load(const ahpp_graph_desc_t *d, ahpp_graph_t **out) {
         g.n_cu = n_cu > 0 ? n_cu : 1;
         g.grid_cap = g.n_cu * kBlocksPerCu;
         noalloc_setup(g.device);
-        build_graph(g, d->edge_u, d->edge_v, d->edge_w, d->assoc_u, d->assoc_a, d->assoc_w, s);
+        const KeyInput kin = key_input(*d);
+        build_graph(g, d->edge_u, d->edge_v, d->edge_w, d->assoc_u, d->assoc_a, d->assoc_w, kin, s);
         alloc_query_state(g);
         ensure_topk_scratch(g, 1);
         if (d->lambda > 0) {
@@ -460,8 +485,14 @@ ahpp_status_t ahpp_graph_load(const ahpp_graph_desc_t *d, ahpp_graph_t **out) {
             g.lambda_iters = 0;
         } else {
             auto t0 = std::chrono::steady_clock::now();
-            g.lambda_iters = d->lambda_iters > 0 ? d->lambda_iters : default_lambda_iters(g.n_u, g.alpha);
-            g.lambda = compute_lambda(g, g.lambda_iters, s) * (1.0 + 1e-4);
+            g.lambda_iters = kin.lambda_iters;
+            const std::string dir = d->cache_dir ? d->cache_dir : "";
+            if (!dir.empty() && lambda_cache_read(dir, kin, g.key, &g.lambda)) {
+                g.lambda_cached = 1;
+            } else {
+                g.lambda = compute_lambda(g, g.lambda_iters, s) * (1.0 + 1e-4);
+                if (!dir.empty()) g.lambda_cached = lambda_cache_write(dir, kin, g.key, g.lambda) ? 2 : -1;
+            }
             g.lambda_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         }
         check_hip(hipStreamSynchronize(s), "load");
@@ -503,7 +534,24 @@ ahpp_status_t ahpp_graph_info(const ahpp_graph_t *h, ahpp_graph_info_t *info) {
     info->device_bytes = g.device_bytes;
     info->load_ms = g.load_ms;
     info->lambda_ms = g.lambda_ms;
+    info->key[0] = g.key[0];
+    info->key[1] = g.key[1];
+    info->lambda_cached = g.lambda_cached;
+    info->reserved = 0;
     return AHPP_OK;
+}
+
+ahpp_status_t ahpp_graph_key(const ahpp_graph_desc_t *d, uint64_t *key) {
+    g_last_error.clear();
+    if (!d || !key) return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_key: desc and key must not be NULL");
+    const std::string bad = desc_error(d);
+    if (!bad.empty()) return fail(AHPP_ERR_INVALID_ARG, "ahpp_graph_key: " + bad);
+    return guarded("ahpp_graph_key", [&] {
+        const KeyInput kin = key_input(*d);
+        coo_key_host(kin, d->edge_u, d->edge_v, kin.has_ew ? d->edge_w : nullptr, d->assoc_u, d->assoc_a,
+                     kin.has_aw ? d->assoc_w : nullptr, key);
+        return AHPP_OK;
+    });
 }
 
 void ahpp_graph_free(ahpp_graph_t *h) {

@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -670,9 +671,29 @@ void build_hot(Graph &g, hipStream_t s) {
 
 }  // namespace
 
+namespace {
+// With AHPP_LOAD_TRACE=1 the load prints the time of each phase to stderr
+// (the stream is synchronized at each mark).
+struct LoadTrace {
+    bool on;
+    std::chrono::steady_clock::time_point t;
+    LoadTrace() : on(std::getenv("AHPP_LOAD_TRACE") && std::atoi(std::getenv("AHPP_LOAD_TRACE")) == 1),
+                  t(std::chrono::steady_clock::now()) {}
+    void mark(const char *what, hipStream_t s) {
+        if (!on) return;
+        (void)hipStreamSynchronize(s);
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[ahpp load] %-28s %9.1f ms\n", what,
+                     std::chrono::duration<double, std::milli>(now - t).count());
+        t = now;
+    }
+};
+}  // namespace
+
 void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew, const int32_t *au,
-                 const int32_t *aa, const float *aw, hipStream_t s) {
+                 const int32_t *aa, const float *aw, const KeyInput &kin, hipStream_t s) {
     auto t0 = std::chrono::steady_clock::now();
+    LoadTrace trace;
     const int64_t m_e = g.m_e, m_a = g.m_a, m = m_e + m_a;
     {  // The COO upload and the entry scratch end with the block.
         // Upload COO (a missing weight array means every weight is 1).
@@ -713,6 +734,9 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
             throw Failure{-1, msg};
         }
         g.unit = !(flags & 16u);
+        trace.mark("upload + validation", s);
+        coo_key_device(kin, d_eu, d_ev, d_ew, d_au, d_aa, d_aw, g.key, s);
+        trace.mark("input key", s);
 
         // Device numbering of U, V and the attributes: by descending number of
         // CSR entries that name the node, ties by input id.  The random gathers
@@ -743,6 +767,7 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
                   "numbering");
         check_hip(hipStreamSynchronize(s), "numbering");
         g.n_v = v_rows;
+        trace.mark("numbering", s);
 
         // Entries of both CSRs.
         DevTemp<uint32_t> key_((size_t)m, "entries");
@@ -759,6 +784,7 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
             hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_au, d_aa, d_aw, m_a,
                                (int32_t)g.n_v, 0u, key + m_e, col + m_e, w + m_e);
         build_csr(g, g.fwd, g.n_u, key, col, w, m, !g.unit, s, g.n_v + g.n_a);
+        trace.mark("U rows (sort + schedule)", s);
         // back: rows V then attributes (row n_v + a); columns are U ids.
         if (m_e > 0)
             hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_e)), dim3(kBlock), 0, s, d_ev, d_eu, d_ew, m_e, 0, 0u,
@@ -767,6 +793,7 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
             hipLaunchKernelGGL(k_make_entries, dim3(grid_for(m_a)), dim3(kBlock), 0, s, d_aa, d_au, d_aw, m_a, 0,
                                (uint32_t)g.n_v, key + m_e, col + m_e, w + m_e);
         build_csr(g, g.back, g.n_v + g.n_a, key, col, w, m, true, s, g.n_u);
+        trace.mark("V/attribute rows", s);
     }
 
     // Coefficients: 1/d(u), 1/s(u) in double, then inv_b and the back weights
@@ -788,7 +815,9 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
     check_hip(hipMemcpyAsync(&dang, d_dang, 8, hipMemcpyDeviceToHost, s), "dangling D2H");
     check_hip(hipStreamSynchronize(s), "coefficients");
     g.dangling_u = (int64_t)dang;
+    trace.mark("coefficients", s);
     build_hot(g, s);
+    trace.mark("hot rows", s);
     g.load_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
