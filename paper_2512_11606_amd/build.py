@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libahpp.so")
-SOURCES = ["graph_build.hip", "push.hip", "batch.hip", "serve.hip", "topk.hip", "mc.hip", "noalloc.hip", "prep_cache.hip", "capi.hip"]
+SOURCES = ["graph_build.hip", "push.hip", "batch.hip", "serve.hip", "topk.hip", "mc.hip", "noalloc.hip", "prep_cache.hip", "hot_dense.hip", "capi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 CXXFLAGS = [

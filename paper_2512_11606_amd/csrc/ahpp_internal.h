@@ -177,7 +177,14 @@ struct HotSet {
     SplitRow *cold_split = nullptr;
     int64_t n_cold_split = 0;
     int64_t cold_nnz = 0, cold_rows = 0;
+    // The same rows as a dense block for the matrix cores (hot_dense.hip):
+    // w'(u, x_h) split into three bf16 parts in MFMA operand order, U cut
+    // into dense_chunks chunks of dense_kc rows (nullptr: the streaming pass).
+    uint16_t *w3 = nullptr;
+    int64_t dense_kc = 0, dense_ks = 0;
+    int32_t dense_chunks = 0;
 };
+constexpr int kDenseChunks = 512;        // U chunks of the dense hot pass
 
 // Weighted-draw tables of the Monte Carlo walks (built on first use).
 struct McTables {
@@ -327,6 +334,14 @@ void coo_key_host(const KeyInput &in, const int32_t *eu, const int32_t *ev, cons
                   const int32_t *aa, const float *aw, uint64_t key[2]);
 bool lambda_cache_read(const std::string &dir, const KeyInput &in, const uint64_t key[2], double *lambda);
 bool lambda_cache_write(const std::string &dir, const KeyInput &in, const uint64_t key[2], double lambda);
+
+// hot_dense.hip: the hot rows as a dense MFMA product (on unless
+// AHPP_HOT_DENSE=0); build at load, launch per batched round (partials
+// [dense_chunks][n_hot][kTileQ] per tile, added by the hot reduction).
+bool hot_dense_enabled();
+void build_hot_dense(Graph &g, hipStream_t s);
+void launch_hot_dense(const Graph &g, const uint16_t *q, int64_t q_stride, const TileCtl *ctl, int nt, float *part,
+                      int64_t part_stride, hipStream_t s);
 
 // graph_build.hip (also computes g.key on the device from the uploaded COO)
 void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew, const int32_t *au,

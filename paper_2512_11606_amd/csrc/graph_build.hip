@@ -817,6 +817,7 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
     g.dangling_u = (int64_t)dang;
     trace.mark("coefficients", s);
     build_hot(g, s);
+    if (hot_dense_enabled()) build_hot_dense(g, s);
     trace.mark("hot rows", s);
     g.load_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -836,7 +837,7 @@ void free_graph(Graph &g) {
     free_csr(g.hot.list);
     free_mc_tables(g.mc);
     for (void *p : {(void *)g.hot.rows, (void *)g.hot.len, (void *)g.hot.cold_items, (void *)g.hot.cold_split,
-                    (void *)g.hot.chunk_start, (void *)g.hot.blk_base})
+                    (void *)g.hot.chunk_start, (void *)g.hot.blk_base, (void *)g.hot.w3})
         dfree(p);
     g.hot = HotSet{};
     free_batch_state(g.batch);
