@@ -148,43 +148,29 @@ struct BatchState {
 };
 
 // Hot rows: the longest rows of the back CSR (the most popular attributes
-// and V nodes).  The batched engine does not gather them entry by entry: it
-// streams each tile's U rows once, in fixed chunks of blocks of
-// kHotBlockRows rows, and adds every hot row's terms in registers (wave g
-// owns the hot rows h with h % kHotWaves == g, one lane per four query
-// columns, so each accumulator has one writer and the sum order is fixed),
-// then adds the chunk partials in chunk order.  The load places the rows on
-// hot indices so that the waves' entry totals are level.
-constexpr int kHotMax = 128;             // at most this many hot rows
-constexpr int kHotWaves = 16;            // waves of the streaming pass; wave g owns h % 16 == g
-constexpr int kHotPerWave = kHotMax / kHotWaves;  // hot rows (register accumulators) per wave
+// and V nodes, a few percent to tens of percent dense over U).  The batched
+// engine does not gather them entry by entry: it sums them as a dense
+// product on the matrix cores (hot_dense.hip) over fixed chunks of U, then
+// adds the chunk partials in chunk order, so each sum has a fixed order and
+// results do not depend on the tiles in flight.
+constexpr int kHotMax = 128;             // at most this many hot rows (four 32-row MFMA blocks)
 constexpr int64_t kHotMinLen = 1024;     // a hot row has at least one full item of entries
-constexpr int kHotBlockRows = 32;        // U rows per staged block of the streaming pass
+constexpr int kDenseChunks = 512;        // U chunks of the dense hot pass
 struct HotSet {
     int32_t n = 0;                       // hot rows (0: none, the batch gathers every row)
-    int32_t *rows = nullptr;             // [n] back row of hot index h
+    int32_t *rows = nullptr;             // [n] back row of hot index h (longest first)
     int32_t *len = nullptr;              // [n] entries of that row
-    // The hot entries as segments: segment ((g * n_blocks + B) * kHotPerWave
-    // + h / kHotWaves) holds, for block B and the hot row h (h % kHotWaves ==
-    // g), the entries (row of u within the block, back weight), by u.
-    DevCsr list;
-    int32_t n_chunks = 0;                // fixed U chunks of the streaming pass:
-    int64_t *chunk_start = nullptr;      //   chunk c = rows [start[c], start[c+1]) (device)
-    int64_t *blk_base = nullptr;         //   its blocks B = blk_base[c] ... (device, n_chunks + 1)
-    int64_t n_blocks = 0;
     WorkItem *cold_items = nullptr;      // back schedule without the hot rows
     int64_t n_cold_items = 0;
     SplitRow *cold_split = nullptr;
     int64_t n_cold_split = 0;
     int64_t cold_nnz = 0, cold_rows = 0;
-    // The same rows as a dense block for the matrix cores (hot_dense.hip):
-    // w'(u, x_h) split into three bf16 parts in MFMA operand order, U cut
-    // into dense_chunks chunks of dense_kc rows (nullptr: the streaming pass).
+    // w'(u, x_h) split into three bf16 parts in MFMA operand order; U cut
+    // into dense_chunks chunks of dense_kc rows (dense_ks K-steps of 16 rows).
     uint16_t *w3 = nullptr;
     int64_t dense_kc = 0, dense_ks = 0;
     int32_t dense_chunks = 0;
 };
-constexpr int kDenseChunks = 512;        // U chunks of the dense hot pass
 
 // Weighted-draw tables of the Monte Carlo walks (built on first use).
 struct McTables {
@@ -335,10 +321,10 @@ void coo_key_host(const KeyInput &in, const int32_t *eu, const int32_t *ev, cons
 bool lambda_cache_read(const std::string &dir, const KeyInput &in, const uint64_t key[2], double *lambda);
 bool lambda_cache_write(const std::string &dir, const KeyInput &in, const uint64_t key[2], double lambda);
 
-// hot_dense.hip: the hot rows as a dense MFMA product (on unless
-// AHPP_HOT_DENSE=0); build at load, launch per batched round (partials
+// hot_dense.hip: the hot rows as a dense MFMA product; its weights' bytes,
+// their build at load, and the launch of a batched round (partials
 // [dense_chunks][n_hot][kTileQ] per tile, added by the hot reduction).
-bool hot_dense_enabled();
+size_t hot_dense_bytes(const Graph &g);
 void build_hot_dense(Graph &g, hipStream_t s);
 void launch_hot_dense(const Graph &g, const uint16_t *q, int64_t q_stride, const TileCtl *ctl, int nt, float *part,
                       int64_t part_stride, hipStream_t s);

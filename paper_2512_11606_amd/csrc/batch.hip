@@ -162,12 +162,6 @@ __device__ __forceinline__ float readlane_f(float v, int k) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
 }
 
-__device__ __forceinline__ int64_t readlane_i64(int64_t v, int k) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, k);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), k);
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
 __device__ __forceinline__ int64_t lane_col() { return (int64_t)(threadIdx.x & 63) * kVec; }
 
 // Per-lane epilogues over the lane's kVec queries.
@@ -565,183 +559,6 @@ __global__ void __launch_bounds__(kTileQ) kb_control(TileCtl *ctl, const float *
 
 // ---------------------------------------------------------------- hot rows
 
-struct HotArgs {
-    const uint16_t *q;      // bf16 transport residues Q (tile 0)
-    int64_t r_stride;
-    float *part;            // chunk partials (tile 0), [n_chunks][n_hot][kTileQ]
-    int64_t part_stride;
-    const TileCtl *ctl;
-    const int64_t *chunk_start;  // chunk c = U rows [chunk_start[c], chunk_start[c + 1])
-    const int64_t *blk_base;     // first block of chunk c
-    int64_t n_blocks;
-    int n_hot, n_chunks;
-};
-
-constexpr int kHotThreads = kHotWaves * kWave;  // one workgroup per (chunk, tile)
-constexpr int kHotStage = kHotBlockRows * kTileQ / 4 / kHotThreads;  // float4 per thread per block
-constexpr int kHotWindow = 2 * kWave;            // hot-list entries per wave held in registers
-static_assert(kHotPerWave == 8, "a wave's block holds one segment per register row, 8 of them");
-static_assert(kHotPerWave < kWave, "a block's segment offsets sit one per lane");
-
-// What a wave needs for one block of U rows, loaded one block ahead with
-// vector loads (coalesced, many in flight) and read back with readlane.
-struct HotBlock {
-    uint2 x[kHotStage];    // the thread's share of the block's transport residues (4 x bf16 each)
-    int64_t off;           // lane s <= kHotPerWave: start of the wave's segment s (s = kHotPerWave: the end)
-    int32_t p0, p1;        // entries e_b + lane and e_b + 64 + lane: row within the block
-    float w0, w1;          //   and back weight
-};
-
-// One workgroup of kHotWaves waves per (chunk, tile).  The chunk's U rows are
-// streamed from HBM once, in blocks of kHotBlockRows rows: each block is
-// loaded one block ahead into registers, thresholded into LDS, and read from
-// there by every wave (one barrier per block).  Wave g owns the hot rows
-// h = g + 16 s (s = 0..7) and keeps their sums for its lane's query columns
-// 4l .. 4l+3 in registers.  Its entries of a block come as 8 segments, one
-// per register row s, each listing (row within the block, w') by row, so the
-// per-entry work is one 16-byte LDS read and four FMAs into a register row
-// known at compile time; rows with no entry cost nothing.  Each accumulator
-// has one owner and its adds are ordered by block and row, so the result is
-// deterministic.
-__global__ void __launch_bounds__(kHotThreads) kb_hot(HotArgs a, const int64_t *__restrict__ hot_off,
-                                                      const int32_t *__restrict__ hot_col,
-                                                      const float *__restrict__ hot_w) {
-    __shared__ float4 xs[2][kHotBlockRows * kTileQ / 4];
-    const int t = blockIdx.y;
-    const TileCtl &tc = a.ctl[t];
-    if (tc.all_done) return;
-    const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
-    const int grp = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
-    // Staging role: float4 i of the block is row i / 64, columns 4 (i % 64) .. + 3.
-    const int scol = (tid % (kTileQ / 4)) * 4;
-    float sth[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) sth[k] = tc.q[scol + k].theta;
-    const uint16_t *rt = a.q + t * a.r_stride;
-    float *pt = a.part + t * a.part_stride;
-    const int c = blockIdx.x;
-    const int64_t u0 = a.chunk_start[c], u1 = a.chunk_start[c + 1];
-    const int64_t nb = (u1 - u0 + kHotBlockRows - 1) / kHotBlockRows;
-    // Segment offsets of this wave: block b of the chunk starts at seg(b).
-    const int64_t *seg = hot_off + ((int64_t)grp * a.n_blocks + a.blk_base[c]) * kHotPerWave;
-    float4 acc[kHotPerWave];
-#pragma unroll
-    for (int k = 0; k < kHotPerWave; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    const int64_t e_end = seg[nb * kHotPerWave];  // end of this wave's entries in the chunk
-    // Loads of block b; e_b is the offset of its first entry (known from the
-    // previous block, or read directly for the first block).
-    auto load_block = [&](HotBlock &blk, int64_t b, int64_t e_b) {
-        const int64_t ub = u0 + b * kHotBlockRows;
-#pragma unroll
-        for (int i = 0; i < kHotStage; ++i) {
-            const int64_t u = ub + (tid + i * kHotThreads) / (kTileQ / 4);
-            if (u < u1) {
-                const nt_u2 t = __builtin_nontemporal_load(reinterpret_cast<const nt_u2 *>(rt + u * kTileQ + scol));
-                blk.x[i] = make_uint2(t.x, t.y);
-            } else {
-                blk.x[i] = make_uint2(0u, 0u);
-            }
-        }
-        blk.off = (lane <= kHotPerWave && b < nb) ? seg[b * kHotPerWave + lane] : 0;
-        blk.p0 = e_b + lane < e_end ? hot_col[e_b + lane] : 0;
-        blk.w0 = e_b + lane < e_end ? hot_w[e_b + lane] : 0.0f;
-        blk.p1 = e_b + kWave + lane < e_end ? hot_col[e_b + kWave + lane] : 0;
-        blk.w1 = e_b + kWave + lane < e_end ? hot_w[e_b + kWave + lane] : 0.0f;
-    };
-    auto stage = [&](int buf, const HotBlock &blk) {
-#pragma unroll
-        for (int i = 0; i < kHotStage; ++i) {
-            float4 v = make_float4(__uint_as_float(blk.x[i].x << 16), __uint_as_float(blk.x[i].x & 0xFFFF0000u),
-                                   __uint_as_float(blk.x[i].y << 16), __uint_as_float(blk.x[i].y & 0xFFFF0000u));
-            v.x = sth[0] != FLT_MAX ? v.x : 0.0f;
-            v.y = sth[1] != FLT_MAX ? v.y : 0.0f;
-            v.z = sth[2] != FLT_MAX ? v.z : 0.0f;
-            v.w = sth[3] != FLT_MAX ? v.w : 0.0f;
-            xs[buf][tid + i * kHotThreads] = v;
-        }
-    };
-    if (nb > 0) {
-        HotBlock cur;
-        load_block(cur, 0, seg[0]);
-        stage(0, cur);
-        __syncthreads();
-        int buf = 0;
-        for (int64_t b = 0; b < nb; ++b) {
-            const int64_t e_b = readlane_i64(cur.off, 0);
-            HotBlock nxt;
-            load_block(nxt, b + 1, readlane_i64(cur.off, kHotPerWave));
-            const float4 *xb = xs[buf];
-            auto add = [&](float4 &s, float w, const float4 &x) {
-                s.x += w * x.x;
-                s.y += w * x.y;
-                s.z += w * x.z;
-                s.w += w * x.w;
-            };
-            // Entries ka .. kb-1 of the block into s, in order, two at a time
-            // (both LDS reads in flight before the adds; groups of four
-            // measured no faster, most segments being short).  get(k, p, w)
-            // yields entry k: (row within the block, w').
-            auto run = [&](float4 &s, int ka, int kb, auto get) {
-                int k = ka;
-                for (; k + 1 < kb; k += 2) {
-                    int pa, pb;
-                    float wa, wb;
-                    get(k, pa, wa);
-                    get(k + 1, pb, wb);
-                    const float4 xa = xb[pa * (kTileQ / 4) + lane];
-                    const float4 xc = xb[pb * (kTileQ / 4) + lane];
-                    add(s, wa, xa);
-                    add(s, wb, xc);
-                }
-                if (k < kb) {
-                    int p;
-                    float w;
-                    get(k, p, w);
-                    add(s, w, xb[p * (kTileQ / 4) + lane]);
-                }
-            };
-            // Segment bounds relative to the block's first entry: lane s of
-            // rel is where segment s starts (lanes 0 .. kHotPerWave used).
-            const int rel = (int)(cur.off - e_b);
-            int k1 = 0;
-#pragma unroll
-            for (int sg = 0; sg < kHotPerWave; ++sg) {
-                const int k0 = k1;
-                k1 = __builtin_amdgcn_readlane(rel, sg + 1);
-                // The segment's entries come from three places, taken as
-                // three ranges so the loops carry no per-entry branch: the
-                // first kWave entries of the block from lanes of p0/w0, the
-                // next kWave from p1/w1, any further ones from memory.
-                run(acc[sg], k0, min(k1, kWave), [&](int k, int &p, float &w) {
-                    p = __builtin_amdgcn_readlane(cur.p0, k);
-                    w = readlane_f(cur.w0, k);
-                });
-                if (k1 > kWave) {
-                    run(acc[sg], max(k0, kWave), min(k1, kHotWindow), [&](int k, int &p, float &w) {
-                        p = __builtin_amdgcn_readlane(cur.p1, k - kWave);
-                        w = readlane_f(cur.w1, k - kWave);
-                    });
-                    run(acc[sg], max(k0, kHotWindow), k1, [&](int k, int &p, float &w) {
-                        p = hot_col[e_b + k];
-                        w = hot_w[e_b + k];
-                    });
-                }
-            }
-            stage(buf ^ 1, nxt);
-            buf ^= 1;
-            cur = nxt;
-            __syncthreads();
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < kHotPerWave; ++k) {
-        const int h = grp + k * kHotWaves;
-        if (h < a.n_hot)
-            *reinterpret_cast<float4 *>(pt + ((int64_t)c * a.n_hot + h) * kTileQ + lane * 4) = acc[k];
-    }
-}
-
 struct HotReduceArgs {
     const float *part;      // tile 0 partials
     int64_t part_stride;
@@ -1044,9 +861,8 @@ void free_batch_state(BatchState &b) {
     b = BatchState{};
 }
 
-// Chunks of the hot-row partials: the dense pass's U chunks, else the
-// streaming pass's.
-int64_t hot_chunks(const Graph &g) { return g.hot.w3 ? g.hot.dense_chunks : g.hot.n_chunks; }
+// Chunks of the hot-row partials (the dense pass's U chunks).
+int64_t hot_chunks(const Graph &g) { return g.hot.dense_chunks; }
 
 int64_t batch_tile_bytes(const Graph &g, bool with_out) {
     const int64_t items = std::max<int64_t>(std::max(g.fwd.n_items, g.back.n_items), 1);
@@ -1142,10 +958,8 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
     const double back_comp = back_csr + q * (2.0 * g.n_u + back_row);
     const double fwd_bytes = fwd_csr + q * (2.0 * g.fwd.nnz + fwd_row);
     const double fwd_comp = fwd_csr + q * (2.0 * n_x + fwd_row);
-    const double hot_bytes =
-        hs.w3 ? 6.0 * hs.dense_ks * 16.0 * 128.0 + 12.0 * hs.n + q * (2.0 * g.n_u + 8.0 * hs.dense_chunks * hs.n + 10.0 * hs.n)
-              : 8.0 * hs.list.nnz + 8.0 * (hs.list.n_rows + 1) + 12.0 * hs.n +
-                    q * (2.0 * g.n_u + 8.0 * hs.n_chunks * hs.n + 10.0 * hs.n);
+    const double hot_bytes = 6.0 * (double)hs.dense_ks * 16.0 * kHotMax + 12.0 * hs.n +
+                             q * (2.0 * g.n_u + 8.0 * hs.dense_chunks * hs.n + 10.0 * hs.n);
     if (p.back)
         profiled(g.prof, 2, back_bytes, back_comp, s, [&] {
             hipLaunchKernelGGL((kb_gather<false, kBBack>), dim3(p.back, nt), dim3(kBlock), 0, s, back);
@@ -1161,15 +975,7 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
         HotReduceArgs ra{b.hot_part, tile_hot, hs.rows, hs.len, g.inv_b, b.c, b.zh, tile_x, b.blk_np + 4 * slot, su,
                          b.ctl, hs.n, n_ch};
         profiled(g.prof, 4, hot_bytes, hot_bytes, s, [&] {
-            if (hs.w3) {
-                launch_hot_dense(g, b.q, tile_u, b.ctl, nt, b.hot_part, tile_hot, s);
-            } else {
-                HotArgs ha{b.q,         tile_u,      b.hot_part, tile_hot, b.ctl, hs.chunk_start,
-                           hs.blk_base, hs.n_blocks, hs.n,       hs.n_chunks};
-                hipLaunchKernelGGL(kb_hot, dim3((unsigned)hs.n_chunks, nt), dim3(kHotThreads), 0, s, ha,
-                                   (const int64_t *)hs.list.off, (const int32_t *)hs.list.col,
-                                   (const float *)hs.list.w);
-            }
+            launch_hot_dense(g, b.q, tile_u, b.ctl, nt, b.hot_part, tile_hot, s);
             hipLaunchKernelGGL(kb_hot_reduce, dim3((unsigned)hs.n, nt), dim3(kBlock), 0, s, ra);
         });
     }

@@ -299,53 +299,6 @@ __global__ void k_back_coeffs(const int64_t *off, const int32_t *col, float *w, 
     }
 }
 
-// Entries of the hot rows, keyed by (group of h, U column): entry i of hot
-// row h (start[h] <= i < start[h + 1]) becomes (key (h % kHotWaves) * n_u + u,
-// col h, w back weight).
-// Hot entry i (the hot rows' entries, concatenated in hot order; start[h]
-// = first entry of hot row h): its hot index and back CSR position.
-__device__ __forceinline__ int hot_of_entry(const int64_t *start, int n_hot, int64_t i) {
-    int lo = 0, hi = n_hot - 1;  // last h with start[h] <= i
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (start[mid] <= i) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// cnt[u] = hot entries naming U row u (at most kHotMax per row).
-__global__ void k_hot_count(const int64_t *off, const int32_t *col, const int32_t *rows, const int64_t *start,
-                            int n_hot, int64_t m, unsigned *cnt) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-        const int h = hot_of_entry(start, n_hot, i);
-        atomicAdd(&cnt[col[off[rows[h]] + (i - start[h])]], 1u);
-    }
-}
-
-// Segment key, row within the block and weight of every hot entry: U row u
-// lies in chunk c (chunk_start[c] <= u < chunk_start[c + 1]), block B =
-// blk_base[c] + (u - chunk_start[c]) / kHotBlockRows.
-__global__ void k_hot_entries(const int64_t *off, const int32_t *col, const float *w, const int32_t *rows,
-                              const int64_t *start, int n_hot, int64_t m, const int64_t *chunk_start,
-                              const int64_t *blk_base, int n_chunks, int64_t n_blocks, uint32_t *key, int32_t *hcol,
-                              float *hw) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-        const int h = hot_of_entry(start, n_hot, i);
-        const int64_t p = off[rows[h]] + (i - start[h]);
-        const int64_t u = col[p];
-        int lo = 0, hi = n_chunks - 1;  // last c with chunk_start[c] <= u
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (chunk_start[mid] <= u) lo = mid; else hi = mid - 1;
-        }
-        const int64_t rel = u - chunk_start[lo];
-        const int64_t blk = blk_base[lo] + rel / kHotBlockRows;
-        key[i] = (uint32_t)(((int64_t)(h % kHotWaves) * n_blocks + blk) * kHotPerWave + h / kHotWaves);
-        hcol[i] = (int32_t)(rel % kHotBlockRows);
-        hw[i] = w[p];
-    }
-}
-
 unsigned grid_for(int64_t n, int per_block = kBlock, unsigned cap = 65536u) {
     int64_t g = (n + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -511,43 +464,22 @@ int64_t number_by_count(Graph &g, int64_t n, std::initializer_list<std::pair<con
     return (int64_t)n_nz;
 }
 
-// Streaming-pass cost of U row u (a row of the device numbering): its hot
-// entries plus kHotWaves for its staging; cost[n_u] = 0.
-__global__ void k_hot_cost(const unsigned *cnt, int64_t n_u, unsigned long long *cost) {
-    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u <= n_u; u += (int64_t)gridDim.x * blockDim.x)
-        cost[u] = u < n_u ? (unsigned long long)cnt[u] + kHotWaves : 0ull;
-}
-
-// start[c] = the first row whose exclusive cost prefix reaches c / n_chunks
-// of the total (start[0] = 0, start[n_chunks] = n_u; non-decreasing).
-__global__ void k_chunk_bounds(const unsigned long long *prefix, int64_t n_u, int n_chunks, int64_t *start) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c > n_chunks) return;
-    if (c == n_chunks) {
-        start[c] = n_u;
-        return;
-    }
-    const unsigned long long target = prefix[n_u] / (unsigned long long)n_chunks * (unsigned long long)c +
-                                      prefix[n_u] % (unsigned long long)n_chunks * (unsigned long long)c /
-                                          (unsigned long long)n_chunks;
-    int64_t lo = 0, hi = n_u;  // smallest u in [0, n_u] with prefix[u] >= target
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) / 2;
-        if (prefix[mid] >= target) hi = mid; else lo = mid + 1;
-    }
-    start[c] = lo;
-}
-
 // Picks the hot rows of the back CSR (the kHotMax longest rows with at least
-// kHotMinLen entries; AHPP_HOT_ROWS=<n> lowers the cap, 0 turns it off),
-// splits U into the pass's chunks and blocks, builds the segmented hot list
-// and the back schedule without the hot rows.
+// kHotMinLen entries, longest first; AHPP_HOT_ROWS=<n> lowers the cap, 0
+// turns them off), builds their dense MFMA weights and the back schedule
+// without them.  The dense block (6 bytes per hot row and U node, rounded up
+// to whole chunks) is used when it takes at most a quarter of the device's
+// memory, a fixed property of the device, so whether a graph has hot rows
+// (and so the order of its sums) does not depend on what else is allocated.
 void build_hot(Graph &g, hipStream_t s) {
     HotSet &h = g.hot;
     int cap = kHotMax;
     if (const char *e = std::getenv("AHPP_HOT_ROWS")) cap = std::max(0, std::min(kHotMax, std::atoi(e)));
     const int64_t n_rows = g.back.n_rows;
     if (cap == 0 || n_rows == 0 || g.back.nnz == 0) return;
+    size_t free_b = 0, total_b = 0;
+    check_hip(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    if ((double)hot_dense_bytes(g) > 0.25 * (double)total_b) return;
     std::vector<int64_t> off((size_t)n_rows + 1);
     check_hip(hipMemcpyAsync(off.data(), g.back.off, off.size() * 8, hipMemcpyDeviceToHost, s), "hot rows");
     check_hip(hipStreamSynchronize(s), "hot rows");
@@ -560,95 +492,20 @@ void build_hot(Graph &g, hipStream_t s) {
                      [&](int32_t a, int32_t b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
     if ((int)order.size() > cap) order.resize(cap);
     const int n = (int)order.size();
-    // Hot index h belongs to wave h % kHotWaves (register row h / kHotWaves)
-    // of the streaming pass, whose blocks wait for their slowest wave.  The
-    // rows, longest first, take the free index of the wave with the fewest
-    // entries so far, which levels the waves' totals; each row keeps its own
-    // accumulator, so the sums do not change.
-    {
-        std::vector<int64_t> total(kHotWaves, 0);
-        std::vector<int> used(kHotWaves, 0);
-        std::vector<int32_t> placed((size_t)n, -1);
-        for (int i = 0; i < n; ++i) {
-            int best = -1;
-            for (int wv = 0; wv < kHotWaves; ++wv) {
-                if (wv + used[wv] * kHotWaves >= n) continue;  // no index of this wave left below n
-                if (best < 0 || total[wv] < total[best]) best = wv;
-            }
-            placed[(size_t)(best + used[best] * kHotWaves)] = order[i];
-            ++used[best];
-            total[best] += off[order[i] + 1] - off[order[i]];
-        }
-        order.swap(placed);
-    }
     std::vector<int32_t> len(n);
-    std::vector<int64_t> start(n + 1, 0);
     std::vector<uint8_t> skip((size_t)n_rows, 0);
+    int64_t m = 0;
     for (int i = 0; i < n; ++i) {
         len[i] = (int32_t)(off[order[i] + 1] - off[order[i]]);
-        start[i + 1] = start[i] + len[i];
+        m += len[i];
         skip[order[i]] = 1;
     }
-    const int64_t m = start[n];
     h.n = n;
     h.rows = (int32_t *)dev_alloc(g, (size_t)n * 4, "hot rows");
     h.len = (int32_t *)dev_alloc(g, (size_t)n * 4, "hot rows");
     check_hip(hipMemcpyAsync(h.rows, order.data(), (size_t)n * 4, hipMemcpyHostToDevice, s), "hot rows");
     check_hip(hipMemcpyAsync(h.len, len.data(), (size_t)n * 4, hipMemcpyHostToDevice, s), "hot rows");
-    {  // hot entries, chunks and the segmented list; the scratch ends with the block
-        DevTemp<int64_t> start_((size_t)n + 1, "hot entries");
-        DevTemp<uint32_t> key_((size_t)m, "hot entries");
-        DevTemp<int32_t> col_((size_t)m, "hot entries");
-        DevTemp<float> w_((size_t)m, "hot entries");
-        int64_t *d_start = start_.get();
-        uint32_t *key = key_.get();
-        int32_t *col = col_.get();
-        float *w = w_.get();
-        check_hip(hipMemcpyAsync(d_start, start.data(), (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s), "hot entries");
-
-        // Fixed chunking (a property of the graph and the device, not of the
-        // launch), so the sum order never depends on how many tiles run.  The
-        // chunks are balanced by cost (a row's hot entries plus kHotWaves for its
-        // staging), since the device numbering puts the rows with the most
-        // entries first.
-        h.n_chunks = (int32_t)std::max<int64_t>(1, std::min<int64_t>(g.n_cu, g.n_u));
-        h.chunk_start = (int64_t *)dev_alloc(g, (size_t)(h.n_chunks + 1) * 8, "hot chunks");
-        {
-            const int64_t nc = g.n_u + 1;
-            DevTemp<unsigned> cnt_((size_t)g.n_u, "hot chunks");
-            DevTemp<unsigned long long> cost_((size_t)nc, "hot chunks");
-            DevTemp<unsigned long long> part_((size_t)((nc + kScanTile - 1) / kScanTile + 1), "hot chunks");
-            unsigned *cnt = cnt_.get();
-            unsigned long long *cost = cost_.get(), *part = part_.get();
-            check_hip(hipMemsetAsync(cnt, 0, (size_t)g.n_u * 4, s), "hot chunks");
-            hipLaunchKernelGGL(k_hot_count, dim3(grid_for(m)), dim3(kBlock), 0, s, g.back.off, g.back.col, h.rows,
-                               d_start, n, m, cnt);
-            hipLaunchKernelGGL(k_hot_cost, dim3(grid_for(nc)), dim3(kBlock), 0, s, cnt, g.n_u, cost);
-            exclusive_scan_u64(cost, cost, nc, part, s);
-            hipLaunchKernelGGL(k_chunk_bounds, dim3(grid_for(h.n_chunks + 1)), dim3(kBlock), 0, s, cost, g.n_u,
-                               h.n_chunks, h.chunk_start);
-            check_hip(hipGetLastError(), "hot chunks launch");
-            check_hip(hipStreamSynchronize(s), "hot chunks");
-        }
-        // Blocks of kHotBlockRows rows from each chunk's start.
-        std::vector<int64_t> cstart((size_t)h.n_chunks + 1), bbase((size_t)h.n_chunks + 1, 0);
-        check_hip(hipMemcpyAsync(cstart.data(), h.chunk_start, cstart.size() * 8, hipMemcpyDeviceToHost, s),
-                  "hot chunks");
-        check_hip(hipStreamSynchronize(s), "hot chunks");
-        for (int c = 0; c < h.n_chunks; ++c)
-            bbase[c + 1] = bbase[c] + (cstart[c + 1] - cstart[c] + kHotBlockRows - 1) / kHotBlockRows;
-        h.n_blocks = bbase[h.n_chunks];
-        const int64_t n_seg = (int64_t)kHotWaves * h.n_blocks * kHotPerWave;
-        if (n_seg >= (int64_t)UINT32_MAX) throw Failure{-1, "ahpp_graph_load: too many hot-pass blocks"};
-        h.blk_base = (int64_t *)dev_alloc(g, bbase.size() * 8, "hot chunks");
-        check_hip(hipMemcpyAsync(h.blk_base, bbase.data(), bbase.size() * 8, hipMemcpyHostToDevice, s), "hot chunks");
-        hipLaunchKernelGGL(k_hot_entries, dim3(grid_for(m)), dim3(kBlock), 0, s, g.back.off, g.back.col, g.back.w,
-                           h.rows, d_start, n, m, (const int64_t *)h.chunk_start, (const int64_t *)h.blk_base,
-                           h.n_chunks, h.n_blocks, key, col, w);
-        check_hip(hipGetLastError(), "hot entries launch");
-        // Segments keep their entries in row order (a sort by row within the block first).
-        build_csr(g, h.list, n_seg, key, col, w, m, true, s, kHotBlockRows, false);
-    }
+    build_hot_dense(g, s);
     // Back schedule without the hot rows.
     std::vector<WorkItem> items;
     std::vector<SplitRow> split;
@@ -817,7 +674,6 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
     g.dangling_u = (int64_t)dang;
     trace.mark("coefficients", s);
     build_hot(g, s);
-    if (hot_dense_enabled()) build_hot_dense(g, s);
     trace.mark("hot rows", s);
     g.load_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -834,10 +690,9 @@ void free_graph(Graph &g) {
     g.cap_stream = nullptr;
     free_csr(g.fwd);
     free_csr(g.back);
-    free_csr(g.hot.list);
     free_mc_tables(g.mc);
     for (void *p : {(void *)g.hot.rows, (void *)g.hot.len, (void *)g.hot.cold_items, (void *)g.hot.cold_split,
-                    (void *)g.hot.chunk_start, (void *)g.hot.blk_base, (void *)g.hot.w3})
+                    (void *)g.hot.w3})
         dfree(p);
     g.hot = HotSet{};
     free_batch_state(g.batch);

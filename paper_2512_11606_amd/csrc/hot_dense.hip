@@ -24,8 +24,6 @@
 
 #include <algorithm>
 #include <cfloat>
-#include <cstdlib>
-#include <cstring>
 
 #include "ahpp_internal.h"
 
@@ -211,24 +209,31 @@ __global__ void __launch_bounds__(kDenseThreads) kb_hot_dense(DenseArgs a) {
 
 }  // namespace
 
-bool hot_dense_enabled() {
-    static const bool on = [] {
-        const char *e = std::getenv("AHPP_HOT_DENSE");
-        return !(e && std::atoi(e) == 0);
-    }();
-    return on;
+namespace {
+// U rows per chunk of a graph (a multiple of kStageU) and the chunk count.
+void dense_shape(int64_t n_u, int64_t *kc, int64_t *n_chunks) {
+    int64_t c = (n_u + kDenseChunks - 1) / kDenseChunks;
+    c = (c + kStageU - 1) / kStageU * kStageU;
+    *kc = std::max<int64_t>(c, kStageU);
+    *n_chunks = (n_u + *kc - 1) / *kc;
+}
+}  // namespace
+
+size_t hot_dense_bytes(const Graph &g) {
+    int64_t kc, n_chunks;
+    dense_shape(g.n_u, &kc, &n_chunks);
+    return (size_t)3 * (size_t)(n_chunks * kc / kKS) * kHBlocks * kFragElems * 2;
 }
 
 void build_hot_dense(Graph &g, hipStream_t s) {
     HotSet &h = g.hot;
     if (h.n <= 0 || g.n_u <= 0) return;
-    int64_t kc = (g.n_u + kDenseChunks - 1) / kDenseChunks;
-    kc = (kc + kStageU - 1) / kStageU * kStageU;
-    const int64_t n_chunks = (g.n_u + kc - 1) / kc;
+    int64_t kc, n_chunks;
+    dense_shape(g.n_u, &kc, &n_chunks);
     const int64_t n_ks = n_chunks * kc / kKS;
-    const size_t elems = (size_t)3 * n_ks * kHBlocks * kFragElems;
-    h.w3 = (uint16_t *)dev_alloc(g, elems * 2, "dense hot weights");
-    check_hip(hipMemsetAsync(h.w3, 0, elems * 2, s), "dense hot weights");
+    const size_t bytes = hot_dense_bytes(g);
+    h.w3 = (uint16_t *)dev_alloc(g, bytes, "dense hot weights");
+    check_hip(hipMemsetAsync(h.w3, 0, bytes, s), "dense hot weights");
     hipLaunchKernelGGL(k_hot_w3, dim3((unsigned)h.n), dim3(kBlock), 0, s, (const int64_t *)g.back.off,
                        (const int32_t *)g.back.col, (const float *)g.back.w, (const int32_t *)h.rows, n_ks, h.w3);
     check_hip(hipGetLastError(), "dense hot weights launch");
