@@ -28,7 +28,7 @@ def test_source_hash_covers_every_schedule_source(tmp_path):
         open(p, "wb").write(old)
     assert bench._source_hash(files) == base
     names = {os.path.basename(p) for p in bench.KERNEL_SOURCES}
-    assert names == {"batch.hip", "ahpp_internal.h", "graph_build.hip"}
+    assert names == {"batch.hip", "hot_dense.hip", "ahpp_internal.h", "graph_build.hip"}
 
 
 @pytest.mark.parametrize("kind", sorted(bench.TRAFFIC_FILES))
