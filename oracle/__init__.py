@@ -78,6 +78,10 @@ def _load():
     lib.og_normalisers.argtypes = [P, P, P, P, P]
     lib.og_power_series.restype = ctypes.c_int
     lib.og_power_series.argtypes = [P, dbl, dbl, i32, ctypes.c_int, P, P, ctypes.c_int]
+    lib.og_power_series_terms.restype = ctypes.c_int
+    lib.og_power_series_terms.argtypes = [P, dbl, dbl, P, P, ctypes.c_int, ctypes.c_int]
+    lib.og_l1.restype = dbl
+    lib.og_l1.argtypes = [P, i64]
     lib.og_lambda_thm3.restype = dbl
     lib.og_lambda_thm3.argtypes = [P, dbl, dbl, ctypes.c_int, P, ctypes.c_int]
     lib.og_asrp.restype = ctypes.c_int
@@ -182,16 +186,32 @@ class OracleGraph:
         return d_u, d_v, s_u, t_a
 
     def power_series(self, source: int, alpha: float = ALPHA, beta: float = BETA, T: Optional[int] = None,
-                     nthreads: int = 0):
-        """Exact AHPP row of ``source`` (Def. 2) and the l1 bound of the dropped tail."""
+                     nthreads: int = 0, progress=None, every: int = 16):
+        """Exact AHPP row of ``source`` (Def. 2) and the l1 bound of the dropped tail.
+
+        With ``progress`` the T terms are summed ``every`` at a time (the same
+        steps in the same order) and progress(terms_done, T) is called after
+        each group."""
         T = pi_iterations(alpha) if T is None else T
         out = np.zeros(self.n_u)
-        tail = ctypes.c_double(0.0)
-        rc = _load().og_power_series(self._h, alpha, beta, int(source), int(T), _ptr(out), ctypes.byref(tail),
-                                     int(nthreads))
-        if rc != 0:
+        if progress is None:
+            tail = ctypes.c_double(0.0)
+            rc = _load().og_power_series(self._h, alpha, beta, int(source), int(T), _ptr(out), ctypes.byref(tail),
+                                         int(nthreads))
+            if rc != 0:
+                raise ValueError("power_series: bad arguments")
+            return out, tail.value
+        if not 0 <= source < self.n_u or T < 0 or every < 1:
             raise ValueError("power_series: bad arguments")
-        return out, tail.value
+        y = np.zeros(self.n_u)
+        y[source] = 1.0
+        done = 0
+        while done < T:
+            n = min(every, T - done)
+            _load().og_power_series_terms(self._h, alpha, beta, _ptr(y), _ptr(out), int(n), int(nthreads))
+            done += n
+            progress(done, T)
+        return out, _load().og_l1(_ptr(y), self.n_u)
 
     def lambda_thm3(self, alpha: float = ALPHA, beta: float = BETA, T: Optional[int] = None,
                     return_pi_T: bool = False, nthreads: int = 0):

@@ -11,7 +11,8 @@
  *   og_build / og_free      adjacency lists N(u), N(v), A(u), A^-1(a) with
  *                           weights and the normalisers d(u), d(v), s(u), t(a)
  *                           (Section 2.1 notation; Eq. 1 and Eq. 2 denominators)
- *   og_power_series         exact AHPP by the power series of Def. 2 / Eq. 3,
+ *   og_power_series         exact AHPP by the power series of Def. 2 / Eq. 3
+ *                           (og_power_series_terms: the same, some terms at a time),
  *                           i.e. Algorithm 1 (PI) written as a truncated sum
  *   og_lambda_thm3          lambda of Theorem 3 (Eq. 6): PI from the all-ones
  *                           row vector, max entry plus |U|(1-alpha)^T
@@ -161,6 +162,32 @@ static void apply_P(const og_graph *g, double beta, const double *y, double *y_o
     }
 }
 
+/* L further terms of the series of Def. 2 from the current term
+ * y = (1-alpha)^l e_u P^l: pi += alpha y, then y <- (1-alpha) y P, L times. */
+int og_power_series_terms(const og_graph *g, double alpha, double beta, double *y, double *pi, int L,
+                          int nthreads) {
+    if (!g || !y || !pi || L < 0) return -1;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    const int64_t n_u = g->n_u;
+    double *y2 = (double *)calloc((size_t)n_u, sizeof(double));
+    double *z_v = (double *)calloc((size_t)(g->n_v + 1), sizeof(double));
+    double *z_a = (double *)calloc((size_t)(g->n_a + 1), sizeof(double));
+    for (int l = 0; l < L; ++l) {
+        for (int64_t j = 0; j < n_u; ++j) pi[j] += alpha * y[j];
+        apply_P(g, beta, y, y2, z_v, z_a);
+        for (int64_t j = 0; j < n_u; ++j) y[j] = (1.0 - alpha) * y2[j];
+    }
+    free(y2); free(z_v); free(z_a);
+    return 0;
+}
+
+/* ||y||_1, summed in index order. */
+double og_l1(const double *y, int64_t n) {
+    double s = 0.0;
+    for (int64_t j = 0; j < n; ++j) s += fabs(y[j]);
+    return s;
+}
+
 /* Exact AHPP (Def. 2): pi_u = sum_{l=0}^{T-1} alpha (1-alpha)^l e_u P^l.
  * The dropped tail sum_{l>=T} alpha (1-alpha)^l e_u P^l is entrywise at most
  * ||(1-alpha)^T e_u P^T||_1, returned in *tail_l1 (Section 3.2: the PI error
@@ -168,25 +195,13 @@ static void apply_P(const og_graph *g, double beta, const double *y, double *y_o
 int og_power_series(const og_graph *g, double alpha, double beta, int32_t source, int T, double *pi_out,
                     double *tail_l1, int nthreads) {
     if (!g || source < 0 || source >= g->n_u || T < 0) return -1;
-    if (nthreads > 0) omp_set_num_threads(nthreads);
     const int64_t n_u = g->n_u;
     double *y = (double *)calloc((size_t)n_u, sizeof(double));
-    double *y2 = (double *)calloc((size_t)n_u, sizeof(double));
-    double *z_v = (double *)calloc((size_t)(g->n_v + 1), sizeof(double));
-    double *z_a = (double *)calloc((size_t)(g->n_a + 1), sizeof(double));
     memset(pi_out, 0, (size_t)n_u * sizeof(double));
     y[source] = 1.0;                       /* (1-alpha)^0 e_u P^0 */
-    for (int l = 0; l < T; ++l) {
-        for (int64_t j = 0; j < n_u; ++j) pi_out[j] += alpha * y[j];
-        apply_P(g, beta, y, y2, z_v, z_a);
-        for (int64_t j = 0; j < n_u; ++j) y[j] = (1.0 - alpha) * y2[j];
-    }
-    if (tail_l1) {
-        double s = 0.0;
-        for (int64_t j = 0; j < n_u; ++j) s += fabs(y[j]);
-        *tail_l1 = s;
-    }
-    free(y); free(y2); free(z_v); free(z_a);
+    og_power_series_terms(g, alpha, beta, y, pi_out, T, nthreads);
+    if (tail_l1) *tail_l1 = og_l1(y, n_u);
+    free(y);
     return 0;
 }
 

@@ -75,6 +75,11 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with __graft_entry__.build() or "
                           "python paper_2512_11606_amd/build.py")
+    # torch and this library both link libamdhip64.so.7, and the process keeps
+    # whichever copy is loaded first.  torch's device memory and streams must
+    # live in the runtime the library's kernels use, and torch cannot start
+    # its own on a runtime another build loaded, so torch goes first.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.ahpp_graph_load.restype = ctypes.c_int

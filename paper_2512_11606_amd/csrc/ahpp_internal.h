@@ -16,6 +16,7 @@ namespace ahpp {
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kBlock = 256;          // threads per workgroup (4 waves)
 constexpr int kItemEdges = 1024;     // CSR entries handled by one wave item
+constexpr int kCsrPad = 32;          // zero entries (column 0, weight 0) after the last CSR entry
 constexpr int kPerLane = kItemEdges / kWave;
 constexpr int kShortRow = 64;        // rows up to this length are packed together
 constexpr int kMaxRowsPerItem = 128; // rows per packed item (a multiple of kWave)
@@ -46,8 +47,8 @@ struct SplitRow {
 struct DevCsr {
     int64_t n_rows = 0, nnz = 0;
     int64_t *off = nullptr;         // n_rows + 1
-    int32_t *col = nullptr;         // nnz
-    float *w = nullptr;             // nnz (nullptr when every weight is 1)
+    int32_t *col = nullptr;         // nnz, then kCsrPad zeros
+    float *w = nullptr;             // nnz, then kCsrPad zeros (nullptr when every weight is 1)
     WorkItem *items = nullptr;      // n_items
     int64_t n_items = 0;
     SplitRow *split = nullptr;      // rows cut into several chunks

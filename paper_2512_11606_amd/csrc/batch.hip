@@ -162,6 +162,13 @@ __device__ __forceinline__ float readlane_f(float v, int k) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
 }
 
+// A value the same in every lane, held in scalar registers.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u), hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ int64_t lane_col() { return (int64_t)(threadIdx.x & 63) * kVec; }
 
 // Per-lane epilogues over the lane's kVec queries.
@@ -239,16 +246,25 @@ struct BEpi<kBFwd> {
     }
 };
 
-// Sum over entries [e0, e0 + ne) of w * thr(x[col]) for this lane's queries,
+// Sum over entries [e0, e0 + ne) of w * x[col] for this lane's queries,
 // flushing each completed row of [r0, r0 + n_rows) through the epilogue.
-// Row ends are relative to e0; rows may be empty.
+// Row ends are relative to e0; rows may be empty.  r0, n_rows, e0, ne and
+// every row end are the same in all lanes (the caller makes them so): the
+// columns and weights come in groups of kInFlight through scalar loads (the
+// columns a group ahead), the loop's tests are scalar, and the kInFlight
+// gathers of a group are issued without tests.  Slots past the last entry
+// read the entries that follow (the CSR's zero padding at its end) and add
+// them with weight 0.  A stopped query's sums are computed like the others
+// and discarded by the epilogue.
 template <bool kUnit, int kMode, class RowEnd, class RowScale>
-__device__ __forceinline__ void run_entries(const BArgs &a, const uint16_t *__restrict__ xt, int64_t r0, int n_rows,
-                                            int64_t e0, int ne, BEpi<kMode> &epi, RowEnd row_end,
-                                            RowScale row_scale, QV *acc_out) {
+__device__ __forceinline__ void run_entries(const int32_t *__restrict__ col, const float *__restrict__ wt,
+                                            const uint16_t *__restrict__ xt, int64_t r0, int n_rows, int64_t e0,
+                                            int ne, BEpi<kMode> &epi, RowEnd row_end, RowScale row_scale,
+                                            QV *acc_out) {
     using Pre = typename BEpi<kMode>::Pre;
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t lc = lane_col();
+    const uint32_t lane_bytes = (uint32_t)lane * (kVec * 2);
+    const char *xb = reinterpret_cast<const char *>(xt);
     int j = 0, rstart = 0;
     int rend = n_rows > 0 ? row_end(0) : INT_MAX;
     Pre pre = epi.pre(r0, n_rows > 0 ? row_scale(0) : 0.0f);
@@ -263,47 +279,41 @@ __device__ __forceinline__ void run_entries(const BArgs &a, const uint16_t *__re
             rend = INT_MAX;
         }
     }
-    for (int base = 0; base < ne; base += kWave) {
-        const int cnt = ne - base < kWave ? ne - base : kWave;
-        const int32_t my_c = lane < cnt ? a.col[e0 + base + lane] : 0;
-        float my_w = 1.0f;
-        if constexpr (!kUnit) my_w = lane < cnt ? a.w[e0 + base + lane] : 0.0f;
-        for (int k0 = 0; k0 < cnt; k0 += kInFlight) {
-            uint2 v[kInFlight];  // packed transport values, unpacked when added
+    for (int k0 = 0; k0 < ne; k0 += kInFlight) {
+        int32_t cn[kInFlight];
+        float wk[kInFlight];
 #pragma unroll
-            for (int u = 0; u < kInFlight; ++u) {
-                const int k = k0 + u < kWave ? k0 + u : kWave - 1;
-                const int32_t c = __builtin_amdgcn_readlane(my_c, k);
-                v[u] = k0 + u < cnt ? *reinterpret_cast<const uint2 *>(xt + (int64_t)c * kTileQ + lc)
-                                    : make_uint2(0u, 0u);
-            }
+        for (int u = 0; u < kInFlight; ++u) cn[u] = col[e0 + k0 + u];
 #pragma unroll
-            for (int u = 0; u < kInFlight; ++u) {
-                const int k = k0 + u;
-                if (k < cnt) {
-                    const float wk = kUnit ? 1.0f : readlane_f(my_w, k);
-                    const float xu[kVec] = {__uint_as_float(v[u].x << 16), __uint_as_float(v[u].x & 0xFFFF0000u),
-                                            __uint_as_float(v[u].y << 16), __uint_as_float(v[u].y & 0xFFFF0000u)};
+        for (int u = 0; u < kInFlight; ++u) wk[u] = kUnit ? 1.0f : wt[e0 + k0 + u];
+        uint2 v[kInFlight];  // packed transport values, unpacked when added
 #pragma unroll
-                    for (int q = 0; q < kVec; ++q) {
-                        float xv = xu[q];
-                        // Q is already cut by the threshold; a stopped query pushes nothing.
-                        if constexpr (kMode == kBBack) xv = epi.theta.v[q] != FLT_MAX ? xv : 0.0f;
-                        acc.v[q] += kUnit ? xv : wk * xv;
-                    }
-                    const int e = base + k + 1;
-                    while (e == rend) {
-                        epi.full(r0 + j, acc, pre, rend - rstart);
-                        acc = qv_zero();
-                        rstart = rend;
-                        ++j;
-                        if (j < n_rows) {
-                            rend = row_end(j);
-                            pre = epi.pre(r0 + j, row_scale(j));
-                        } else {
-                            rend = INT_MAX;
-                        }
-                    }
+        for (int u = 0; u < kInFlight; ++u) {
+            const char *row = xb + (size_t)(uint32_t)cn[u] * (kTileQ * 2);
+            v[u] = *reinterpret_cast<const uint2 *>(row + lane_bytes);
+        }
+        if (ne - k0 < kInFlight) {
+#pragma unroll
+            for (int u = 0; u < kInFlight; ++u)
+                if (u >= ne - k0) wk[u] = 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) {
+            const float xu[kVec] = {__uint_as_float(v[u].x << 16), __uint_as_float(v[u].x & 0xFFFF0000u),
+                                    __uint_as_float(v[u].y << 16), __uint_as_float(v[u].y & 0xFFFF0000u)};
+#pragma unroll
+            for (int q = 0; q < kVec; ++q) acc.v[q] += wk[u] * xu[q];
+            const int e = k0 + u + 1;
+            while (e == rend) {
+                epi.full(r0 + j, acc, pre, rend - rstart);
+                acc = qv_zero();
+                rstart = rend;
+                ++j;
+                if (j < n_rows) {
+                    rend = row_end(j);
+                    pre = epi.pre(r0 + j, row_scale(j));
+                } else {
+                    rend = INT_MAX;
                 }
             }
         }
@@ -373,7 +383,8 @@ __device__ __forceinline__ void bflush(const BArgs &a, int t, int j, BEpi<kMode>
 }
 
 template <bool kUnit, int kMode>
-__global__ void __launch_bounds__(kBlock) kb_gather(BArgs a) {
+__global__ void __launch_bounds__(kBlock) kb_gather(BArgs a, const int32_t *__restrict__ col,
+                                                    const float *__restrict__ wt) {
     const int t = blockIdx.y, wg = blockIdx.x;
     const TileCtl &tc = a.ctl[t];
     if (tc.all_done) return;
@@ -381,15 +392,17 @@ __global__ void __launch_bounds__(kBlock) kb_gather(BArgs a) {
     const uint16_t *xt = a.x + t * a.x_stride;
     float *part = a.part + t * a.part_stride;
     BEpi<kMode> epi = make_bepi<kMode>(a, t, lane_theta(tc));
-    const int64_t wave0 = (int64_t)wg * kWavesPerBlock + (threadIdx.x >> 6);
+    const int64_t wave0 = (int64_t)wg * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t it = wave0; it < a.n_items; it += stride) {
-        const WorkItem item = a.items[it];
+        WorkItem item = a.items[it];
+        item.row = __builtin_amdgcn_readfirstlane(item.row);
+        item.n = __builtin_amdgcn_readfirstlane(item.n);
         if (item.n > 0) {
             const int64_t r0 = item.row;
             const int n = item.n;
-            const int64_t e0 = a.off[r0];
-            const int ne = (int)(a.off[r0 + n] - e0);
+            const int64_t e0 = uniform64(a.off[r0]);
+            const int ne = __builtin_amdgcn_readfirstlane((int)(a.off[r0 + n] - e0));
             // Row ends (relative to e0) and row scales, one row per lane.
             int end0 = INT_MAX, end1 = INT_MAX;
             float sc0 = 0.0f, sc1 = 0.0f;
@@ -403,10 +416,10 @@ __global__ void __launch_bounds__(kBlock) kb_gather(BArgs a) {
                 return jj < kWave ? __builtin_amdgcn_readlane(end0, jj) : __builtin_amdgcn_readlane(end1, jj - kWave);
             };
             auto row_scale = [&](int jj) { return jj < kWave ? readlane_f(sc0, jj) : readlane_f(sc1, jj - kWave); };
-            run_entries<kUnit, kMode>(a, xt, r0, n, e0, ne, epi, row_end, row_scale, nullptr);
+            run_entries<kUnit, kMode>(col, wt, xt, r0, n, e0, ne, epi, row_end, row_scale, nullptr);
         } else {
             const int64_t row = item.row;
-            const int64_t rb = a.off[row], re = a.off[row + 1];
+            const int64_t rb = uniform64(a.off[row]), re = uniform64(a.off[row + 1]);
             const int64_t e0 = rb + (int64_t)(-item.n) * kItemEdges;
             const int ne = (int)(re - e0 < kItemEdges ? re - e0 : kItemEdges);
             const bool whole = re - rb <= kItemEdges;
@@ -415,7 +428,7 @@ __global__ void __launch_bounds__(kBlock) kb_gather(BArgs a) {
             auto row_end = [&](int) { return whole ? ne : INT_MAX; };
             auto row_scale = [&](int) { return scale; };
             QV acc;
-            run_entries<kUnit, kMode>(a, xt, row, whole ? 1 : 0, e0, ne, epi, row_end, row_scale, &acc);
+            run_entries<kUnit, kMode>(col, wt, xt, row, whole ? 1 : 0, e0, ne, epi, row_end, row_scale, &acc);
             if (!whole) qv_store(part + it * kTileQ + lane_col(), acc);
         }
     }
@@ -962,7 +975,8 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
                              q * (2.0 * g.n_u + 8.0 * hs.dense_chunks * hs.n + 10.0 * hs.n);
     if (p.back)
         profiled(g.prof, 2, back_bytes, back_comp, s, [&] {
-            hipLaunchKernelGGL((kb_gather<false, kBBack>), dim3(p.back, nt), dim3(kBlock), 0, s, back);
+            hipLaunchKernelGGL((kb_gather<false, kBBack>), dim3(p.back, nt), dim3(kBlock), 0, s, back,
+                               (const int32_t *)g.back.col, (const float *)g.back.w);
         });
     if (p.back_fix) {
         BArgs a = back;
@@ -984,9 +998,11 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
               b.blk_np + 2 * slot, sf, su, (float)g.alpha};
     profiled(g.prof, 3, fwd_bytes, fwd_comp, s, [&] {
         if (g.unit)
-            hipLaunchKernelGGL((kb_gather<true, kBFwd>), dim3(p.fwd, nt), dim3(kBlock), 0, s, fwd);
+            hipLaunchKernelGGL((kb_gather<true, kBFwd>), dim3(p.fwd, nt), dim3(kBlock), 0, s, fwd,
+                               (const int32_t *)g.fwd.col, (const float *)nullptr);
         else
-            hipLaunchKernelGGL((kb_gather<false, kBFwd>), dim3(p.fwd, nt), dim3(kBlock), 0, s, fwd);
+            hipLaunchKernelGGL((kb_gather<false, kBFwd>), dim3(p.fwd, nt), dim3(kBlock), 0, s, fwd,
+                               (const int32_t *)g.fwd.col, (const float *)g.fwd.w);
     });
     if (p.fwd_fix) {
         BArgs a = fwd;

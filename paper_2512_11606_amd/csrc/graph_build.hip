@@ -391,8 +391,13 @@ void build_csr(Graph &g, DevCsr &c, int64_t n_rows, uint32_t *key, int32_t *col,
     c.n_rows = n_rows;
     c.nnz = m;
     c.off = (int64_t *)dev_alloc(g, (size_t)(n_rows + 1) * sizeof(int64_t), "csr offsets");
-    c.col = (int32_t *)dev_alloc(g, (size_t)std::max<int64_t>(m, 1) * sizeof(int32_t), "csr columns");
-    if (keep_w) c.w = (float *)dev_alloc(g, (size_t)std::max<int64_t>(m, 1) * sizeof(float), "csr weights");
+    // The padding lets a group of scalar loads run past the last row's end.
+    c.col = (int32_t *)dev_alloc(g, (size_t)(m + kCsrPad) * sizeof(int32_t), "csr columns");
+    check_hip(hipMemsetAsync(c.col + m, 0, kCsrPad * sizeof(int32_t), s), "csr padding");
+    if (keep_w) {
+        c.w = (float *)dev_alloc(g, (size_t)(m + kCsrPad) * sizeof(float), "csr weights");
+        check_hip(hipMemsetAsync(c.w + m, 0, kCsrPad * sizeof(float), s), "csr padding");
+    }
     if (m > 0) {
         // Columns are non-negative, so their bits order like unsigned keys.
         if (n_cols > 0)

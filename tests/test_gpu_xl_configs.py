@@ -125,8 +125,14 @@ def test_hub_batch_on_the_20m_graph(env):
             t = time.time()
             og = O.OracleGraph.from_graph(g)
             box["build_s"] = time.time() - t
+            _say(f"oracle adjacency built in {box['build_s']:.1f} s")
             t = time.time()
-            box["exact"], box["tail"] = og.power_series(int(srcs[0]))
+
+            def report(done, total):
+                if done % 32 == 0 or done == total:
+                    _say(f"oracle series: {done} of {total} terms, {time.time() - t:.1f} s")
+
+            box["exact"], box["tail"] = og.power_series(int(srcs[0]), progress=report)
             box["series_s"] = time.time() - t
             og.close()
         except BaseException as e:  # noqa: BLE001 - re-raised below

@@ -117,6 +117,21 @@ def test_power_series_matches_dense_solve(tiny_oracle, tiny_Pi):
         assert tail < 1e-12
 
 
+def test_power_series_in_groups_equals_one_call(tiny_oracle, tiny_Pi):
+    """Summed a few terms at a time (with progress reports) the series takes
+    the same steps: the same row and tail bit for bit, still the dense solve."""
+    seen = []
+    for every in (1, 7, 64, 1000):
+        seen.clear()
+        pi, tail = tiny_oracle.power_series(777, progress=lambda d, t: seen.append((d, t)), every=every)
+        ref, ref_tail = tiny_oracle.power_series(777)
+        assert np.array_equal(pi, ref) and tail == ref_tail
+        assert np.abs(pi - tiny_Pi[777]).max() < 1e-12
+        assert seen[-1][0] == seen[-1][1] and all(a[0] < b[0] for a, b in zip(seen, seen[1:]))
+    with pytest.raises(ValueError):
+        tiny_oracle.power_series(-1, progress=print)
+
+
 def test_power_series_weighted_matches_dense_solve():
     g = small_weighted()
     og = O.OracleGraph.from_graph(g)
