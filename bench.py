@@ -276,6 +276,7 @@ def prep_cache_leg(ahpp, synth, name="large20m"):
     t = time.perf_counter()
     g = synth.make_graph(name)
     gen_s = time.perf_counter() - t
+    print(f"[bench] generated {name} in {gen_s:.1f} s", file=sys.stderr, flush=True)
     d = tempfile.mkdtemp(prefix="ahpp-cache-")
     out = {"workload": f"load of {name} ({g.n_u}/{g.n_v}/{g.m_e} edges, {g.m_a} attribute entries) from host COO, "
                        f"fresh then from the lambda cache", "generate_s": round(gen_s, 1)}
@@ -288,6 +289,7 @@ def prep_cache_leg(ahpp, synth, name="large20m"):
             out[leg] = {"wall_s": round(wall, 2), "build_ms": round(info["load_ms"], 1),
                         "lambda_ms": round(info["lambda_ms"], 1), "lambda_cached": info["lambda_cached"],
                         "device_bytes": info["device_bytes"]}
+            print(f"[bench] {name} load ({leg}): {wall:.2f} s", file=sys.stderr, flush=True)
             dg.free()
     finally:
         shutil.rmtree(d, ignore_errors=True)

@@ -3,15 +3,18 @@
 //
 // Queries are independent (each has its own residues, reserves, eps_f,
 // threshold, phase and stop rule), so a batch is a set of tiles of kTileQ
-// queries, kVec consecutive queries per lane of a wave.  A tile's vectors are
-// stored node-major: node x owns the kTileQ floats [x][0..kTileQ), one 1 KB
-// row.  A round is the same pair of pull-form gathers as the single-query
-// path (z = inv_b * W'^T thr(r), then r <- keep(r) + W z with the reserve
-// update), but every CSR entry is read once per tile and drives one
-// contiguous 1 KB gather of all the tile's queries (random 1 KB reads run
-// near HBM speed on MI355X, 256-byte ones at about half of it).  Row
-// bookkeeping is wave-uniform (scalar), and each wave keeps kInFlight
-// gathers in flight.
+// queries.  A tile's vectors are stored node-major: node x owns the kTileQ
+// values [x][0..kTileQ) (1 KB of float32 state, 512 bytes of bfloat16
+// transport).  A round is the same pair of pull-form gathers as the
+// single-query path (z = inv_b * W'^T thr(r), then r <- keep(r) + W z with
+// the reserve update), but every CSR entry is read once per tile and drives
+// one contiguous 512-byte gather of all the tile's queries.  Row bookkeeping
+// is wave-uniform (scalar), columns and weights arrive through scalar loads,
+// and each wave keeps 8 KB of gathers in flight.  The forward gather reads
+// two entries per 16-byte lane load (one per half-wave): gathers that hit
+// L2 are bound by the number of load instructions (about 28 G wave loads/s
+// on MI355X whatever their width), those that miss by bytes (about 7.5 TB/s
+// for random rows), and half of the forward gathers hit.
 //
 // A query that has stopped keeps threshold +inf: it pushes nothing, so its
 // state no longer changes while the rest of its tile runs on.
@@ -54,7 +57,7 @@ static_assert(kVec == 4 || kVec == 2 || kVec == 1, "kVec must be 1, 2 or 4");
 static_assert(kTileQ <= kBlock, "one workgroup thread per tile query");
 
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kInFlight = 16;  // gathers issued before the first is used (8 bytes per lane each)
+constexpr int kEntryGroup = 16;  // CSR entries per group: 8 two-entry loads in flight (16 bytes per lane each)
 constexpr int kMaskWords = kTileQ / 64;
 enum BMode { kBBack = 0, kBFwd = 1 };
 
@@ -169,7 +172,14 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-__device__ __forceinline__ int64_t lane_col() { return (int64_t)(threadIdx.x & 63) * kVec; }
+// The kVec queries of a lane in the gathers' epilogues: lane l < 32 takes
+// queries 8l .. 8l+3 and lane l + 32 takes 8l+4 .. 8l+7, the halves that the
+// two-entry loads leave in each lane (see run_entries).
+__device__ __forceinline__ int lane_q0() {
+    const int l = threadIdx.x & 63;
+    return 8 * (l & 31) + 4 * (l >> 5);
+}
+__device__ __forceinline__ int64_t lane_col() { return (int64_t)lane_q0(); }
 
 // Per-lane epilogues over the lane's kVec queries.
 template <int kMode>
@@ -246,67 +256,79 @@ struct BEpi<kBFwd> {
     }
 };
 
-// Sum over entries [e0, e0 + ne) of w * x[col] for this lane's queries,
+// Sum over entries [e0, e0 + ne) of w * x[col] for every query of the tile,
 // flushing each completed row of [r0, r0 + n_rows) through the epilogue.
 // Row ends are relative to e0; rows may be empty.  r0, n_rows, e0, ne and
-// every row end are the same in all lanes (the caller makes them so): the
-// columns and weights come in groups of kInFlight through scalar loads (the
-// columns a group ahead), the loop's tests are scalar, and the kInFlight
-// gathers of a group are issued without tests.  Slots past the last entry
-// read the entries that follow (the CSR's zero padding at its end) and add
-// them with weight 0.  A stopped query's sums are computed like the others
-// and discarded by the epilogue.
-template <bool kUnit, int kMode, class RowEnd, class RowScale>
+// every row end are the same in all lanes (the caller makes them so).
+//
+// One 16-byte load per lane fetches two entries: lanes 0-31 read the 512-byte
+// transport row of entry k (8 queries each) and lanes 32-63 that of entry
+// k + 1, so a wave issues one load per two entries and keeps each lane's 8
+// partial sums.  At a row end the two halves are added with one lane swap
+// (v_permlane32_swap) per pair of sums, which leaves every lane the totals of
+// its 4 epilogue queries (lane_q0).  When a row ends between the two entries
+// of a load, the lower half is added first, the row flushed, then the upper
+// half added for the next row.  Columns and weights come kEntryGroup at a
+// time through scalar loads; slots past the last entry read the entries that
+// follow (the CSR's zero padding at its end) and add them with weight 0.  A
+// stopped query's sums are computed like the others and discarded by the
+// epilogue.
+template <bool kUnit, int kMode, bool kPaired, class RowEnd, class RowScale>
 __device__ __forceinline__ void run_entries(const int32_t *__restrict__ col, const float *__restrict__ wt,
                                             const uint16_t *__restrict__ xt, int64_t r0, int n_rows, int64_t e0,
                                             int ne, BEpi<kMode> &epi, RowEnd row_end, RowScale row_scale,
                                             QV *acc_out) {
     using Pre = typename BEpi<kMode>::Pre;
     const int lane = threadIdx.x & (kWave - 1);
-    const uint32_t lane_bytes = (uint32_t)lane * (kVec * 2);
-    const char *xb = reinterpret_cast<const char *>(xt);
+    const bool upper = lane >= 32;
+    // Each half picks its entry's column and weight from the scalar pair
+    // with a lane mask (bit operations, so the pair stays in registers).
+    const uint32_t umask = upper ? ~0u : 0u;
+    auto pick = [&](uint32_t lo, uint32_t hi) { return lo ^ ((lo ^ hi) & umask); };
+    const char *xl = reinterpret_cast<const char *>(xt) + (uint32_t)(lane & 31) * 16u;
     int j = 0, rstart = 0;
     int rend = n_rows > 0 ? row_end(0) : INT_MAX;
     Pre pre = epi.pre(r0, n_rows > 0 ? row_scale(0) : 0.0f);
-    QV acc = qv_zero();
-    while (j < n_rows && rend == 0) {
-        epi.full(r0 + j, acc, pre, 0);
-        ++j;
-        if (j < n_rows) {
-            rend = row_end(j);
-            pre = epi.pre(r0 + j, row_scale(j));
-        } else {
-            rend = INT_MAX;
+    float acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
+    // The 4 totals of this lane's epilogue queries.
+    auto totals = [&]() {
+        QV s;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[q]), __float_as_uint(acc[q + 4]),
+                                                             false, false);
+            s.v[q] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
         }
-    }
-    for (int k0 = 0; k0 < ne; k0 += kInFlight) {
-        int32_t cn[kInFlight];
-        float wk[kInFlight];
+        return s;
+    };
+    // Flushes every row that ends at entry position e.
+    auto flush_at = [&](int e) {
+        while (e == rend) {
+            epi.full(r0 + j, totals(), pre, rend - rstart);
 #pragma unroll
-        for (int u = 0; u < kInFlight; ++u) cn[u] = col[e0 + k0 + u];
-#pragma unroll
-        for (int u = 0; u < kInFlight; ++u) wk[u] = kUnit ? 1.0f : wt[e0 + k0 + u];
-        uint2 v[kInFlight];  // packed transport values, unpacked when added
-#pragma unroll
-        for (int u = 0; u < kInFlight; ++u) {
-            const char *row = xb + (size_t)(uint32_t)cn[u] * (kTileQ * 2);
-            v[u] = *reinterpret_cast<const uint2 *>(row + lane_bytes);
+            for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
+            rstart = rend;
+            ++j;
+            if (j < n_rows) {
+                rend = row_end(j);
+                pre = epi.pre(r0 + j, row_scale(j));
+            } else {
+                rend = INT_MAX;
+            }
         }
-        if (ne - k0 < kInFlight) {
-#pragma unroll
-            for (int u = 0; u < kInFlight; ++u)
-                if (u >= ne - k0) wk[u] = 0.0f;
-        }
-#pragma unroll
-        for (int u = 0; u < kInFlight; ++u) {
-            const float xu[kVec] = {__uint_as_float(v[u].x << 16), __uint_as_float(v[u].x & 0xFFFF0000u),
-                                    __uint_as_float(v[u].y << 16), __uint_as_float(v[u].y & 0xFFFF0000u)};
-#pragma unroll
-            for (int q = 0; q < kVec; ++q) acc.v[q] += wk[u] * xu[q];
-            const int e = k0 + u + 1;
+    };
+    flush_at(0);
+    if constexpr (!kPaired) {
+        // One entry per load: each lane reads its 4 epilogue queries (8 bytes)
+        // of the entry's row, and its sums need no combining.
+        const char *xq = reinterpret_cast<const char *>(xt) + (uint32_t)lane_q0() * 2u;
+        QV a4 = qv_zero();
+        auto flush1 = [&](int e) {
             while (e == rend) {
-                epi.full(r0 + j, acc, pre, rend - rstart);
-                acc = qv_zero();
+                epi.full(r0 + j, a4, pre, rend - rstart);
+                a4 = qv_zero();
                 rstart = rend;
                 ++j;
                 if (j < n_rows) {
@@ -316,9 +338,81 @@ __device__ __forceinline__ void run_entries(const int32_t *__restrict__ col, con
                     rend = INT_MAX;
                 }
             }
+        };
+        for (int k0 = 0; k0 < ne; k0 += kEntryGroup) {
+            int32_t cn[kEntryGroup];
+            float wk[kEntryGroup];
+#pragma unroll
+            for (int u = 0; u < kEntryGroup; ++u) cn[u] = col[e0 + k0 + u];
+#pragma unroll
+            for (int u = 0; u < kEntryGroup; ++u) wk[u] = kUnit ? 1.0f : wt[e0 + k0 + u];
+            uint2 v[kEntryGroup];
+#pragma unroll
+            for (int u = 0; u < kEntryGroup; ++u)
+                v[u] = *reinterpret_cast<const uint2 *>(xq + (uint64_t)(uint32_t)cn[u] * (kTileQ * 2));
+            if (ne - k0 < kEntryGroup) {
+#pragma unroll
+                for (int u = 0; u < kEntryGroup; ++u)
+                    if (u >= ne - k0) wk[u] = 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kEntryGroup; ++u) {
+                const float xu[4] = {__uint_as_float(v[u].x << 16), __uint_as_float(v[u].x & 0xFFFF0000u),
+                                     __uint_as_float(v[u].y << 16), __uint_as_float(v[u].y & 0xFFFF0000u)};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a4.v[q] += wk[u] * xu[q];
+                flush1(k0 + u + 1);
+            }
+        }
+        if (acc_out) *acc_out = a4;
+        return;
+    }
+    for (int k0 = 0; k0 < ne; k0 += kEntryGroup) {
+        int32_t cn[kEntryGroup];
+        float wk[kEntryGroup];
+#pragma unroll
+        for (int u = 0; u < kEntryGroup; ++u) cn[u] = col[e0 + k0 + u];
+#pragma unroll
+        for (int u = 0; u < kEntryGroup; ++u) wk[u] = kUnit ? 1.0f : wt[e0 + k0 + u];
+        uint4 v[kEntryGroup / 2];  // packed transport values, unpacked when added
+#pragma unroll
+        for (int p = 0; p < kEntryGroup / 2; ++p) {
+            const uint32_t c = pick((uint32_t)cn[2 * p], (uint32_t)cn[2 * p + 1]);
+            v[p] = *reinterpret_cast<const uint4 *>(xl + (uint64_t)c * (kTileQ * 2));
+        }
+        if (ne - k0 < kEntryGroup) {
+#pragma unroll
+            for (int u = 0; u < kEntryGroup; ++u)
+                if (u >= ne - k0) wk[u] = 0.0f;
+        }
+#pragma unroll
+        for (int p = 0; p < kEntryGroup / 2; ++p) {
+            const uint32_t b[4] = {v[p].x, v[p].y, v[p].z, v[p].w};
+            float x[8];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                x[2 * h] = __uint_as_float(b[h] << 16);
+                x[2 * h + 1] = __uint_as_float(b[h] & 0xFFFF0000u);
+            }
+            const int e_lo = k0 + 2 * p + 1;
+            if (rend != e_lo) {
+                // Both entries belong to the current row.
+                const float w = __uint_as_float(pick(__float_as_uint(wk[2 * p]), __float_as_uint(wk[2 * p + 1])));
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[q] += w * x[q];
+            } else {
+                const float wl = __uint_as_float(pick(__float_as_uint(wk[2 * p]), 0u));
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[q] += wl * x[q];
+                flush_at(e_lo);
+                const float wu = __uint_as_float(pick(0u, __float_as_uint(wk[2 * p + 1])));
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[q] += wu * x[q];
+            }
+            flush_at(e_lo + 1);
         }
     }
-    if (acc_out) *acc_out = acc;
+    if (acc_out) *acc_out = totals();
 }
 
 template <int kMode>
@@ -335,7 +429,7 @@ __device__ __forceinline__ BEpi<kMode> make_bepi(const BArgs &a, int t, const QV
     }
     e.theta = theta;
     if constexpr (kMode == kBFwd) {
-        const int q0 = (threadIdx.x & 63) * kVec;
+        const int q0 = lane_q0();
 #pragma unroll
         for (int j = 0; j < kVec; ++j) e.theta_q.v[j] = a.ctl[t].q[q0 + j].theta_q;
     }
@@ -349,7 +443,7 @@ __device__ __forceinline__ BEpi<kMode> make_bepi(const BArgs &a, int t, const QV
 
 __device__ __forceinline__ QV lane_theta(const TileCtl &tc) {
     QV th;
-    const int q0 = (threadIdx.x & 63) * kVec;
+    const int q0 = lane_q0();
 #pragma unroll
     for (int j = 0; j < kVec; ++j) th.v[j] = tc.q[q0 + j].theta;
     return th;
@@ -363,8 +457,8 @@ __device__ __forceinline__ void bflush(const BArgs &a, int t, int j, BEpi<kMode>
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < kVec; ++j) {
-        smx[wid][lane * kVec + j] = epi.mx[j];
-        snp[wid][lane * kVec + j] = epi.np[j];
+        smx[wid][lane_q0() + j] = epi.mx[j];
+        snp[wid][lane_q0() + j] = epi.np[j];
     }
     __syncthreads();
     const int q = threadIdx.x;
@@ -383,7 +477,7 @@ __device__ __forceinline__ void bflush(const BArgs &a, int t, int j, BEpi<kMode>
 }
 
 template <bool kUnit, int kMode>
-__global__ void __launch_bounds__(kBlock) kb_gather(BArgs a, const int32_t *__restrict__ col,
+__global__ void __launch_bounds__(kBlock, 4) kb_gather(BArgs a, const int32_t *__restrict__ col,
                                                     const float *__restrict__ wt) {
     const int t = blockIdx.y, wg = blockIdx.x;
     const TileCtl &tc = a.ctl[t];
@@ -416,7 +510,7 @@ __global__ void __launch_bounds__(kBlock) kb_gather(BArgs a, const int32_t *__re
                 return jj < kWave ? __builtin_amdgcn_readlane(end0, jj) : __builtin_amdgcn_readlane(end1, jj - kWave);
             };
             auto row_scale = [&](int jj) { return jj < kWave ? readlane_f(sc0, jj) : readlane_f(sc1, jj - kWave); };
-            run_entries<kUnit, kMode>(col, wt, xt, r0, n, e0, ne, epi, row_end, row_scale, nullptr);
+            run_entries<kUnit, kMode, kMode == kBFwd>(col, wt, xt, r0, n, e0, ne, epi, row_end, row_scale, nullptr);
         } else {
             const int64_t row = item.row;
             const int64_t rb = uniform64(a.off[row]), re = uniform64(a.off[row + 1]);
@@ -428,7 +522,8 @@ __global__ void __launch_bounds__(kBlock) kb_gather(BArgs a, const int32_t *__re
             auto row_end = [&](int) { return whole ? ne : INT_MAX; };
             auto row_scale = [&](int) { return scale; };
             QV acc;
-            run_entries<kUnit, kMode>(col, wt, xt, row, whole ? 1 : 0, e0, ne, epi, row_end, row_scale, &acc);
+            run_entries<kUnit, kMode, kMode == kBFwd>(col, wt, xt, row, whole ? 1 : 0, e0, ne, epi, row_end, row_scale,
+                                                      &acc);
             if (!whole) qv_store(part + it * kTileQ + lane_col(), acc);
         }
     }
