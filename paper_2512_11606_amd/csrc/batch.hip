@@ -57,7 +57,12 @@ static_assert(kVec == 4 || kVec == 2 || kVec == 1, "kVec must be 1, 2 or 4");
 static_assert(kTileQ <= kBlock, "one workgroup thread per tile query");
 
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kEntryGroup = 16;  // CSR entries per group: 8 two-entry loads in flight (16 bytes per lane each)
+// CSR entries per group of loads issued before the first is used: one entry
+// per 8-byte lane load (back gather), two per 16-byte lane load (forward).
+constexpr int kGroupSingle = 16;
+constexpr int kGroupPair = 16;
+static_assert(kGroupSingle <= kCsrPad + 1 && kGroupPair <= kCsrPad + 1 && kGroupPair % 2 == 0,
+              "a group may read up to group - 1 entries past a row (the CSR padding)");
 constexpr int kMaskWords = kTileQ / 64;
 enum BMode { kBBack = 0, kBFwd = 1 };
 
@@ -268,8 +273,8 @@ struct BEpi<kBFwd> {
 // (v_permlane32_swap) per pair of sums, which leaves every lane the totals of
 // its 4 epilogue queries (lane_q0).  When a row ends between the two entries
 // of a load, the lower half is added first, the row flushed, then the upper
-// half added for the next row.  Columns and weights come kEntryGroup at a
-// time through scalar loads; slots past the last entry read the entries that
+// half added for the next row.  Columns and weights come a group at a time
+// through scalar loads; slots past the last entry read the entries that
 // follow (the CSR's zero padding at its end) and add them with weight 0.  A
 // stopped query's sums are computed like the others and discarded by the
 // epilogue.
@@ -339,24 +344,24 @@ __device__ __forceinline__ void run_entries(const int32_t *__restrict__ col, con
                 }
             }
         };
-        for (int k0 = 0; k0 < ne; k0 += kEntryGroup) {
-            int32_t cn[kEntryGroup];
-            float wk[kEntryGroup];
+        for (int k0 = 0; k0 < ne; k0 += kGroupSingle) {
+            int32_t cn[kGroupSingle];
+            float wk[kGroupSingle];
 #pragma unroll
-            for (int u = 0; u < kEntryGroup; ++u) cn[u] = col[e0 + k0 + u];
+            for (int u = 0; u < kGroupSingle; ++u) cn[u] = col[e0 + k0 + u];
 #pragma unroll
-            for (int u = 0; u < kEntryGroup; ++u) wk[u] = kUnit ? 1.0f : wt[e0 + k0 + u];
-            uint2 v[kEntryGroup];
+            for (int u = 0; u < kGroupSingle; ++u) wk[u] = kUnit ? 1.0f : wt[e0 + k0 + u];
+            uint2 v[kGroupSingle];
 #pragma unroll
-            for (int u = 0; u < kEntryGroup; ++u)
+            for (int u = 0; u < kGroupSingle; ++u)
                 v[u] = *reinterpret_cast<const uint2 *>(xq + (uint64_t)(uint32_t)cn[u] * (kTileQ * 2));
-            if (ne - k0 < kEntryGroup) {
+            if (ne - k0 < kGroupSingle) {
 #pragma unroll
-                for (int u = 0; u < kEntryGroup; ++u)
+                for (int u = 0; u < kGroupSingle; ++u)
                     if (u >= ne - k0) wk[u] = 0.0f;
             }
 #pragma unroll
-            for (int u = 0; u < kEntryGroup; ++u) {
+            for (int u = 0; u < kGroupSingle; ++u) {
                 const float xu[4] = {__uint_as_float(v[u].x << 16), __uint_as_float(v[u].x & 0xFFFF0000u),
                                      __uint_as_float(v[u].y << 16), __uint_as_float(v[u].y & 0xFFFF0000u)};
 #pragma unroll
@@ -367,26 +372,26 @@ __device__ __forceinline__ void run_entries(const int32_t *__restrict__ col, con
         if (acc_out) *acc_out = a4;
         return;
     }
-    for (int k0 = 0; k0 < ne; k0 += kEntryGroup) {
-        int32_t cn[kEntryGroup];
-        float wk[kEntryGroup];
+    for (int k0 = 0; k0 < ne; k0 += kGroupPair) {
+        int32_t cn[kGroupPair];
+        float wk[kGroupPair];
 #pragma unroll
-        for (int u = 0; u < kEntryGroup; ++u) cn[u] = col[e0 + k0 + u];
+        for (int u = 0; u < kGroupPair; ++u) cn[u] = col[e0 + k0 + u];
 #pragma unroll
-        for (int u = 0; u < kEntryGroup; ++u) wk[u] = kUnit ? 1.0f : wt[e0 + k0 + u];
-        uint4 v[kEntryGroup / 2];  // packed transport values, unpacked when added
+        for (int u = 0; u < kGroupPair; ++u) wk[u] = kUnit ? 1.0f : wt[e0 + k0 + u];
+        uint4 v[kGroupPair / 2];  // packed transport values, unpacked when added
 #pragma unroll
-        for (int p = 0; p < kEntryGroup / 2; ++p) {
+        for (int p = 0; p < kGroupPair / 2; ++p) {
             const uint32_t c = pick((uint32_t)cn[2 * p], (uint32_t)cn[2 * p + 1]);
             v[p] = *reinterpret_cast<const uint4 *>(xl + (uint64_t)c * (kTileQ * 2));
         }
-        if (ne - k0 < kEntryGroup) {
+        if (ne - k0 < kGroupPair) {
 #pragma unroll
-            for (int u = 0; u < kEntryGroup; ++u)
+            for (int u = 0; u < kGroupPair; ++u)
                 if (u >= ne - k0) wk[u] = 0.0f;
         }
 #pragma unroll
-        for (int p = 0; p < kEntryGroup / 2; ++p) {
+        for (int p = 0; p < kGroupPair / 2; ++p) {
             const uint32_t b[4] = {v[p].x, v[p].y, v[p].z, v[p].w};
             float x[8];
 #pragma unroll

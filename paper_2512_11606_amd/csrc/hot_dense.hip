@@ -19,7 +19,9 @@
 // n + 32 (k / 8), element k % 8; C[m][n] at lane n + 32 ((m / 4) % 2),
 // element 4 (m / 8) + m % 4.  The weights are stored in that A order
 // (1 KB per 32 rows x 16 columns, one 16-byte load per lane); the transport
-// rows are staged through LDS transposed ([query][u], 16 bytes per lane read).
+// rows are staged through LDS transposed ([query][u], 16 bytes per lane read;
+// each thread transposes a 4-row x 8-query block in registers and writes 8
+// bytes per query).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -112,39 +114,39 @@ __global__ void __launch_bounds__(kDenseThreads) kb_hot_dense(DenseArgs a) {
     if (tc.all_done) return;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6;
     const uint16_t *qt = a.q + t * a.q_stride;
-    // Staging role: U row ul of each stage, query groups q8 = tid / 32 + 8 i
-    // (queries 8 q8 .. 8 q8 + 7), i = 0..3; which of those queries still run.
-    const int ul = tid % kStageU;
-    uint32_t live = 0;  // bit 8 i + j: query 8 (tid / 32 + 8 i) + j runs
+    // Staging role: U rows 4 ub .. 4 ub + 3 of each stage and queries
+    // 8 qg .. 8 qg + 7.  A thread loads its four 16-byte row pieces, zeroes
+    // the stopped queries, transposes the 4 x 8 block in registers and
+    // writes 8 bytes (4 U rows) per query.
+    const int ub = tid & 7, qg = tid >> 3;
+    u32x4 lm;  // 16-bit lane masks of the thread's 8 queries: all ones where the query runs
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-            if (tc.q[8 * (tid / 32 + 8 * i) + j].theta != FLT_MAX) live |= 1u << (8 * i + j);
+    for (int d = 0; d < 4; ++d)
+        lm[d] = (tc.q[8 * qg + 2 * d].theta != FLT_MAX ? 0x0000FFFFu : 0u) |
+                (tc.q[8 * qg + 2 * d + 1].theta != FLT_MAX ? 0xFFFF0000u : 0u);
     const int64_t u_begin = (int64_t)c * a.kc;
     const int n_stage = (int)(a.kc / kStageU);
     const int64_t ks_begin = u_begin / kKS;
     u32x4 stg[4];
     auto load_stage = [&](int st) {
-        const int64_t u = u_begin + (int64_t)st * kStageU + ul;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int q8 = tid / 32 + 8 * i;
-            stg[i] = u < a.n_u ? __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(qt + u * kTileQ + 8 * q8))
+            const int64_t u = u_begin + (int64_t)st * kStageU + 4 * ub + i;
+            stg[i] = u < a.n_u ? __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(qt + u * kTileQ + 8 * qg))
                                : u32x4{0u, 0u, 0u, 0u};
         }
     };
     auto write_stage = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int q8 = tid / 32 + 8 * i;
+        for (int i = 0; i < 4; ++i) stg[i] &= lm;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const uint32_t word = stg[i][j / 2];
-                uint16_t v = (uint16_t)((j & 1) ? (word >> 16) : (word & 0xFFFFu));
-                if (!((live >> (8 * i + j)) & 1u)) v = 0;
-                qs[buf][(8 * q8 + j) * kQsStride + ul] = v;
-            }
+        for (int q = 0; q < 8; ++q) {
+            // query q is bytes 0-1 (q even) or 2-3 (q odd) of word q / 2 of
+            // each row piece; lo packs rows 0 and 1, hi rows 2 and 3
+            const uint32_t sel = (q & 1) ? 0x07060302u : 0x05040100u;
+            const uint32_t lo = __builtin_amdgcn_perm(stg[1][q / 2], stg[0][q / 2], sel);
+            const uint32_t hi = __builtin_amdgcn_perm(stg[3][q / 2], stg[2][q / 2], sel);
+            *reinterpret_cast<uint2 *>(&qs[buf][(8 * qg + q) * kQsStride + 4 * ub]) = make_uint2(lo, hi);
         }
     };
     bf16x8 af[2][3], an[2][3];
