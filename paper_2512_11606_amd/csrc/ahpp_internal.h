@@ -51,6 +51,11 @@ struct DevCsr {
     float *w = nullptr;             // nnz, then kCsrPad zeros (nullptr when every weight is 1)
     WorkItem *items = nullptr;      // n_items
     int64_t n_items = 0;
+    // Per item, so a wave need not read the offsets before its entries: the
+    // first entry, and the entry count (a pack of rows, or a whole row) or,
+    // for a chunk of a row cut into several, minus its entry count.
+    int64_t *item_e0 = nullptr;     // n_items
+    int32_t *item_ne = nullptr;     // n_items
     SplitRow *split = nullptr;      // rows cut into several chunks
     int64_t n_split = 0;
     int32_t max_row_len = 0;

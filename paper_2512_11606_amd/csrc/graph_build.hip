@@ -421,6 +421,26 @@ void build_csr(Graph &g, DevCsr &c, int64_t n_rows, uint32_t *key, int32_t *col,
     if ((int64_t)items.size() > (int64_t)INT32_MAX) throw Failure{-1, "ahpp_graph_load: schedule exceeds int32 items"};
     c.n_items = (int64_t)items.size();
     c.n_split = (int64_t)split.size();
+    std::vector<int64_t> ie0(items.size());
+    std::vector<int32_t> ine(items.size());
+    for (size_t i = 0; i < items.size(); ++i) {
+        const WorkItem &it = items[i];
+        if (it.n > 0) {
+            ie0[i] = off[it.row];
+            ine[i] = (int32_t)(off[it.row + it.n] - off[it.row]);
+        } else {
+            const int64_t rb = off[it.row], len = off[it.row + 1] - rb, first = (int64_t)(-it.n) * kItemEdges;
+            ie0[i] = rb + first;
+            const int32_t ne = (int32_t)std::min<int64_t>(len - first, kItemEdges);
+            ine[i] = len <= kItemEdges ? ne : -ne;
+        }
+    }
+    c.item_e0 = (int64_t *)dev_alloc(g, std::max<size_t>(items.size(), 1) * 8, "schedule");
+    c.item_ne = (int32_t *)dev_alloc(g, std::max<size_t>(items.size(), 1) * 4, "schedule");
+    if (!items.empty()) {
+        check_hip(hipMemcpyAsync(c.item_e0, ie0.data(), ie0.size() * 8, hipMemcpyHostToDevice, s), "schedule H2D");
+        check_hip(hipMemcpyAsync(c.item_ne, ine.data(), ine.size() * 4, hipMemcpyHostToDevice, s), "schedule H2D");
+    }
     c.items = (WorkItem *)dev_alloc(g, std::max<size_t>(items.size(), 1) * sizeof(WorkItem), "schedule");
     c.split = (SplitRow *)dev_alloc(g, std::max<size_t>(split.size(), 1) * sizeof(SplitRow), "split rows");
     if (!items.empty())
@@ -684,7 +704,7 @@ void build_graph(Graph &g, const int32_t *eu, const int32_t *ev, const float *ew
 }
 
 static void free_csr(DevCsr &c) {
-    dfree(c.off); dfree(c.col); dfree(c.w); dfree(c.items); dfree(c.split);
+    dfree(c.off); dfree(c.col); dfree(c.w); dfree(c.items); dfree(c.split); dfree(c.item_e0); dfree(c.item_ne);
     c = DevCsr{};
 }
 

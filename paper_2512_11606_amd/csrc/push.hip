@@ -51,9 +51,13 @@ struct CsrView {
     int64_t n_items;
     const SplitRow *__restrict__ split;
     int64_t n_split;
+    const int64_t *__restrict__ item_e0;
+    const int32_t *__restrict__ item_ne;
 };
 
-CsrView view(const DevCsr &c) { return CsrView{c.off, c.col, c.w, c.items, c.n_items, c.split, c.n_split}; }
+CsrView view(const DevCsr &c) {
+    return CsrView{c.off, c.col, c.w, c.items, c.n_items, c.split, c.n_split, c.item_e0, c.item_ne};
+}
 
 struct GatherArgs {
     CsrView c;
@@ -211,15 +215,30 @@ __device__ __forceinline__ void spmv_items(const GatherArgs &a, float theta, flo
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wave0 = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
-    WorkItem next = wave0 < c.n_items ? c.items[wave0] : WorkItem{0, 0};
+    // The next item's descriptor, first entry and count are read a step
+    // ahead, so an item's entry loads wait on no other load.
+    WorkItem next = WorkItem{0, 0};
+    int64_t next_e0 = 0;
+    int32_t next_ne = 0;
+    if (wave0 < c.n_items) {
+        next = c.items[wave0];
+        next_e0 = c.item_e0[wave0];
+        next_ne = c.item_ne[wave0];
+    }
     for (int64_t it = wave0; it < c.n_items; it += stride) {
         const WorkItem item = next;
-        if (it + stride < c.n_items) next = c.items[it + stride];
+        const int64_t item_e0 = next_e0;
+        const int32_t item_ne = next_ne;
+        if (it + stride < c.n_items) {
+            next = c.items[it + stride];
+            next_e0 = c.item_e0[it + stride];
+            next_ne = c.item_ne[it + stride];
+        }
         float t[kPerLane];
         if (item.n > 0) {
             const int64_t r0 = item.row;
-            const int64_t e0 = c.off[r0];
-            const int ne = (int)(c.off[r0 + item.n] - e0);
+            const int64_t e0 = item_e0;
+            const int ne = item_ne;
             int64_t rb[kRowsPerLane], re[kRowsPerLane];
             float2 pre[kRowsPerLane];
 #pragma unroll
@@ -254,10 +273,9 @@ __device__ __forceinline__ void spmv_items(const GatherArgs &a, float theta, flo
             wave_lds_sync();
         } else {
             const int64_t row = item.row;
-            const int64_t rb = c.off[row], re = c.off[row + 1];
-            const int64_t e0 = rb + (int64_t)(-item.n) * kItemEdges;
-            const int ne = (int)(re - e0 < kItemEdges ? re - e0 : kItemEdges);
-            const bool whole = re - rb <= kItemEdges;
+            const int64_t e0 = item_e0;
+            const int ne = item_ne < 0 ? -item_ne : item_ne;
+            const bool whole = item_ne > 0;  // the row is this one item
             const float2 pre = whole ? epi.pre(row) : make_float2(0.0f, 0.0f);
             load_terms<kUnit, kThr, kNode>(c, a.x, e0, ne, theta, a.deg, r_max_of(a), t);
             float s = 0.0f;
@@ -265,7 +283,7 @@ __device__ __forceinline__ void spmv_items(const GatherArgs &a, float theta, flo
             for (int k = 0; k < kPerLane; ++k) s += t[k];
             s = wave_sum(s);
             if (lane == 0) {
-                if (whole) epi.full(row, s, pre, re - rb);
+                if (whole) epi.full(row, s, pre, ne);
                 else a.part[it] = s;
             }
         }
