@@ -53,7 +53,7 @@ namespace ahpp {
 
 namespace {
 
-static_assert(kVec == 4 || kVec == 2 || kVec == 1, "kVec must be 1, 2 or 4");
+static_assert(kVec == 4, "the gathers move 4 bf16 values (8 bytes) per lane and entry");
 static_assert(kTileQ <= kBlock, "one workgroup thread per tile query");
 
 constexpr int kWavesPerBlock = kBlock / kWave;
@@ -112,14 +112,6 @@ __device__ __forceinline__ void qv_store(float *p, const QV &a) {
 constexpr float kCarryBound = 0.0078125f;  // 2^-7: carry < kCarryBound * rz16(value)
 
 __device__ __forceinline__ float rz16(float v) { return __uint_as_float(__float_as_uint(v) & 0xFFFF0000u); }
-
-// Stores rz16 of the four values (the top 16 bits of each).
-__device__ __forceinline__ void qh_store(uint16_t *p, const QV &a) {
-    uint2 t;
-    t.x = (__float_as_uint(a.v[0]) >> 16) | (__float_as_uint(a.v[1]) & 0xFFFF0000u);
-    t.y = (__float_as_uint(a.v[2]) >> 16) | (__float_as_uint(a.v[3]) & 0xFFFF0000u);
-    *reinterpret_cast<uint2 *>(p) = t;
-}
 
 // Streaming (non-temporal) access to per-row state that no other wave of
 // the launch reads again, so it does not push gathered rows out of L2
@@ -459,11 +451,11 @@ template <int kMode>
 __device__ __forceinline__ void bflush(const BArgs &a, int t, int j, BEpi<kMode> &epi) {
     __shared__ float smx[kWavesPerBlock][kTileQ];
     __shared__ unsigned long long snp[kWavesPerBlock][kTileQ];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int q0 = lane_q0(), wid = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < kVec; ++j) {
-        smx[wid][lane_q0() + j] = epi.mx[j];
-        snp[wid][lane_q0() + j] = epi.np[j];
+        smx[wid][q0 + j] = epi.mx[j];
+        snp[wid][q0 + j] = epi.np[j];
     }
     __syncthreads();
     const int q = threadIdx.x;
