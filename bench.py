@@ -297,13 +297,15 @@ def prep_cache_leg(ahpp, synth, name="large20m"):
 
 
 SWEEP_FRACS = (0.3, 0.6, 0.9, 1.3)   # offered load as a fraction of the measured capacity
+LOW_LOAD_QPS, LOW_LOAD_QUERIES = 2.0, 40   # a low arrival rate, served without and with solo queries
 
 
 def serve_sweep_leg(ahpp, synth, args):
     """Continuous batching on the 5M/2M/100M serving graph: capacity from a
     closed burst (every query queued at once), then Poisson arrivals at
     fractions of it, the last one past it; per rate p50 / p99 latency from
-    arrival to top-k on the host."""
+    arrival to top-k on the host.  Then a low rate, batched and with lone
+    queries answered on the single-query engine."""
     from paper_2512_11606_amd import serve
     t_gen = time.perf_counter()
     g = synth.make_graph(args.serve_graph)
@@ -311,7 +313,7 @@ def serve_sweep_leg(ahpp, synth, args):
     load_s = time.perf_counter() - t_gen
     n = args.serve_queries
     n_burst = 2 * args.serve_slots
-    total = n_burst + n * len(SWEEP_FRACS)
+    total = n_burst + n * len(SWEEP_FRACS) + 2 * LOW_LOAD_QUERIES
     sources = synth.degree_queries(g, total, 2003)
     pick = (synth.CounterRNG(2003, "serve_eps").uniform(total) * len(SERVE_EPS)).astype(int)
     eps = [SERVE_EPS[min(i, len(SERVE_EPS) - 1)] for i in pick]
@@ -336,6 +338,21 @@ def serve_sweep_leg(ahpp, synth, args):
             summ["converged"] = sum(1 for r in res.values() if r["stats"]["converged"] == 1)
             summ["load_fraction"] = frac
             out["rates"].append({kk: (round(v, 2) if isinstance(v, float) else v) for kk, v in summ.items()})
+        # Low load: the same arrivals batched in the tiles, then with lone
+        # queries on the single-query engine (ahpp_server_set_solo).
+        out["low_load"] = []
+        for j, solo in enumerate((0, 4)):
+            lo = n_burst + len(SWEEP_FRACS) * n + j * LOW_LOAD_QUERIES
+            srv.set_solo(solo)
+            print(f"[bench] serving {LOW_LOAD_QUERIES} queries at {LOW_LOAD_QPS} q/s, solo_max {solo}",
+                  file=sys.stderr, flush=True)
+            summ, res = serve.run(srv, sources[lo:lo + LOW_LOAD_QUERIES], eps[lo:lo + LOW_LOAD_QUERIES],
+                                  rate_qps=LOW_LOAD_QPS, rounds_per_step=args.serve_rounds, seed=3100 + j,
+                                  max_wall_s=300.0)
+            summ["converged"] = sum(1 for r in res.values() if r["stats"]["converged"] == 1)
+            summ["solo_max"] = solo
+            out["low_load"].append({kk: (round(v, 2) if isinstance(v, float) else v) for kk, v in summ.items()})
+        srv.set_solo(0)
     finally:
         srv.close()
         dg.free()

@@ -270,6 +270,21 @@ ahpp_status_t ahpp_server_results(ahpp_server_t *s, int32_t max_n, int64_t *tags
 ahpp_status_t ahpp_server_info(const ahpp_server_t *s, int32_t *slots, int32_t *running, int32_t *queued,
                                int32_t *ready);
 
+/* Low load on the single-query engine.  A tile round moves the state of all
+ * 256 lanes of a tile, however few queries run in it, so at low load a
+ * query's latency is its rounds times a full tile round.  With solo_max > 0,
+ * a step that finds 1..solo_max queries queued and at most solo_max running
+ * in the tiles first answers the queued ones one after another with
+ * ahpp_query's engine (the same eps guarantee, Theorem 2; results are
+ * ahpp_query's, bit for bit), then runs its rounds for the queries in the
+ * tiles; otherwise the queue is admitted into the tiles as before, so under
+ * load the server batches.  Such a step uses the graph's single-query buffers, so it must not
+ * overlap an ahpp_query, ahpp_query_schedule or ahpp_query_mc call on the
+ * same graph.
+ *   solo_max: 0 (the default: always batch) .. 256.
+ * Errors: INVALID_ARG. */
+ahpp_status_t ahpp_server_set_solo(ahpp_server_t *s, int32_t solo_max);
+
 /* Monte Carlo estimate of one AHPP row (Section 3.1; Lemma 1): n_walks
  * alpha-hidden walks from `source`; pi(u, x) ~ (walks that stop at x) /
  * n_walks.  Each walk stops at its node with probability alpha, else moves by

@@ -24,7 +24,7 @@ EXPORTED = ("ahpp_graph_load", "ahpp_graph_info", "ahpp_graph_key", "ahpp_graph_
             "ahpp_query_schedule",
             "ahpp_query_batch", "ahpp_topk",
             "ahpp_server_create", "ahpp_server_free", "ahpp_server_submit", "ahpp_server_step",
-            "ahpp_server_results", "ahpp_server_info", "ahpp_graph_tune", "ahpp_query_mc", "ahpp_profile_enable",
+            "ahpp_server_results", "ahpp_server_info", "ahpp_server_set_solo", "ahpp_graph_tune", "ahpp_query_mc", "ahpp_profile_enable",
             "ahpp_profile_read", "ahpp_last_error")
 
 # Kernel kinds of ahpp_profile_read.
@@ -110,6 +110,8 @@ def load_library(path: str = LIB_PATH):
     lib.ahpp_server_results.argtypes = [P, i32, P, P, P, P, P, P, P, P]
     lib.ahpp_server_info.restype = ctypes.c_int
     lib.ahpp_server_info.argtypes = [P, P, P, P, P]
+    lib.ahpp_server_set_solo.restype = ctypes.c_int
+    lib.ahpp_server_set_solo.argtypes = [P, i32]
     lib.ahpp_query_schedule.restype = ctypes.c_int
     lib.ahpp_query_schedule.argtypes = [P, i32, dbl, i32, i32, P, P, i32, P, P, P, P, P]
     lib.ahpp_query_mc.restype = ctypes.c_int
@@ -436,6 +438,11 @@ class Server:
         n = ctypes.c_int32(0)
         _check(load_library().ahpp_server_step(self._h, int(rounds), ctypes.byref(n), _stream(self.g.device, stream)))
         return int(n.value)
+
+    def set_solo(self, solo_max: int) -> None:
+        """Lone queries on the single-query engine when no query runs in the
+        tiles and at most solo_max wait (0: off; see ahpp_server_set_solo)."""
+        _check(load_library().ahpp_server_set_solo(self._h, int(solo_max)))
 
     def info(self) -> dict:
         v = [ctypes.c_int32(0) for _ in range(4)]

@@ -426,6 +426,7 @@ class Server {
     int results(int max_n, int64_t *tags, int32_t *topk_idx, float *topk_val, int32_t *topk_n, ahpp_stats_t *stats,
                 float *pi_out, hipStream_t s);
     void info(int32_t *slots, int32_t *running, int32_t *queued, int32_t *ready) const;
+    void set_solo(int32_t solo_max) { solo_max_ = solo_max; }
     Graph &graph() { return g_; }
 
   private:
@@ -447,10 +448,13 @@ class Server {
         ahpp_stats_t st;
         float *d_pi;
     };
+    // Answers every queued query on the single-query path (see step).
+    void serve_solo(double t_step, hipStream_t s);
     Graph &g_;
     BatchState b_;
     int32_t k_, max_iters_;
     bool keep_pi_;
+    int32_t solo_max_ = 0;
     std::vector<Lane> lanes_;
     std::deque<Pending> queue_;
     std::deque<Result> ready_;

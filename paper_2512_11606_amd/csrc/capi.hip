@@ -382,6 +382,15 @@ ahpp_status_t ahpp_server_results(ahpp_server_t *srv, int32_t max_n, int64_t *ta
     });
 }
 
+ahpp_status_t ahpp_server_set_solo(ahpp_server_t *srv, int32_t solo_max) {
+    g_last_error.clear();
+    if (!srv || !srv->impl) return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_set_solo: NULL server");
+    if (solo_max < 0 || solo_max > kTileQ)
+        return fail(AHPP_ERR_INVALID_ARG, "ahpp_server_set_solo: solo_max must be in [0, 256]");
+    srv->impl->set_solo(solo_max);
+    return AHPP_OK;
+}
+
 ahpp_status_t ahpp_server_info(const ahpp_server_t *srv, int32_t *slots, int32_t *running, int32_t *queued,
                                int32_t *ready) {
     g_last_error.clear();

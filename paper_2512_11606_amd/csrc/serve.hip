@@ -80,8 +80,45 @@ Server::~Server() {
 
 void Server::submit(int64_t tag, int32_t source, double eps) { queue_.push_back(Pending{tag, source, eps}); }
 
+void Server::serve_solo(double t_step, hipStream_t s) {
+    while (!queue_.empty()) {
+        const Pending p = queue_.front();
+        queue_.pop_front();
+        Result r;
+        r.tag = p.tag;
+        r.d_pi = nullptr;
+        if (keep_pi_) check_hip(hipMalloc((void **)&r.d_pi, (size_t)g_.n_u * 4), "kept vector");
+        ahpp_stats_t st;
+        run_query(g_, g_.q, true, p.source, p.eps, 0, max_iters_, r.d_pi, nullptr, k_, d_idx_, d_val_, d_n_, &st, s);
+        int32_t n = 0;
+        check_hip(hipMemcpyAsync(&n, d_n_, 4, hipMemcpyDeviceToHost, s), "collect");
+        check_hip(hipStreamSynchronize(s), "collect");
+        r.idx.resize((size_t)n);
+        r.val.resize((size_t)n);
+        if (n > 0) {
+            check_hip(hipMemcpyAsync(r.idx.data(), d_idx_, (size_t)n * 4, hipMemcpyDeviceToHost, s), "collect");
+            check_hip(hipMemcpyAsync(r.val.data(), d_val_, (size_t)n * 4, hipMemcpyDeviceToHost, s), "collect");
+            check_hip(hipStreamSynchronize(s), "collect");
+        }
+        st.ms = (float)(now_ms() - t_step);
+        r.st = st;
+        ready_.push_back(std::move(r));
+    }
+}
+
 int Server::step(int rounds, hipStream_t s) {
     const double t_step = now_ms();
+    // 0. Low load (at most solo_max queries queued and at most solo_max in
+    // the tiles): a tile round moves every lane's bytes however few queries
+    // run in it, so the queued ones are answered one after another on the
+    // single-query path (the kernels of ahpp_query: the same guarantee, a
+    // fraction of a tile round's time per round); queries already in the
+    // tiles run on.  Otherwise the queue is admitted into the tiles, so under
+    // load the server batches as before.
+    if (solo_max_ > 0 && !queue_.empty() && (int64_t)queue_.size() <= solo_max_) {
+        const int64_t in_tiles = std::count_if(lanes_.begin(), lanes_.end(), [](const Lane &l) { return l.busy; });
+        if (in_tiles <= solo_max_) serve_solo(t_step, s);
+    }
     // 1. Admission into free lanes.
     std::vector<AdmitReq> reqs;
     for (size_t i = 0; i < lanes_.size() && !queue_.empty(); ++i) {

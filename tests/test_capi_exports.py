@@ -34,7 +34,8 @@ def test_every_declared_symbol_is_exported(lib):
     bound_by_methods = {"ahpp_graph_free": ahpp.Graph.free, "ahpp_last_error": ahpp._check,
                         "ahpp_server_create": ahpp.Server.__init__, "ahpp_server_free": ahpp.Server.close,
                         "ahpp_server_submit": ahpp.Server.submit, "ahpp_server_step": ahpp.Server.step,
-                        "ahpp_server_results": ahpp.Server.results, "ahpp_server_info": ahpp.Server.info}
+                        "ahpp_server_results": ahpp.Server.results, "ahpp_server_info": ahpp.Server.info,
+                        "ahpp_server_set_solo": ahpp.Server.set_solo}
     for n in names:
         assert hasattr(lib, n), n
         assert getattr(ahpp, n, None) is not None or n in bound_by_methods, n

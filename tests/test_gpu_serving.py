@@ -169,3 +169,76 @@ def test_server_graph_replay_matches_plain_launches(env, monkeypatch):
         for t in range(srcs.size):
             assert torch.equal(replay[t]["pi"], plain[t]["pi"]), (rep, t)
             assert replay[t]["topk_idx"].tolist() == plain[t]["topk_idx"].tolist()
+
+
+def test_solo_lone_queries_are_ahpp_query(env):
+    """With solo mode on, a step that finds at most solo_max queries waiting
+    and at most solo_max in the tiles answers the waiting ones on the
+    single-query engine: each such result is ahpp_query's bit for bit and
+    meets Theorem 2 against the exact series; a longer queue, or a short one
+    behind more than solo_max running queries, is batched as before."""
+    g, dg, ahpp, torch = env
+    srv = ahpp.Server(dg, k=25, max_device_bytes=1 << 30, keep_pi=True, max_slots=256)
+    for bad in (-1, 257):
+        with pytest.raises(ahpp.AhppError) as e:
+            srv.set_solo(bad)
+        assert e.value.status == ahpp.ERR_INVALID_ARG
+    srv.set_solo(2)
+    og = O.OracleGraph.from_graph(g)
+    srcs = synth.degree_queries(g, 8, 44)
+    eps = [1e-6, 1e-7, 1e-5, 1e-8, 1e-6, 1e-7, 1e-6, 1e-7]
+
+    def check(r, s, e, bitwise):
+        pi = r["pi"].cpu().numpy().astype(np.float64)
+        exact, _ = og.power_series(s)
+        chk = O.check_query(exact, pi, e, tol=TOL, k=25, source=s, topk_ids=r["topk_idx"])
+        assert chk.ok, (s, e, chk.detail)
+        assert r["stats"]["converged"] == 1
+        alone = ahpp.ahpp_query(dg, s, e, k=25)
+        a_pi = alone.pi.cpu().numpy().astype(np.float64)
+        n = int(alone.topk_n.cpu()[0])
+        if bitwise:
+            assert np.array_equal(a_pi, pi), (s, e)
+            assert np.array_equal(alone.topk_idx.cpu().numpy()[:n], r["topk_idx"]), (s, e)
+            assert alone.stats[0]["iters"] == r["stats"]["iters"]
+        else:
+            assert np.abs(a_pi - pi).max() <= e + TOL, (s, e)
+
+    # One, then two lone queries: answered in the step that finds them.
+    for group in ((0,), (1, 2)):
+        for i in group:
+            srv.submit(i, int(srcs[i]), eps[i])
+        _say("solo step with", len(group), "queued")
+        assert srv.step(4) == len(group)
+        assert srv.info()["running"] == 0
+        for r in srv.results(want_pi=True):
+            i = r["tag"]
+            check(r, int(srcs[i]), eps[i], bitwise=True)
+    # Three waiting (above solo_max): batched in the tiles.
+    for i in (3, 4, 5):
+        srv.submit(i, int(srcs[i]), eps[i])
+    srv.step(1)
+    assert srv.info()["running"] == 3
+    # A lone arrival behind 3 running queries: batched with solo_max 2,
+    # answered alone in the next step with solo_max 4.
+    srv.submit(6, int(srcs[6]), eps[6])
+    srv.step(1)
+    assert srv.info()["running"] == 4 and not srv.results()
+    srv.submit(7, int(srcs[7]), eps[7])
+    srv.set_solo(4)
+    srv.step(1)
+    got = srv.results(want_pi=True)
+    assert [r["tag"] for r in got] == [7] and srv.info()["running"] == 4
+    check(got[0], int(srcs[7]), eps[7], bitwise=True)
+    done = {}
+    guard = 0
+    while len(done) < 4:
+        srv.step(4)
+        for r in srv.results(want_pi=True):
+            done[r["tag"]] = r
+        guard += 1
+        assert guard < 10000
+    assert sorted(done) == [3, 4, 5, 6]
+    for i, r in done.items():
+        check(r, int(srcs[i]), eps[i], bitwise=False)
+    srv.close()
