@@ -87,21 +87,29 @@ void Server::serve_solo(double t_step, hipStream_t s) {
         Result r;
         r.tag = p.tag;
         r.d_pi = nullptr;
-        if (keep_pi_) check_hip(hipMalloc((void **)&r.d_pi, (size_t)g_.n_u * 4), "kept vector");
-        ahpp_stats_t st;
-        run_query(g_, g_.q, true, p.source, p.eps, 0, max_iters_, r.d_pi, nullptr, k_, d_idx_, d_val_, d_n_, &st, s);
-        int32_t n = 0;
-        check_hip(hipMemcpyAsync(&n, d_n_, 4, hipMemcpyDeviceToHost, s), "collect");
-        check_hip(hipStreamSynchronize(s), "collect");
-        r.idx.resize((size_t)n);
-        r.val.resize((size_t)n);
-        if (n > 0) {
-            check_hip(hipMemcpyAsync(r.idx.data(), d_idx_, (size_t)n * 4, hipMemcpyDeviceToHost, s), "collect");
-            check_hip(hipMemcpyAsync(r.val.data(), d_val_, (size_t)n * 4, hipMemcpyDeviceToHost, s), "collect");
+        try {
+            if (keep_pi_) check_hip(hipMalloc((void **)&r.d_pi, (size_t)g_.n_u * 4), "kept vector");
+            ahpp_stats_t st;
+            run_query(g_, g_.q, true, p.source, p.eps, 0, max_iters_, r.d_pi, nullptr, k_, d_idx_, d_val_, d_n_, &st,
+                      s);
+            int32_t n = 0;
+            check_hip(hipMemcpyAsync(&n, d_n_, 4, hipMemcpyDeviceToHost, s), "collect");
             check_hip(hipStreamSynchronize(s), "collect");
+            r.idx.resize((size_t)n);
+            r.val.resize((size_t)n);
+            if (n > 0) {
+                check_hip(hipMemcpyAsync(r.idx.data(), d_idx_, (size_t)n * 4, hipMemcpyDeviceToHost, s), "collect");
+                check_hip(hipMemcpyAsync(r.val.data(), d_val_, (size_t)n * 4, hipMemcpyDeviceToHost, s), "collect");
+                check_hip(hipStreamSynchronize(s), "collect");
+            }
+            st.ms = (float)(now_ms() - t_step);
+            r.st = st;
+        } catch (...) {
+            // The query goes back to the head of the queue; its vector is freed.
+            dfree(r.d_pi);
+            queue_.push_front(p);
+            throw;
         }
-        st.ms = (float)(now_ms() - t_step);
-        r.st = st;
         ready_.push_back(std::move(r));
     }
 }
