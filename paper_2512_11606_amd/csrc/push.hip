@@ -451,10 +451,12 @@ Rule make_rule(const Graph &g) {
     return r;
 }
 
-// Workgroups of the single-query gathers: twice the batched kernels' cap
-// (measured: 2-3% shorter gathers on m1, each wave with fewer items of a
-// latency-bound chain).  Their partials are sized for it.
-inline int single_cap(const Graph &g) { return 2 * g.grid_cap; }
+// Workgroups of the single-query gathers: four times the batched kernels'
+// cap, so each wave has fewer items of its latency-bound chain (m1, per
+// launch of the back / forward gather: 176 / 153 us at 1x, 172 / 148 at 2x,
+// 166 / 145 at 4x, 172 / 144 at 6x, 173 / 158 at 8x).  Their partials are
+// sized for it.
+inline int single_cap(const Graph &g) { return 4 * g.grid_cap; }
 
 // Launch shapes of one round.
 struct Plan {
