@@ -212,43 +212,47 @@ __global__ void __launch_bounds__(kDenseThreads) kb_hot_dense(DenseArgs a) {
 }  // namespace
 
 namespace {
-// U rows per chunk of a graph (a multiple of kStageU) and the chunk count.
-void dense_shape(int64_t n_u, int64_t *kc, int64_t *n_chunks) {
-    int64_t c = (n_u + kDenseChunks - 1) / kDenseChunks;
-    c = (c + kStageU - 1) / kStageU * kStageU;
-    *kc = std::max<int64_t>(c, kStageU);
-    *n_chunks = (n_u + *kc - 1) / *kc;
+// K-steps of the weight block: U padded to whole stages plus kStageU rows
+// per possible chunk, so that every chunking below stays inside it (a
+// chunking into at most kDenseWorkgroups chunks pads U by under kStageU rows
+// per chunk); the padding holds zero weights.
+int64_t dense_block_ks(int64_t n_u) {
+    return ((n_u + kStageU - 1) / kStageU + kDenseWorkgroups) * kStageU / kKS;
 }
 }  // namespace
 
+void dense_chunking(int64_t n_u, int nt, int64_t *kc, int64_t *n_chunks) {
+    const int64_t want = std::max<int64_t>(1, (kDenseWorkgroups + nt - 1) / std::max(nt, 1));
+    int64_t c = (n_u + want - 1) / want;
+    c = (c + kStageU - 1) / kStageU * kStageU;
+    *kc = std::max<int64_t>(c, kStageU);
+    *n_chunks = std::max<int64_t>(1, (n_u + *kc - 1) / *kc);
+}
+
 size_t hot_dense_bytes(const Graph &g) {
-    int64_t kc, n_chunks;
-    dense_shape(g.n_u, &kc, &n_chunks);
-    return (size_t)3 * (size_t)(n_chunks * kc / kKS) * kHBlocks * kFragElems * 2;
+    return (size_t)3 * (size_t)dense_block_ks(g.n_u) * kHBlocks * kFragElems * 2;
 }
 
 void build_hot_dense(Graph &g, hipStream_t s) {
     HotSet &h = g.hot;
     if (h.n <= 0 || g.n_u <= 0) return;
-    int64_t kc, n_chunks;
-    dense_shape(g.n_u, &kc, &n_chunks);
-    const int64_t n_ks = n_chunks * kc / kKS;
+    const int64_t n_ks = dense_block_ks(g.n_u);
     const size_t bytes = hot_dense_bytes(g);
     h.w3 = (uint16_t *)dev_alloc(g, bytes, "dense hot weights");
     check_hip(hipMemsetAsync(h.w3, 0, bytes, s), "dense hot weights");
     hipLaunchKernelGGL(k_hot_w3, dim3((unsigned)h.n), dim3(kBlock), 0, s, (const int64_t *)g.back.off,
                        (const int32_t *)g.back.col, (const float *)g.back.w, (const int32_t *)h.rows, n_ks, h.w3);
     check_hip(hipGetLastError(), "dense hot weights launch");
-    h.dense_kc = kc;
-    h.dense_chunks = (int32_t)n_chunks;
     h.dense_ks = n_ks;
 }
 
 void launch_hot_dense(const Graph &g, const uint16_t *q, int64_t q_stride, const TileCtl *ctl, int nt, float *part,
                       int64_t part_stride, hipStream_t s) {
     const HotSet &h = g.hot;
-    DenseArgs a{q, q_stride, ctl, h.w3, h.dense_ks, h.dense_kc, g.n_u, h.n, h.dense_chunks, nt, part, part_stride};
-    hipLaunchKernelGGL(kb_hot_dense, dim3((unsigned)(h.dense_chunks * nt)), dim3(kDenseThreads), 0, s, a);
+    int64_t kc, n_chunks;
+    dense_chunking(g.n_u, nt, &kc, &n_chunks);
+    DenseArgs a{q, q_stride, ctl, h.w3, h.dense_ks, kc, g.n_u, h.n, (int)n_chunks, nt, part, part_stride};
+    hipLaunchKernelGGL(kb_hot_dense, dim3((unsigned)(n_chunks * nt)), dim3(kDenseThreads), 0, s, a);
 }
 
 }  // namespace ahpp
