@@ -161,12 +161,12 @@ struct BatchState {
 // results do not depend on the tiles in flight.
 constexpr int kHotMax = 128;             // at most this many hot rows (four 32-row MFMA blocks)
 constexpr int64_t kHotMinLen = 1024;     // a hot row has at least one full item of entries
-// Workgroups of one launch of the dense hot pass (chunks of U x tiles in
-// flight): two per CU whatever the tile count.  Fewer, longer chunks also
-// cut the partials its reduction reads (m1 with 4 tiles, pass and reduction
-// per round: 0.80 ms at 512 chunks per tile, 0.73 at 256, 0.70 at 128, 0.99
-// at 64).
-constexpr int64_t kDenseWorkgroups = 512;
+// U chunks of the dense hot pass, a fixed property of the graph so that the
+// order of its sums (chunk partials added in chunk order) never depends on
+// the tiles in flight.  Longer chunks also cut the partials its reduction
+// reads (m1, 4-tile batch, pass and reduction per round: 0.80 ms at 512
+// chunks, 0.73 at 256, 0.70 at 128, 0.99 at 64).
+constexpr int kDenseChunks = 128;
 struct HotSet {
     int32_t n = 0;                       // hot rows (0: none, the batch gathers every row)
     int32_t *rows = nullptr;             // [n] back row of hot index h (longest first)
@@ -332,10 +332,10 @@ bool lambda_cache_read(const std::string &dir, const KeyInput &in, const uint64_
 bool lambda_cache_write(const std::string &dir, const KeyInput &in, const uint64_t key[2], double lambda);
 
 // hot_dense.hip: the hot rows as a dense MFMA product; the chunking of U
-// for nt tiles in flight (kc rows per chunk), its weights' bytes, their build
-// at load, and the launch of a batched round (partials
-// [n_chunks][n_hot][kTileQ] per tile, added by the hot reduction).
-void dense_chunking(int64_t n_u, int nt, int64_t *kc, int64_t *n_chunks);
+// (kc rows per chunk), its weights' bytes, their build at load, and the
+// launch of a batched round (partials [n_chunks][n_hot][kTileQ] per tile,
+// added by the hot reduction).
+void dense_chunking(int64_t n_u, int64_t *kc, int64_t *n_chunks);
 size_t hot_dense_bytes(const Graph &g);
 void build_hot_dense(Graph &g, hipStream_t s);
 void launch_hot_dense(const Graph &g, const uint16_t *q, int64_t q_stride, const TileCtl *ctl, int nt, float *part,

@@ -966,24 +966,17 @@ void free_batch_state(BatchState &b) {
     b = BatchState{};
 }
 
-// Chunks of the hot-row partials (the dense pass's U chunks) with nt tiles
-// in flight, and the partial slots per tile a state of `tiles` tiles needs
-// for any nt up to it (nt x chunks stays near kDenseWorkgroups).
-int64_t hot_chunks(const Graph &g, int nt) {
+// Chunks of the hot-row partials (the dense pass's U chunks).
+int64_t hot_chunks(const Graph &g) {
     int64_t kc, n_chunks;
-    dense_chunking(g.n_u, nt, &kc, &n_chunks);
+    dense_chunking(g.n_u, &kc, &n_chunks);
     return n_chunks;
-}
-int64_t hot_slots_per_tile(const Graph &g, int tiles) {
-    int64_t worst = 0;
-    for (int nt = 1; nt <= tiles; ++nt) worst = std::max(worst, nt * hot_chunks(g, nt));
-    return (worst + tiles - 1) / tiles;
 }
 
 int64_t batch_tile_bytes(const Graph &g, bool with_out) {
     const int64_t items = std::max<int64_t>(std::max(g.fwd.n_items, g.back.n_items), 1);
     const int64_t Q = kTileQ;
-    const int64_t hot = (int64_t)hot_chunks(g, 1) * g.hot.n;  // the most a tile can need
+    const int64_t hot = (int64_t)hot_chunks(g) * g.hot.n;
     // Per (node, query): r, pi (4 + 4 B) and q (2 B) for U; carry (4 B) and zh (2 B) for V and attributes.
     return Q * (10 * g.n_u + 6 * std::max<int64_t>(g.n_v + g.n_a, 1) + 4 * (items + hot + (with_out ? g.n_u : 0))) +
            (int64_t)sizeof(TileCtl) + (int64_t)batch_cap(g) * Q * (2 * 4 + 5 * 8) + (int64_t)g.grid_cap * Q * 8 +
@@ -1008,8 +1001,7 @@ void ensure_batch_state(Graph &g, BatchState &b, int tiles, bool with_out) {
     b.red_max = (float *)dev_alloc(g, T * kCtlSlices * Q * 4, "batch control slices");
     b.red_np = (unsigned long long *)dev_alloc(g, T * kCtlSlices * Q * 8, "batch control slices");
     if (g.hot.n > 0)
-        b.hot_part = (float *)dev_alloc(g, T * (size_t)hot_slots_per_tile(g, tiles) * g.hot.n * Q * 4,
-                                        "batch hot-row partials");
+        b.hot_part = (float *)dev_alloc(g, T * (size_t)hot_chunks(g) * g.hot.n * Q * 4, "batch hot-row partials");
     if (with_out) b.out = (float *)dev_alloc(g, T * Q * g.n_u * 4, "batch scores");
     b.sums = (double *)dev_alloc(g, T * g.grid_cap * Q * 8, "batch sums");
     b.tiles = tiles;
@@ -1076,7 +1068,7 @@ void batch_round(Graph &g, BatchState &b, int nt, hipStream_t s) {
     const double fwd_bytes = fwd_csr + q * (2.0 * g.fwd.nnz + fwd_row);
     const double fwd_comp = fwd_csr + q * (2.0 * n_x + fwd_row);
     int64_t hot_kc = 0, n_ch = 0;
-    if (hs.n > 0) dense_chunking(g.n_u, nt, &hot_kc, &n_ch);
+    if (hs.n > 0) dense_chunking(g.n_u, &hot_kc, &n_ch);
     const double hot_bytes = 6.0 * (double)(hot_kc * n_ch) * kHotMax + 12.0 * hs.n +
                              q * (2.0 * g.n_u + 8.0 * (double)n_ch * hs.n + 10.0 * hs.n);
     if (p.back)

@@ -211,23 +211,21 @@ __global__ void __launch_bounds__(kDenseThreads) kb_hot_dense(DenseArgs a) {
 
 }  // namespace
 
-namespace {
-// K-steps of the weight block: U padded to whole stages plus kStageU rows
-// per possible chunk, so that every chunking below stays inside it (a
-// chunking into at most kDenseWorkgroups chunks pads U by under kStageU rows
-// per chunk); the padding holds zero weights.
-int64_t dense_block_ks(int64_t n_u) {
-    return ((n_u + kStageU - 1) / kStageU + kDenseWorkgroups) * kStageU / kKS;
-}
-}  // namespace
-
-void dense_chunking(int64_t n_u, int nt, int64_t *kc, int64_t *n_chunks) {
-    const int64_t want = std::max<int64_t>(1, (kDenseWorkgroups + nt - 1) / std::max(nt, 1));
-    int64_t c = (n_u + want - 1) / want;
+void dense_chunking(int64_t n_u, int64_t *kc, int64_t *n_chunks) {
+    int64_t c = (n_u + kDenseChunks - 1) / kDenseChunks;
     c = (c + kStageU - 1) / kStageU * kStageU;
     *kc = std::max<int64_t>(c, kStageU);
     *n_chunks = std::max<int64_t>(1, (n_u + *kc - 1) / *kc);
 }
+
+namespace {
+// K-steps of the weight block: U padded to whole chunks (zero weights).
+int64_t dense_block_ks(int64_t n_u) {
+    int64_t kc, n_chunks;
+    dense_chunking(n_u, &kc, &n_chunks);
+    return n_chunks * kc / kKS;
+}
+}  // namespace
 
 size_t hot_dense_bytes(const Graph &g) {
     return (size_t)3 * (size_t)dense_block_ks(g.n_u) * kHBlocks * kFragElems * 2;
@@ -250,7 +248,7 @@ void launch_hot_dense(const Graph &g, const uint16_t *q, int64_t q_stride, const
                       int64_t part_stride, hipStream_t s) {
     const HotSet &h = g.hot;
     int64_t kc, n_chunks;
-    dense_chunking(g.n_u, nt, &kc, &n_chunks);
+    dense_chunking(g.n_u, &kc, &n_chunks);
     DenseArgs a{q, q_stride, ctl, h.w3, h.dense_ks, kc, g.n_u, h.n, (int)n_chunks, nt, part, part_stride};
     hipLaunchKernelGGL(kb_hot_dense, dim3((unsigned)(n_chunks * nt)), dim3(kDenseThreads), 0, s, a);
 }

@@ -314,13 +314,16 @@ def test_captured_rounds_match_plain_launches(torch_cuda, ahpp, tiny, tiny_graph
         assert torch.isfinite(x).all()
 
 
-def test_tuned_schedule_changes_speed_only(torch_cuda, ahpp):
+def test_tuned_schedule_changes_speed_only(torch_cuda, ahpp, monkeypatch):
     """The autotuner picks a schedule among its candidates; batch results are
-    bitwise the same before and after (every sum has a fixed order)."""
+    bitwise the same before and after, and with 1 or 4 tiles in flight (every
+    sum has a fixed order, the hot rows' chunk partials included: this graph
+    has 8 rows of over 1,024 entries, and its U spans several 32-node stages
+    per chunk)."""
     import torch
     g = synth.make_custom(6000, 3000, 60000, 300, 6, seed=818, unit_weights=False)
     dg = ahpp.load_graph(g)
-    srcs = np.concatenate([synth.mixed_batch_queries(g, 500, 51), synth.degree_queries(g, 100, 52)])
+    srcs = np.concatenate([synth.mixed_batch_queries(g, 800, 51), synth.degree_queries(g, 100, 52)])
     eps = np.where(np.arange(srcs.size) % 2 == 0, 1e-6, 1e-7)
     before = ahpp.ahpp_query_batch(dg, srcs, eps, k=25)
     info = ahpp.ahpp_graph_tune(dg, max_tiles=4)
@@ -331,4 +334,10 @@ def test_tuned_schedule_changes_speed_only(torch_cuda, ahpp):
     assert torch.equal(before.pi, after.pi)
     assert torch.equal(before.topk_idx, after.topk_idx)
     assert [s["iters"] for s in before.stats] == [s["iters"] for s in after.stats]
+    for tiles in ("1", "4"):
+        monkeypatch.setenv("AHPP_BATCH_TILES", tiles)
+        _say("same batch,", tiles, "tiles in flight")
+        res = ahpp.ahpp_query_batch(dg, srcs, eps, k=25)
+        assert torch.equal(before.pi, res.pi), tiles
+        assert torch.equal(before.topk_idx, res.topk_idx), tiles
     dg.free()
