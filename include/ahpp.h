@@ -95,7 +95,11 @@ typedef struct {
     uint64_t key[2];            /* ahpp_graph_key of the inputs, computed on the device at load */
     int32_t lambda_cached;      /* 0 no cache dir, 1 lambda read from the cache, 2 computed and stored,
                                    -1 computed, storing failed */
-    int32_t reserved;
+    int32_t hot_rows;           /* V/attribute rows the batched queries sum as a dense product on the
+                                   matrix cores: the longest rows of at least 1,024 entries, at most
+                                   128 (AHPP_HOT_ROWS=<n> in the environment at load lowers that cap,
+                                   0 turns them off); 0 if none, or if their weight block (6 bytes per
+                                   row and U node) would exceed a quarter of the device's memory */
 } ahpp_graph_info_t;
 
 /* Per-query statistics.  n_push counts edge visits as Algorithm 4 counts n_p

@@ -52,7 +52,7 @@ class GraphInfo(ctypes.Structure):
                 ("beta", ctypes.c_double), ("lam", ctypes.c_double), ("lambda_iters", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("dangling_u", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("load_ms", ctypes.c_double), ("lambda_ms", ctypes.c_double), ("key", ctypes.c_uint64 * 2),
-                ("lambda_cached", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lambda_cached", ctypes.c_int32), ("hot_rows", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -546,7 +546,7 @@ ahpp_status_t ahpp_graph_info(const ahpp_graph_t *h, ahpp_graph_info_t *info) {
     info->key[0] = g.key[0];
     info->key[1] = g.key[1];
     info->lambda_cached = g.lambda_cached;
-    info->reserved = 0;
+    info->hot_rows = g.hot.n;
     return AHPP_OK;
 }
 

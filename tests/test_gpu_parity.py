@@ -261,6 +261,7 @@ def test_batch_weighted_ragged_tiles(torch_cuda, ahpp, monkeypatch):
     og = O.OracleGraph.from_graph(g)
     _say("load weighted 5000-node graph for batches")
     dg = ahpp.load_graph(g)
+    assert dg.info["hot_rows"] == 8
     srcs = np.concatenate([synth.mixed_batch_queries(g, 400, 31), synth.degree_queries(g, 200, 32)])
     eps = np.where(np.arange(srcs.size) % 3 == 0, 1e-7, np.where(np.arange(srcs.size) % 3 == 1, 1e-5, 1e-6))
     _say("batch of", srcs.size)
@@ -287,6 +288,54 @@ def test_batch_weighted_ragged_tiles(torch_cuda, ahpp, monkeypatch):
     assert np.array_equal(res1.topk_idx.cpu().numpy(), res.topk_idx.cpu().numpy())
     assert [s["iters"] for s in res1.stats] == [s["iters"] for s in res.stats]
     dg.free()
+
+
+def _hot_small_graph(n_u, seed):
+    """V node 0 and attribute 0 link every U node ceil(1024 / n_u) + 1 times
+    (repeated pairs, R12), so both rows pass 1,024 entries and become hot
+    rows; other edges and attributes are random, weights in [0.5, 1) and
+    (0, 1]."""
+    import types
+    rng = np.random.default_rng(seed)
+    n_v, n_a = 12, 6
+    rep = -(-1024 // n_u) + 1
+    allu = np.repeat(np.arange(n_u), rep)
+    m, ma = 6 * n_u, 3 * n_u
+    edge_u = np.concatenate([allu, rng.integers(0, n_u, m)]).astype(np.int32)
+    edge_v = np.concatenate([np.zeros(allu.size), rng.integers(1, n_v, m)]).astype(np.int32)
+    assoc_u = np.concatenate([allu, rng.integers(0, n_u, ma)]).astype(np.int32)
+    assoc_a = np.concatenate([np.zeros(allu.size), rng.integers(1, n_a, ma)]).astype(np.int32)
+    return types.SimpleNamespace(
+        n_u=n_u, n_v=n_v, n_attr=n_a, edge_u=edge_u, edge_v=edge_v,
+        edge_w=rng.uniform(0.5, 1.0, edge_u.size).astype(np.float32),
+        assoc_u=assoc_u, assoc_a=assoc_a, assoc_w=(1.0 - rng.random(assoc_u.size)).astype(np.float32))
+
+
+@pytest.mark.parametrize("n_u", [20, 33, 70])
+def test_hot_rows_over_small_u(torch_cuda, ahpp, monkeypatch, n_u):
+    """Hot rows over a U smaller than one 32-node stage of the dense pass, one
+    node past it, and a few stages with a ragged end (the pass masks the U
+    rows past n_U and the weight block is zero past them).  Every source's
+    batched answer meets Theorem 2 against the oracle's exact series, and so
+    does the same graph loaded without hot rows (AHPP_HOT_ROWS=0)."""
+    g = _hot_small_graph(n_u, 900 + n_u)
+    og = O.OracleGraph.from_graph(g)
+    srcs = np.arange(n_u, dtype=np.int64)
+    exact = [og.power_series(int(s))[0] for s in srcs]
+    for hot, want in (("128", 2), ("0", 0)):
+        monkeypatch.setenv("AHPP_HOT_ROWS", hot)
+        dg = ahpp.load_graph(g)
+        assert dg.info["hot_rows"] == want, dg.info
+        _say("small-U batch", n_u, "hot rows", want)
+        res = ahpp.ahpp_query_batch(dg, srcs, 1e-7, k=10)
+        pis = res.pi.cpu().numpy()
+        for q, s in enumerate(srcs.tolist()):
+            chk = O.check_query(exact[q], pis[q].astype(np.float64), 1e-7, tol=TOL, k=10, source=s,
+                                topk_ids=res.topk_idx[q, : int(res.topk_n[q].item())].cpu().numpy())
+            assert chk.ok, (n_u, hot, s, chk.detail)
+            assert res.stats[q]["converged"] == 1
+        dg.free()
+    og.close()
 
 
 def test_captured_rounds_match_plain_launches(torch_cuda, ahpp, tiny, tiny_graph, monkeypatch):
@@ -323,6 +372,7 @@ def test_tuned_schedule_changes_speed_only(torch_cuda, ahpp, monkeypatch):
     import torch
     g = synth.make_custom(6000, 3000, 60000, 300, 6, seed=818, unit_weights=False)
     dg = ahpp.load_graph(g)
+    assert dg.info["hot_rows"] == 8
     srcs = np.concatenate([synth.mixed_batch_queries(g, 800, 51), synth.degree_queries(g, 100, 52)])
     eps = np.where(np.arange(srcs.size) % 2 == 0, 1e-6, 1e-7)
     before = ahpp.ahpp_query_batch(dg, srcs, eps, k=25)
