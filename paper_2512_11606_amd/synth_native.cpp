@@ -129,9 +129,16 @@ int64_t sn_draw_edges(int64_t n_u, int64_t n_v, int64_t m_e, const double *cdf_u
             if (keep[i]) add.push_back(c[i].key);
         std::vector<Cand>().swap(c);
         std::vector<uint8_t>().swap(keep);
-        std::vector<uint64_t> merged(keys.size() + add.size());
-        __gnu_parallel::merge(keys.begin(), keys.end(), add.begin(), add.end(), merged.begin());
-        keys.swap(merged);
+        // The parallel merge dereferences the first element of each input, so
+        // an empty side (the first round's keys, a round with no fresh pair)
+        // is handled here.
+        if (keys.empty()) {
+            keys.swap(add);
+        } else if (!add.empty()) {
+            std::vector<uint64_t> merged(keys.size() + add.size());
+            __gnu_parallel::merge(keys.begin(), keys.end(), add.begin(), add.end(), merged.begin());
+            keys.swap(merged);
+        }
         need = m_e - (int64_t)keys.size();
         if (++rounds > 500) return -1;
     }
