@@ -213,6 +213,7 @@ ahpp_status_t ahpp_query_schedule(ahpp_graph_t *g, int32_t source, double eps, i
  *   k, topk_idx (device int32[n_q*k]), topk_val (device float[n_q*k]),
  *   topk_n (device int32[n_q]): as in ahpp_query, row q for query q.
  *   stats: host ahpp_stats_t[n_q] or NULL.
+ * n_q = 0 does nothing and returns OK (n_q < 0: INVALID_ARG).
  * Returns NOT_CONVERGED if any query hit max_iters. Blocks until done. */
 ahpp_status_t ahpp_query_batch(ahpp_graph_t *g, int32_t n_q, const int32_t *sources, const double *eps,
                                int32_t max_iters, float *pi_out,

@@ -227,6 +227,48 @@ def test_edge_cases(torch_cuda, ahpp):
     dg2.free()
 
 
+def test_batch_edge_cases(torch_cuda, ahpp):
+    """The batched engine on the same degenerate graphs: dangling U nodes, an
+    attribute-only node, a graph with no V side; a query whose eps is at
+    least lambda stops before any push inside a batch of running ones; an
+    empty batch is a no-op."""
+    import types
+    e = np.array([(0, 0), (1, 0), (1, 1), (2, 1)], dtype=np.int32)
+    a = np.array([(0, 0), (1, 0), (3, 1), (2, 1)], dtype=np.int32)
+    g = types.SimpleNamespace(n_u=5, n_v=2, n_attr=2, edge_u=e[:, 0], edge_v=e[:, 1],
+                              edge_w=np.array([1, 2, 0.5, 1], np.float32), assoc_u=a[:, 0], assoc_a=a[:, 1],
+                              assoc_w=np.array([1, 1, 3, 0.25], np.float32))
+    dg = ahpp.load_graph(g)
+    Pi = O.exact_dense(g)
+    _say("edge-case graph, batched")
+    srcs = np.array([0, 1, 2, 3, 4, 0], dtype=np.int64)
+    eps = np.array([1e-7] * 5 + [10.0 * dg.lam])
+    res = ahpp.ahpp_query_batch(dg, srcs, eps, k=3)
+    pis = res.pi.cpu().numpy().astype(np.float64)
+    for q in range(5):
+        s = int(srcs[q])
+        chk = O.check_query(Pi[s], pis[q], 1e-7, tol=TOL, k=3, source=s,
+                            topk_ids=res.topk_idx[q, : int(res.topk_n[q].item())].cpu().numpy())
+        assert chk.ok, (s, chk.detail)
+    assert float(np.abs(pis[5]).max()) == 0.0 and int(res.topk_n[5].item()) == 0
+    assert res.stats[5]["iters"] == 0 and res.stats[5]["converged"] == 1
+    empty = ahpp.ahpp_query_batch(dg, np.zeros(0, dtype=np.int64), 1e-7, k=3)
+    assert empty.pi.shape == (0, 5) and empty.stats == []
+    dg.free()
+    g2 = types.SimpleNamespace(n_u=4, n_v=0, n_attr=2, edge_u=np.zeros(0, np.int32), edge_v=np.zeros(0, np.int32),
+                               edge_w=None, assoc_u=np.array([0, 1, 2, 3, 0], np.int32),
+                               assoc_a=np.array([0, 0, 1, 1, 1], np.int32), assoc_w=None)
+    dg2 = ahpp.load_graph(g2, beta=1.0)
+    Pi2 = O.exact_dense(g2, beta=1.0)
+    _say("attribute-only graph, batched")
+    res = ahpp.ahpp_query_batch(dg2, np.arange(4), 1e-7)
+    pis = res.pi.cpu().numpy().astype(np.float64)
+    for s in range(4):
+        chk = O.check_query(Pi2[s], pis[s], 1e-7, tol=TOL)
+        assert chk.ok, (s, chk.detail)
+    dg2.free()
+
+
 def test_errors(torch_cuda, ahpp, tiny, tiny_graph):
     with pytest.raises(ahpp.AhppError) as e:
         ahpp.ahpp_query(tiny, tiny.n_u, 1e-6)
