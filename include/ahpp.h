@@ -27,6 +27,17 @@
  *   - No C++ exception crosses this boundary.  Every call returns a status;
  *     on failure ahpp_last_error() describes it (per calling thread).
  *   - A graph handle may be used by one thread at a time.
+ *
+ * Environment (read at each use; results are bitwise the same under every
+ * setting but AHPP_HOT_ROWS, which changes the order of some sums and so
+ * the rounding, never the guarantee)
+ *   AHPP_BATCH_TILES=<n>  tiles of 256 queries the batched engine runs side
+ *                         by side (n > 0), over the tuned or default count.
+ *   AHPP_GRAPHS=1         batched and single-query rounds replayed from
+ *                         captured HIP graphs instead of plain launches.
+ *   AHPP_HOT_ROWS=<n>     at load: at most n hot rows (0..128, 0 = none);
+ *                         see ahpp_graph_info_t.hot_rows.
+ *   AHPP_LOAD_TRACE=1     at load: the time of each build phase on stderr.
  */
 #ifndef AHPP_H
 #define AHPP_H
