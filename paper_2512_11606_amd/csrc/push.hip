@@ -379,11 +379,31 @@ __global__ void __launch_bounds__(kControlThreads) k_control(Control *ctl, Parti
     if (ctl->done) return;
     float m = 0.0f;
     unsigned long long np = 0;
-    for (int i = threadIdx.x; i < p.n_max_a; i += kControlThreads) m = fmaxf(m, p.max_a[i]);
-    for (int i = threadIdx.x; i < p.n_max_b; i += kControlThreads) m = fmaxf(m, p.max_b[i]);
+    // A thread's loads of all six arrays issue before any is used (one
+    // round trip to L2, where the gathers just left the partials, instead of
+    // one per array); max and integer sums give the same bits in any order.
+    int n_all = max(p.n_max_a, p.n_max_b);
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-        for (int i = threadIdx.x; i < p.n_np[k]; i += kControlThreads) np += p.np[k][i];
+    for (int k = 0; k < 4; ++k) n_all = max(n_all, p.n_np[k]);
+    constexpr int kU = 8;
+    for (int i0 = threadIdx.x; i0 < n_all; i0 += kControlThreads * kU) {
+        float va[kU], vb[kU];
+        unsigned long long vn[4][kU];
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+            const int i = i0 + j * kControlThreads;
+            va[j] = i < p.n_max_a ? p.max_a[i] : 0.0f;
+            vb[j] = i < p.n_max_b ? p.max_b[i] : 0.0f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) vn[k][j] = i < p.n_np[k] ? p.np[k][i] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+            m = fmaxf(m, fmaxf(va[j], vb[j]));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) np += vn[k][j];
+        }
+    }
     m = block_max_n<kControlThreads / kWave>(m, ldsf);
     np = block_sum_u64_n<kControlThreads / kWave>(np, lds);
     if (threadIdx.x != 0) return;
